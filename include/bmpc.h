@@ -1,0 +1,201 @@
+/*
+ * bmpc.h -- C ABI of the MI355X (gfx950) direct solver for root-coupled branch-MPC
+ * systems: the two-level (scenario x horizon) parallel Cholesky factorization and
+ * triangular solves of "Accelerating Branch MPC with Two-Level Parallel Direct Solves
+ * on GPUs" (Algorithms 1 and 2), plus mixed-precision iterative refinement.
+ *
+ * The system (Section III-B, eq. (root_coupled_matrix), eq. (tail_block_tridiagonal)):
+ *
+ *        [ K_1               C_1^T ]        K_s = block-tridiagonal, N blocks n x n:
+ *    K = [      ...           ...  ]              D_{s,k} on the diagonal,
+ *        [           K_S     C_S^T ]              E_{s,k} at block (k+1, k),
+ *        [ C_1  ...  C_S     R     ]              E_{s,k}^T at block (k, k+1);
+ *                                          C_s couples the root to stage 0 of tail s.
+ *
+ * Notation: S scenarios (the paper's M), N stages, block size n (the paper's n_b,
+ * Assumption 1), nrhs right-hand sides.  Stages are 0-based: stage k is the paper's
+ * stage k+1, so the root-coupled stage (the paper's x_1) is stage 0.
+ *
+ * Layouts (all row-major n x n blocks, FP64, DEVICE pointers unless stated):
+ *   D  [S][N][n][n]     only the lower triangle of each block is read
+ *   E  [S][N-1][n][n]   E[s][k] is block (k+1, k) of tail s (may be NULL when N == 1)
+ *   C  [S][n][n]        block (root, stage 0)
+ *   R  [n][n]           only the lower triangle is read
+ *   b, x [nrhs][(S*N+1)*n]  each right-hand side in the paper's partition
+ *                       (r^1_1..r^1_N, ..., r^S_1..r^S_N, r_0): tails in forward stage
+ *                       order, the root block last.
+ * The library never keeps a caller pointer after a call returns.
+ *
+ * Streams and ordering.  Every device operation is enqueued on the plan's stream
+ * (hipStream_t passed as void*; NULL = the legacy default stream) and is
+ * asynchronous unless stated.  The library allocates device memory only in
+ * bmpc_analyze; factor/solve/refine allocate nothing and launch no memset, so the
+ * sequence can be captured into a HIP graph.  Calls on one plan must not overlap.
+ *
+ * Errors.  Argument and state errors are reported synchronously by the return value.
+ * Numerical breakdown (a non-positive pivot) is recorded on the device and read by
+ * bmpc_get_info.
+ */
+#ifndef BMPC_H
+#define BMPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BMPC_OK = 0,
+  BMPC_ERR_INVALID = -1,       /* bad argument (dims, NULL pointer, unsupported n) */
+  BMPC_ERR_NOT_SPD = -2,       /* returned by bmpc_get_info when info != 0 */
+  BMPC_ERR_ALLOC = -3,         /* device allocation failed in bmpc_analyze */
+  BMPC_ERR_DEVICE = -4,        /* a HIP call failed */
+  BMPC_ERR_STATE = -5,         /* solve/refine before a factor on this plan */
+  BMPC_ERR_NOT_CONVERGED = -6  /* bmpc_get_stats: refinement hit max_iters */
+} bmpc_status;
+
+typedef enum {
+  BMPC_FP64 = 0,        /* factor, solve and reductions in FP64 */
+  BMPC_FP32_REFINE = 1  /* tail factor + solves in FP32 (FP32 accumulation); root
+                           reduction, root Cholesky and refinement residual in FP64 */
+} bmpc_precision;
+
+typedef struct {
+  int32_t S;    /* scenarios, >= 1 */
+  int32_t N;    /* stages per tail, >= 1 */
+  int32_t n;    /* block size, 1..32 */
+  int32_t nrhs; /* right-hand sides per solve, 1..8 */
+} bmpc_dims;
+
+typedef struct {
+  int32_t window_depth; /* 0 = automatic; else levels eliminated per factor pass
+                           (1..6), bounded by the shared-memory budget */
+  int32_t reserved[7];
+} bmpc_options;
+
+typedef struct {
+  double factor_flops;    /* exact flop count of Algorithm 1 (method's count) */
+  double solve_flops;     /* exact flop count of Algorithm 2 for all nrhs */
+  double factor_bytes;    /* algorithmic HBM bytes: read K (lower triangles of
+                             D, R), write the factor */
+  double solve_bytes;     /* algorithmic HBM bytes: read the factor twice, read b,
+                             write x */
+  double residual_bytes;  /* algorithmic bytes of one FP64 residual b - K x */
+  int32_t levels;         /* elimination levels of one tail, x_1 included */
+  int32_t passes;         /* factor passes (kernel launches over the chains) */
+  int32_t window_depth;   /* levels per factor pass actually used */
+  int32_t reserved;
+  double workspace_bytes; /* device memory owned by the plan */
+} bmpc_cost;
+
+typedef struct bmpc_plan_s* bmpc_plan;
+
+/* One-time analysis (the paper's analysis phase, Section V: fixed sparsity allows
+ * persistent workspaces).  Validates dims, builds the ordering Pi_i
+ * (Section IV-A: reverse the tail, apply Gamma_{N-1} to (x_N..x_2), keep x_1 last),
+ * the level table and the factor structure, and allocates every workspace.  Reads
+ * no caller array.  BMPC_ERR_INVALID for bad dims (n > 32 is unsupported),
+ * BMPC_ERR_ALLOC when device memory runs out, BMPC_ERR_DEVICE if no GPU.
+ * On success *out owns its workspaces until bmpc_destroy. */
+bmpc_status bmpc_analyze(const bmpc_dims* dims, bmpc_precision prec, void* stream,
+                         bmpc_plan* out);
+bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* stream,
+                            const bmpc_options* opts, bmpc_plan* out);
+
+/* Replace the stream later calls enqueue on (e.g. a graph-capture stream). */
+bmpc_status bmpc_set_stream(bmpc_plan plan, void* stream);
+
+/* Algorithm 1: L_i = chol(Pi_i K_i Pi_i^T) for every tail (horizon-parallel block
+ * elimination in the Gamma order), F_{i,1} = C_{i,1} L_{i,1}^{-T},
+ * U_i = F_{i,1} F_{i,1}^T, R~ = R - sum_i U_i (FP64, fixed summation order) and
+ * L_R = chol(R~) (FP64).  Device pointers D, E, C, R as described above; the factor
+ * stays in the plan.  Asynchronous; a non-positive pivot is recorded for
+ * bmpc_get_info and leaves the factor unspecified. */
+bmpc_status bmpc_factor(bmpc_plan plan, const double* D, const double* E,
+                        const double* C, const double* R);
+
+/* Algorithm 2: x = K^{-1} b with the factor of the last bmpc_factor: tail forward
+ * substitution, root reduction r~_0 = r_0 - sum F_{i,1} dy_1^i and root solves in
+ * FP64, root propagation, tail backward substitution, inverse permutation.
+ * b and x are device arrays [nrhs][(S*N+1)*n]; x may alias b.  In a
+ * BMPC_FP32_REFINE plan this is the plain FP32 solve (no refinement).
+ * BMPC_ERR_STATE if no factor has been issued. */
+bmpc_status bmpc_solve(bmpc_plan plan, const double* b, double* x);
+
+/* Mixed-precision iterative refinement (not in the paper; classical scheme, Moler
+ * 1967): x = solve(b); then repeat r = b - K x in FP64 from the caller's FP64
+ * blocks, d = solve(r / |r|_inf) * |r|_inf, x += d, until |d|_inf <= tol * |x|_inf
+ * for every right-hand side or max_iters corrections were applied.  Needs the
+ * factor of the same D, E, C, R.  x on entry is ignored.  The stop test runs on the
+ * device (later launches of a converged loop return at once), so the launch
+ * sequence is fixed and capturable.  max_iters in 0..100. */
+bmpc_status bmpc_refine(bmpc_plan plan, const double* D, const double* E,
+                        const double* C, const double* R, const double* b, double* x,
+                        double tol, int32_t max_iters);
+
+/* Synchronizes the plan's stream.  *info = 0 after a successful factor; otherwise
+ * the 1-based natural row index (tails first, root last, as in b) of the first
+ * non-positive pivot in the elimination order Pi, and the call returns
+ * BMPC_ERR_NOT_SPD. */
+bmpc_status bmpc_get_info(bmpc_plan plan, int64_t* info);
+
+/* Synchronizes.  Corrections applied by the last bmpc_refine and the final
+ * max_q |d_q|_inf / |x_q|_inf.  Returns BMPC_ERR_NOT_CONVERGED if the stop test
+ * was not met within max_iters. */
+bmpc_status bmpc_get_stats(bmpc_plan plan, int32_t* iters, double* rel_correction);
+
+/* Host copies of the analysis.  perm: int32[N], the 0-based stage at each permuted
+ * position of a tail (the same for every tail; x_1 = stage 0 is last). */
+bmpc_status bmpc_query_perm(bmpc_plan plan, int32_t* perm);
+bmpc_status bmpc_query_cost(bmpc_plan plan, bmpc_cost* cost);
+
+/* Algorithmic HBM bytes and flops of one bmpc_factor call attributed to kernel class
+ * cls (see bmpc_kernel_class_name): for the factor passes, the D blocks read and
+ * the factor blocks written by the positions the pass eliminates (the first pass
+ * also reads every E block).  Zero for classes without a model. */
+bmpc_status bmpc_query_kernel_cost(bmpc_plan plan, int32_t cls, double* bytes,
+                                   double* flops);
+
+/* Copy the factor of tail s to host memory (synchronizes): L [N*n][N*n] row-major
+ * in permuted order (lower block structure of L_i; the DIAGONAL blocks are given as
+ * their inverses L_jj^{-1}, which is what the plan stores), F [n][n] = F_{s,1}.
+ * Values are widened to FP64.  For tests of small systems. */
+bmpc_status bmpc_export_tail_factor(bmpc_plan plan, int32_t s, double* L, double* F);
+/* Copy L_R [n][n] (FP64, lower) to host memory (synchronizes). */
+bmpc_status bmpc_export_root_factor(bmpc_plan plan, double* LR);
+
+/* Per-kernel timing with HIP events on the plan's stream.  While enabled, every
+ * launch is bracketed by events; bmpc_get_kernel_times synchronizes and returns, for
+ * each kernel class, the number of launches and their summed milliseconds since the
+ * last reset.  Class ids: see bmpc_kernel_class_name. */
+bmpc_status bmpc_set_profiling(bmpc_plan plan, int32_t enable);
+bmpc_status bmpc_get_kernel_times(bmpc_plan plan, int32_t max_classes, int64_t* launches,
+                                  double* total_ms);
+bmpc_status bmpc_reset_kernel_times(bmpc_plan plan);
+const char* bmpc_kernel_class_name(int32_t cls);
+int32_t bmpc_kernel_class_count(void);
+
+bmpc_status bmpc_destroy(bmpc_plan plan);
+const char* bmpc_status_string(bmpc_status st);
+
+/* ---- host-only helpers (no device needed) ---------------------------------- */
+
+/* Pi_i for N stages (same content as bmpc_query_perm). */
+bmpc_status bmpc_ordering(int32_t N, int32_t* perm);
+
+/* Block structure of one tail's factor plus the root row, under Pi_i: every
+ * (row, col) pair of nonzero blocks with row >= col, positions 0..N-1 for the tail
+ * in permuted order and N for the root, sorted by (row, col).  Writes at most cap
+ * pairs and sets *count to the full number (call with cap = 0 to size). */
+bmpc_status bmpc_structure(int32_t N, int32_t* rows, int32_t* cols, int64_t cap,
+                           int64_t* count);
+
+/* Cost model of a plan without creating one. */
+bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
+                            const bmpc_options* opts, bmpc_cost* cost);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BMPC_H */

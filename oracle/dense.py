@@ -37,17 +37,23 @@ def assemble_K(D, E, C, R) -> np.ndarray:
     return K
 
 
-def perm_matrix(S: int, N: int, n: int, kind: str = "d") -> np.ndarray:
-    """Scalar permutation matrix P with (P K P^T) the block-permuted matrix: row i of
-    P selects the i-th scalar variable of the permuted order."""
+def perm_index(S: int, N: int, n: int, kind: str = "d") -> np.ndarray:
+    """Scalar index vector p of Pi: the i-th variable of the permuted order is natural
+    variable p[i], so (Pi K Pi^T) = K[p][:, p]."""
     order = symbolic.ordering(N, kind)
-    tot = (S * N + 1) * n
     idx = []
     for s in range(S):
         for k in order:
             base = (s * N + k) * n
             idx.extend(range(base, base + n))
-    idx.extend(range(S * N * n, tot))
-    P = np.zeros((tot, tot))
-    P[np.arange(tot), np.array(idx)] = 1.0
+    idx.extend(range(S * N * n, (S * N + 1) * n))
+    return np.array(idx)
+
+
+def perm_matrix(S: int, N: int, n: int, kind: str = "d") -> np.ndarray:
+    """Scalar permutation matrix P with (P K P^T) the block-permuted matrix: row i of
+    P selects the i-th scalar variable of the permuted order."""
+    idx = perm_index(S, N, n, kind)
+    P = np.zeros((idx.size, idx.size))
+    P[np.arange(idx.size), idx] = 1.0
     return P

@@ -1,0 +1,319 @@
+"""Thin Python binding of the bmpc C ABI (include/bmpc.h).
+
+Argument marshalling only: torch tensors provide device memory and the current HIP
+stream; every step of the factorization and solves runs in the HIP kernels of
+``libbmpc.so``.  There is no CPU fallback: a missing library or GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbmpc.so")
+
+OK, ERR_INVALID, ERR_NOT_SPD, ERR_ALLOC, ERR_DEVICE, ERR_STATE, ERR_NOT_CONVERGED = \
+    0, -1, -2, -3, -4, -5, -6
+FP64, FP32_REFINE = 0, 1
+
+EXPORTED = [
+    "bmpc_analyze", "bmpc_analyze_ex", "bmpc_set_stream", "bmpc_factor", "bmpc_solve",
+    "bmpc_refine", "bmpc_get_info", "bmpc_get_stats", "bmpc_query_perm",
+    "bmpc_query_cost", "bmpc_query_kernel_cost", "bmpc_export_tail_factor",
+    "bmpc_export_root_factor", "bmpc_set_profiling", "bmpc_get_kernel_times",
+    "bmpc_reset_kernel_times", "bmpc_kernel_class_name", "bmpc_kernel_class_count",
+    "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
+    "bmpc_cost_model",
+]
+
+
+class BmpcError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class _Dims(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("N", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("nrhs", ctypes.c_int32)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("window_depth", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class _Cost(ctypes.Structure):
+    _fields_ = [("factor_flops", ctypes.c_double), ("solve_flops", ctypes.c_double),
+                ("factor_bytes", ctypes.c_double), ("solve_bytes", ctypes.c_double),
+                ("residual_bytes", ctypes.c_double), ("levels", ctypes.c_int32),
+                ("passes", ctypes.c_int32), ("window_depth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_double)]
+
+
+@dataclass
+class Cost:
+    factor_flops: float
+    solve_flops: float
+    factor_bytes: float
+    solve_bytes: float
+    residual_bytes: float
+    levels: int
+    passes: int
+    window_depth: int
+    workspace_bytes: float
+
+
+_lib = None
+
+
+def lib():
+    """Load libbmpc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"bmpc HIP library not built: {LIB_PATH} "
+                           "(run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "bmpc_analyze": [P(_Dims), i32, vp, P(vp)],
+        "bmpc_analyze_ex": [P(_Dims), i32, vp, P(_Options), P(vp)],
+        "bmpc_set_stream": [vp, vp],
+        "bmpc_factor": [vp, vp, vp, vp, vp],
+        "bmpc_solve": [vp, vp, vp],
+        "bmpc_refine": [vp, vp, vp, vp, vp, vp, vp, dbl, i32],
+        "bmpc_get_info": [vp, P(i64)],
+        "bmpc_get_stats": [vp, P(i32), P(dbl)],
+        "bmpc_query_perm": [vp, P(i32)],
+        "bmpc_query_cost": [vp, P(_Cost)],
+        "bmpc_query_kernel_cost": [vp, i32, P(dbl), P(dbl)],
+        "bmpc_export_tail_factor": [vp, i32, P(dbl), P(dbl)],
+        "bmpc_export_root_factor": [vp, P(dbl)],
+        "bmpc_set_profiling": [vp, i32],
+        "bmpc_get_kernel_times": [vp, i32, P(i64), P(dbl)],
+        "bmpc_reset_kernel_times": [vp],
+        "bmpc_destroy": [vp],
+        "bmpc_ordering": [i32, P(i32)],
+        "bmpc_structure": [i32, P(i32), P(i32), i64, P(i64)],
+        "bmpc_cost_model": [P(_Dims), i32, P(_Options), P(_Cost)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.bmpc_status_string.argtypes = [ctypes.c_int]
+    L.bmpc_status_string.restype = ctypes.c_char_p
+    L.bmpc_kernel_class_name.argtypes = [i32]
+    L.bmpc_kernel_class_name.restype = ctypes.c_char_p
+    L.bmpc_kernel_class_count.argtypes = []
+    L.bmpc_kernel_class_count.restype = i32
+    _lib = L
+    return L
+
+
+def status_string(st: int) -> str:
+    return lib().bmpc_status_string(int(st)).decode()
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise BmpcError(st, what)
+
+
+def _prec(precision) -> int:
+    if precision in (FP64, "fp64", "f64"):
+        return FP64
+    if precision in (FP32_REFINE, "fp32", "fp32_refine", "f32"):
+        return FP32_REFINE
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def _cost(c: _Cost) -> Cost:
+    return Cost(c.factor_flops, c.solve_flops, c.factor_bytes, c.solve_bytes,
+                c.residual_bytes, c.levels, c.passes, c.window_depth, c.workspace_bytes)
+
+
+# ---- host-only helpers -------------------------------------------------------------
+
+def ordering(N: int) -> list:
+    buf = (ctypes.c_int32 * N)()
+    _check(lib().bmpc_ordering(N, buf), "bmpc_ordering")
+    return list(buf)
+
+
+def structure(N: int) -> list:
+    cnt = ctypes.c_int64(0)
+    _check(lib().bmpc_structure(N, None, None, 0, ctypes.byref(cnt)), "bmpc_structure")
+    k = cnt.value
+    rows, cols = (ctypes.c_int32 * k)(), (ctypes.c_int32 * k)()
+    _check(lib().bmpc_structure(N, rows, cols, k, ctypes.byref(cnt)), "bmpc_structure")
+    return list(zip(rows, cols))
+
+
+def cost_model(S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
+               window_depth: int = 0) -> Cost:
+    d = _Dims(S, N, n, nrhs)
+    o = _Options(window_depth)
+    c = _Cost()
+    _check(lib().bmpc_cost_model(ctypes.byref(d), _prec(precision), ctypes.byref(o),
+                                 ctypes.byref(c)), "bmpc_cost_model")
+    return _cost(c)
+
+
+def kernel_class_names() -> list:
+    L = lib()
+    return [L.bmpc_kernel_class_name(i).decode() for i in range(L.bmpc_kernel_class_count())]
+
+
+# ---- device plan -----------------------------------------------------------------
+
+def _ptr(t, what, dtype=None, numel=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A bmpc plan: analysis + persistent device workspaces for one (S, N, n, nrhs)."""
+
+    def __init__(self, S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
+                 window_depth: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("bmpc needs a HIP device (torch.cuda.is_available() is False)")
+        self.S, self.N, self.n, self.nrhs = int(S), int(N), int(n), int(nrhs)
+        self.precision = _prec(precision)
+        self._h = ctypes.c_void_p()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        d = _Dims(self.S, self.N, self.n, self.nrhs)
+        o = _Options(int(window_depth))
+        _check(lib().bmpc_analyze_ex(ctypes.byref(d), self.precision,
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
+                                     ctypes.byref(self._h)), "bmpc_analyze")
+
+    @property
+    def length(self) -> int:
+        return (self.S * self.N + 1) * self.n
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().bmpc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._stream = stream
+        _check(lib().bmpc_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)),
+               "bmpc_set_stream")
+
+    def _blocks(self, D, E, C, R):
+        import torch
+        S, N, n = self.S, self.N, self.n
+        f64 = torch.float64
+        return (_ptr(D, "D", f64, S * N * n * n),
+                _ptr(E, "E", f64, S * (N - 1) * n * n) if N > 1 else None,
+                _ptr(C, "C", f64, S * n * n), _ptr(R, "R", f64, n * n))
+
+    def factor(self, D, E, C, R):
+        _check(lib().bmpc_factor(self._h, *self._blocks(D, E, C, R)), "bmpc_factor")
+
+    def _rhs(self, b, x):
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        return (_ptr(b, "b", torch.float64, self.nrhs * self.length),
+                _ptr(x, "x", torch.float64, self.nrhs * self.length), x)
+
+    def solve(self, b, x=None):
+        pb, px, x = self._rhs(b, x)
+        _check(lib().bmpc_solve(self._h, pb, px), "bmpc_solve")
+        return x
+
+    def refine(self, D, E, C, R, b, x=None, tol: float = 1e-12, max_iters: int = 10):
+        blocks = self._blocks(D, E, C, R)
+        pb, px, x = self._rhs(b, x)
+        _check(lib().bmpc_refine(self._h, *blocks, pb, px, float(tol), int(max_iters)),
+               "bmpc_refine")
+        return x
+
+    def info(self) -> int:
+        v = ctypes.c_int64(0)
+        st = lib().bmpc_get_info(self._h, ctypes.byref(v))
+        if st not in (OK, ERR_NOT_SPD):
+            _check(st, "bmpc_get_info")
+        return int(v.value)
+
+    def stats(self):
+        it, rel = ctypes.c_int32(0), ctypes.c_double(0.0)
+        st = lib().bmpc_get_stats(self._h, ctypes.byref(it), ctypes.byref(rel))
+        if st not in (OK, ERR_NOT_CONVERGED):
+            _check(st, "bmpc_get_stats")
+        return int(it.value), float(rel.value), st == OK
+
+    def perm(self) -> list:
+        buf = (ctypes.c_int32 * self.N)()
+        _check(lib().bmpc_query_perm(self._h, buf), "bmpc_query_perm")
+        return list(buf)
+
+    def cost(self) -> Cost:
+        c = _Cost()
+        _check(lib().bmpc_query_cost(self._h, ctypes.byref(c)), "bmpc_query_cost")
+        return _cost(c)
+
+    def kernel_cost(self, cls: int):
+        b, f = ctypes.c_double(0), ctypes.c_double(0)
+        _check(lib().bmpc_query_kernel_cost(self._h, int(cls), ctypes.byref(b),
+                                            ctypes.byref(f)), "bmpc_query_kernel_cost")
+        return float(b.value), float(f.value)
+
+    def export_tail_factor(self, s: int):
+        import numpy as np
+        Nn = self.N * self.n
+        L = np.zeros((Nn, Nn))
+        F = np.zeros((self.n, self.n))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().bmpc_export_tail_factor(self._h, int(s), L.ctypes.data_as(dp),
+                                             F.ctypes.data_as(dp)), "bmpc_export_tail_factor")
+        return L, F
+
+    def export_root_factor(self):
+        import numpy as np
+        LR = np.zeros((self.n, self.n))
+        _check(lib().bmpc_export_root_factor(
+            self._h, LR.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+            "bmpc_export_root_factor")
+        return LR
+
+    def set_profiling(self, enable: bool):
+        _check(lib().bmpc_set_profiling(self._h, int(bool(enable))), "bmpc_set_profiling")
+
+    def reset_kernel_times(self):
+        _check(lib().bmpc_reset_kernel_times(self._h), "bmpc_reset_kernel_times")
+
+    def kernel_times(self) -> dict:
+        L = lib()
+        k = L.bmpc_kernel_class_count()
+        launches = (ctypes.c_int64 * k)()
+        ms = (ctypes.c_double * k)()
+        _check(L.bmpc_get_kernel_times(self._h, k, launches, ms), "bmpc_get_kernel_times")
+        names = kernel_class_names()
+        return {names[i]: (int(launches[i]), float(ms[i])) for i in range(k)}

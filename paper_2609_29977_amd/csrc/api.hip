@@ -1,0 +1,725 @@
+// C ABI of the bmpc library: analysis, plan-owned workspaces and the launch
+// sequences of Algorithm 1 (factor), Algorithm 2 (solve) and mixed-precision
+// iterative refinement.  Host code; kernels live in factor.hip, solve.hip and
+// refine.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/bmpc.h"
+#include "bmpc_internal.h"
+
+namespace bmpc {
+size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw);
+}
+
+using namespace bmpc;
+
+namespace {
+
+constexpr int kLdsBudget = 160 * 1024;
+
+struct PassPlan {
+  int mk, shift, windows, is_final;
+  double flops, bytes;  // algorithmic flops / HBM bytes of the pass
+};
+
+struct Timing {
+  int cls;
+  hipEvent_t a, b;
+};
+
+int nmax_for(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 32); }
+
+double potrf_flops(double n) { return n * n * n / 3.0 + n * n / 2.0 + n / 6.0; }
+double trsm_flops(double n) { return n * n * n; }
+double syrk_flops(double n) { return n * n * n + n * n; }
+double gemm_flops(double n) { return 2.0 * n * n * n; }
+
+int default_window_depth(bool fp64, int nmax) {
+  if (fp64) return nmax <= 8 ? 6 : (nmax <= 16 ? 5 : 3);
+  return nmax <= 8 ? 6 : (nmax <= 16 ? 6 : 4);
+}
+
+int ctz_host(unsigned v) { return __builtin_ctz(v); }
+
+// Permuted position of every chain position (Gamma_{N-1} on the reversed tail,
+// Section IV-A): level-major, positions in increasing order inside a level; X last.
+std::vector<int> make_permpos(int N) {
+  const int m = N - 1;
+  std::vector<int> pp(N, 0);
+  int pos = 0;
+  for (int l = 1; l <= chain_levels(m); ++l)
+    for (int j = 1 << (l - 1); j <= m; j += 1 << l) pp[j - 1] = pos++;
+  pp[N - 1] = pos;  // X = stage 0, last
+  return pp;
+}
+
+std::vector<int> make_perm(int N) {
+  std::vector<int> pp = make_permpos(N), perm(N);
+  for (int j = 1; j <= N; ++j) perm[pp[j - 1]] = N - j;  // position j holds stage N-j
+  return perm;
+}
+
+struct Costs {
+  std::vector<PassPlan> passes;
+  double factor_flops = 0, solve_flops = 0, factor_bytes = 0, solve_bytes = 0,
+         residual_bytes = 0, L_bytes = 0;
+  double pass_flops[KC_COUNT] = {0}, pass_bytes[KC_COUNT] = {0};
+  int levels = 0, Tw = 0;
+};
+
+Costs make_costs(const bmpc_dims& d, bool fp64, int Tw) {
+  Costs c;
+  c.Tw = Tw;
+  const int S = d.S, N = d.N, n = d.n, m = N - 1;
+  const double tb = fp64 ? 8.0 : 4.0;
+  const double nn = (double)n * n, tri = (double)n * (n + 1) / 2.0;
+  const double len = ((double)S * N + 1) * n;
+  int mk = m, shift = 0;
+  double nG = 0;  // off-diagonal factor blocks per tail
+  for (;;) {
+    PassPlan p{};
+    p.is_final = mk < (1 << Tw);
+    p.windows = p.is_final ? 1 : (mk >> Tw) + 1;
+    p.mk = mk;
+    p.shift = shift;
+    double fl = 0, by = 0;
+    for (int q = 1; q <= mk; ++q) {
+      const int v = ctz_host((unsigned)q);
+      if (!p.is_final && v >= Tw) continue;  // a window boundary, eliminated later
+      const int hl = (q != (1 << v)) ? 1 : 0;
+      fl += potrf_flops(n) + (1 + hl) * (trsm_flops(n) + syrk_flops(n)) + hl * gemm_flops(n);
+      by += 8.0 * tri + tb * (tri + (1 + hl) * nn);  // read D, write L_jj^{-1}, G's
+      nG += 1 + hl;
+    }
+    if (shift == 0) by += 8.0 * nn * m;  // every E block is read by the first pass
+    if (p.is_final) {
+      // x_1 step: read D_0 and C, write L_X^{-1} and F; U = F F^T
+      fl += potrf_flops(n) + trsm_flops(n) + syrk_flops(n);
+      by += 8.0 * tri + 8.0 * nn + tb * (tri + nn);
+    }
+    p.flops = fl * S;
+    p.bytes = by * S;
+    c.passes.push_back(p);
+    if (p.is_final) break;
+    mk >>= Tw;
+    shift += Tw;
+  }
+  for (size_t i = 0; i < c.passes.size(); ++i) {
+    const PassPlan& p = c.passes[i];
+    const int cls = p.is_final ? KC_FACTOR_FINAL : (i == 0 ? KC_FACTOR_FIRST : KC_FACTOR_MID);
+    c.pass_flops[cls] += p.flops;
+    c.pass_bytes[cls] += p.bytes;
+    c.factor_flops += p.flops;
+  }
+  c.factor_flops += (double)S * nn + potrf_flops(n);  // root reduction + root Cholesky
+  c.pass_flops[KC_ROOT_POTRF] = potrf_flops(n) + (double)S * nn;
+  const double K_bytes = 8.0 * ((double)S * N * tri + (double)S * m * nn + (double)S * nn + tri);
+  c.L_bytes = tb * ((double)S * N * tri + (double)S * nG * nn + (double)S * nn) + 8.0 * tri;
+  c.factor_bytes = K_bytes + c.L_bytes;
+  c.pass_bytes[KC_ROOT_REDUCE] = 8.0 * S * nn;
+  c.pass_bytes[KC_ROOT_POTRF] = 8.0 * (tri + tri);
+  const double rhs_bytes = 8.0 * len * d.nrhs;
+  c.solve_bytes = 2.0 * c.L_bytes + 2.0 * rhs_bytes;
+  c.residual_bytes = K_bytes + 3.0 * rhs_bytes;
+  c.solve_flops = d.nrhs * ((double)S * (2.0 * N * nn + 4.0 * nG * nn + 4.0 * nn) +
+                            (double)S * n + 2.0 * nn);
+  c.levels = chain_levels(m) + 1;
+  return c;
+}
+
+}  // namespace
+
+struct bmpc_plan_s {
+  bmpc_dims d{};
+  bmpc_precision prec = BMPC_FP64;
+  bool fp64 = true;
+  int m = 0, nmax = 8, Tw = 1, groups = 1;
+  hipStream_t stream = nullptr;
+  Costs costs;
+  std::vector<int> perm, permpos;
+  int stride = 1;
+  // device buffers
+  void* Linv = nullptr;
+  void* Gl = nullptr;
+  void* Gr = nullptr;
+  void* F = nullptr;
+  double* U = nullptr;
+  double* Upart = nullptr;
+  double* LR = nullptr;
+  void* acc[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  void* accX = nullptr;
+  int* d_permpos = nullptr;
+  unsigned long long* d_info = nullptr;
+  void* y = nullptr;
+  double* w = nullptr;
+  double* x0 = nullptr;
+  double* rbuf = nullptr;
+  double* norms = nullptr;  // rnorm, dnorm, xnorm: 3 * nrhs
+  int* flags = nullptr;     // done, iterations
+  double* relcorr = nullptr;
+  std::vector<void*> allocs;
+  double workspace_bytes = 0;
+  bool factored = false;
+  int last_max_iters = 0;
+  // profiling
+  bool profiling = false;
+  std::vector<Timing> timings;
+  std::vector<hipEvent_t> event_pool;
+  int64_t launches[KC_COUNT] = {0};
+  double total_ms[KC_COUNT] = {0};
+};
+
+namespace {
+
+hipEvent_t take_event(bmpc_plan p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Bracket a launch with events when profiling is on.
+template <typename F>
+void timed(bmpc_plan p, int cls, F&& launch) {
+  if (!p->profiling) {
+    launch();
+    return;
+  }
+  Timing t{cls, take_event(p), take_event(p)};
+  (void)hipEventRecord(t.a, p->stream);
+  launch();
+  (void)hipEventRecord(t.b, p->stream);
+  p->timings.push_back(t);
+}
+
+void collect_timings(bmpc_plan p) {
+  if (p->timings.empty()) return;
+  (void)hipEventSynchronize(p->timings.back().b);
+  for (const Timing& t : p->timings) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      p->launches[t.cls] += 1;
+      p->total_ms[t.cls] += ms;
+    }
+    p->event_pool.push_back(t.a);
+    p->event_pool.push_back(t.b);
+  }
+  p->timings.clear();
+}
+
+bool dims_ok(const bmpc_dims* d) {
+  return d && d->S >= 1 && d->N >= 1 && d->n >= 1 && d->n <= 32 && d->nrhs >= 1 &&
+         d->nrhs <= kMaxRhs && (double)d->S * d->N * d->n < 2.0e9;
+}
+
+void free_plan_memory(bmpc_plan p) {
+  for (void* a : p->allocs) (void)hipFree(a);
+  p->allocs.clear();
+  for (const Timing& t : p->timings) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  p->timings.clear();
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+  p->event_pool.clear();
+}
+
+bool dalloc(bmpc_plan p, void** ptr, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    *ptr = nullptr;
+    return false;
+  }
+  p->allocs.push_back(*ptr);
+  p->workspace_bytes += (double)bytes;
+  return true;
+}
+
+int pick_window_depth(bool fp64, int nmax, const bmpc_options* o) {
+  int Tw = (o && o->window_depth > 0) ? o->window_depth : default_window_depth(fp64, nmax);
+  Tw = std::min(Tw, kMaxWindowDepth);
+  while (Tw > 1 && factor_pass_lds_bytes(fp64, nmax, Tw) > (size_t)kLdsBudget) --Tw;
+  return Tw;
+}
+
+template <typename T>
+void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double* C,
+                    const double* R) {
+  const bmpc_dims& d = p->d;
+  hipStream_t st = p->stream;
+  timed(p, KC_FACTOR_INIT, [&] { launch_factor_init(p->d_info, st); });
+  const int npass = (int)p->costs.passes.size();
+  for (int k = 0; k < npass; ++k) {
+    const PassPlan& pp = p->costs.passes[k];
+    FactorPassArgs a{};
+    a.S = d.S;
+    a.N = d.N;
+    a.n = d.n;
+    a.m = p->m;
+    a.Tw = p->Tw;
+    a.pass = k;
+    a.npass = npass;
+    a.mk = pp.mk;
+    a.shift = pp.shift;
+    a.windows = pp.windows;
+    a.is_final = pp.is_final;
+    a.D = D;
+    a.E = E;
+    a.C = C;
+    const int in = (k + 1) & 1, out = k & 1;
+    a.accR_in = k > 0 ? p->acc[in][0] : nullptr;
+    a.accL_in = k > 0 ? p->acc[in][1] : nullptr;
+    a.fill_in = k > 0 ? p->acc[in][2] : nullptr;
+    a.accR_out = p->acc[out][0];
+    a.accL_out = p->acc[out][1];
+    a.fill_out = p->acc[out][2];
+    a.stride = p->stride;
+    a.accX = p->accX;
+    a.Linv = p->Linv;
+    a.Gl = p->Gl;
+    a.Gr = p->Gr;
+    a.F = p->F;
+    a.U = p->U;
+    a.permpos = p->d_permpos;
+    a.info = p->d_info;
+    const int cls = pp.is_final ? KC_FACTOR_FINAL : (k == 0 ? KC_FACTOR_FIRST : KC_FACTOR_MID);
+    timed(p, cls, [&] { launch_factor_pass<T>(a, p->nmax, st); });
+  }
+  timed(p, KC_ROOT_REDUCE,
+        [&] { launch_root_reduce(p->U, p->Upart, d.S, d.n, p->groups, st); });
+  const int64_t root_row = (int64_t)d.S * d.N * d.n;
+  timed(p, KC_ROOT_POTRF, [&] {
+    launch_root_potrf(R, p->Upart, p->groups, d.n, p->LR, root_row, p->d_info, st);
+  });
+}
+
+SolveArgs solve_args(bmpc_plan p, const double* b, double* x) {
+  SolveArgs a{};
+  a.S = p->d.S;
+  a.N = p->d.N;
+  a.n = p->d.n;
+  a.m = p->m;
+  a.nrhs = p->d.nrhs;
+  a.Linv = p->Linv;
+  a.Gl = p->Gl;
+  a.Gr = p->Gr;
+  a.F = p->F;
+  a.LR = p->LR;
+  a.b = b;
+  a.x = x;
+  a.y = p->y;
+  a.w = p->w;
+  a.x0 = p->x0;
+  return a;
+}
+
+template <typename T>
+void enqueue_solve(bmpc_plan p, const SolveArgs& a) {
+  hipStream_t st = p->stream;
+  const int L = chain_levels(p->m);
+  for (int l = 1; l <= L; ++l)
+    timed(p, KC_SOLVE_FWD, [&] { launch_solve_fwd_level<T>(a, l, p->nmax, st); });
+  timed(p, KC_SOLVE_X_FWD, [&] { launch_solve_x_fwd<T>(a, p->nmax, st); });
+  timed(p, KC_SOLVE_ROOT, [&] { launch_solve_root(a, st); });
+  timed(p, KC_SOLVE_X_BWD, [&] { launch_solve_x_bwd<T>(a, p->nmax, st); });
+  for (int l = L; l >= 1; --l)
+    timed(p, KC_SOLVE_BWD, [&] { launch_solve_bwd_level<T>(a, l, p->nmax, st); });
+}
+
+bmpc_status last_error_status() {
+  return hipGetLastError() == hipSuccess ? BMPC_OK : BMPC_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bmpc_status_string(bmpc_status st) {
+  switch (st) {
+    case BMPC_OK: return "ok";
+    case BMPC_ERR_INVALID: return "invalid argument";
+    case BMPC_ERR_NOT_SPD: return "matrix not positive definite";
+    case BMPC_ERR_ALLOC: return "device allocation failed";
+    case BMPC_ERR_DEVICE: return "HIP runtime error";
+    case BMPC_ERR_STATE: return "solve before factor";
+    case BMPC_ERR_NOT_CONVERGED: return "refinement did not converge";
+  }
+  return "unknown status";
+}
+
+bmpc_status bmpc_ordering(int32_t N, int32_t* perm) {
+  if (N < 1 || !perm) return BMPC_ERR_INVALID;
+  std::vector<int> pr = make_perm(N);
+  for (int i = 0; i < N; ++i) perm[i] = pr[i];
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_structure(int32_t N, int32_t* rows, int32_t* cols, int64_t cap,
+                           int64_t* count) {
+  if (N < 1 || !count || cap < 0 || (cap > 0 && (!rows || !cols))) return BMPC_ERR_INVALID;
+  const int m = N - 1;
+  std::vector<int> pp = make_permpos(N);
+  std::vector<std::pair<int, int>> b;
+  for (int j = 1; j <= N; ++j) b.push_back({pp[j - 1], pp[j - 1]});
+  for (int j = 1; j <= m; ++j) {
+    const int v = ctz_host((unsigned)j);
+    const int jl = j - (1 << v), jr = j + (1 << v);
+    if (jl >= 1) b.push_back({pp[jl - 1], pp[j - 1]});
+    b.push_back({jr <= m ? pp[jr - 1] : pp[N - 1], pp[j - 1]});
+  }
+  b.push_back({N, pp[N - 1]});  // F: the root row holds the terminal block only
+  b.push_back({N, N});          // L_R
+  std::sort(b.begin(), b.end());
+  *count = (int64_t)b.size();
+  for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)b.size()); ++i) {
+    rows[i] = b[i].first;
+    cols[i] = b[i].second;
+  }
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
+                            const bmpc_options* opts, bmpc_cost* cost) {
+  if (!dims_ok(dims) || !cost || (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
+    return BMPC_ERR_INVALID;
+  const bool fp64 = prec == BMPC_FP64;
+  const int Tw = pick_window_depth(fp64, nmax_for(dims->n), opts);
+  Costs c = make_costs(*dims, fp64, Tw);
+  std::memset(cost, 0, sizeof(*cost));
+  cost->factor_flops = c.factor_flops;
+  cost->solve_flops = c.solve_flops;
+  cost->factor_bytes = c.factor_bytes;
+  cost->solve_bytes = c.solve_bytes;
+  cost->residual_bytes = c.residual_bytes;
+  cost->levels = c.levels;
+  cost->passes = (int32_t)c.passes.size();
+  cost->window_depth = Tw;
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* stream,
+                            const bmpc_options* opts, bmpc_plan* out) {
+  if (!out) return BMPC_ERR_INVALID;
+  *out = nullptr;
+  if (!dims_ok(dims) || (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
+    return BMPC_ERR_INVALID;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BMPC_ERR_DEVICE;
+  bmpc_plan p = new (std::nothrow) bmpc_plan_s();
+  if (!p) return BMPC_ERR_ALLOC;
+  p->d = *dims;
+  p->prec = prec;
+  p->fp64 = prec == BMPC_FP64;
+  p->m = dims->N - 1;
+  p->nmax = nmax_for(dims->n);
+  p->Tw = pick_window_depth(p->fp64, p->nmax, opts);
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  p->costs = make_costs(*dims, p->fp64, p->Tw);
+  p->perm = make_perm(dims->N);
+  p->permpos = make_permpos(dims->N);
+  p->groups = std::min(dims->S, 64);
+  const int S = dims->S, N = dims->N, n = dims->n, nrhs = dims->nrhs;
+  const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
+  const size_t len = ((size_t)S * N + 1) * n;
+  const int npass = (int)p->costs.passes.size();
+  p->stride = (npass > 1 ? p->costs.passes[0].windows : 1) + 1;
+  const size_t gblocks = (size_t)(N > 1 ? N - 1 : 1);
+  bool ok = dalloc(p, &p->Linv, (size_t)S * N * nn * tb) &&
+            dalloc(p, &p->Gl, (size_t)S * gblocks * nn * tb) &&
+            dalloc(p, &p->Gr, (size_t)S * gblocks * nn * tb) &&
+            dalloc(p, &p->F, (size_t)S * nn * tb) &&
+            dalloc(p, (void**)&p->U, (size_t)S * nn * 8) &&
+            dalloc(p, (void**)&p->Upart, (size_t)p->groups * nn * 8) &&
+            dalloc(p, (void**)&p->LR, nn * 8) &&
+            dalloc(p, &p->accX, (size_t)S * npass * nn * tb) &&
+            dalloc(p, (void**)&p->d_permpos, (size_t)N * sizeof(int)) &&
+            dalloc(p, (void**)&p->d_info, sizeof(unsigned long long)) &&
+            dalloc(p, &p->y, (size_t)S * N * nrhs * n * tb) &&
+            dalloc(p, (void**)&p->w, (size_t)S * nrhs * n * 8) &&
+            dalloc(p, (void**)&p->x0, (size_t)nrhs * n * 8) &&
+            dalloc(p, (void**)&p->rbuf, (size_t)nrhs * len * 8) &&
+            dalloc(p, (void**)&p->norms, (size_t)3 * nrhs * 8) &&
+            dalloc(p, (void**)&p->flags, 2 * sizeof(int)) &&
+            dalloc(p, (void**)&p->relcorr, sizeof(double));
+  if (ok && npass > 1) {
+    for (int set = 0; set < 2 && ok; ++set)
+      for (int b = 0; b < 3 && ok; ++b)
+        ok = dalloc(p, &p->acc[set][b], (size_t)S * p->stride * nn * tb);
+  }
+  if (!ok) {
+    free_plan_memory(p);
+    delete p;
+    return BMPC_ERR_ALLOC;
+  }
+  if (hipMemcpy(p->d_permpos, p->permpos.data(), (size_t)N * sizeof(int),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    free_plan_memory(p);
+    delete p;
+    return BMPC_ERR_DEVICE;
+  }
+  *out = p;
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_analyze(const bmpc_dims* dims, bmpc_precision prec, void* stream,
+                         bmpc_plan* out) {
+  return bmpc_analyze_ex(dims, prec, stream, nullptr, out);
+}
+
+bmpc_status bmpc_set_stream(bmpc_plan plan, void* stream) {
+  if (!plan) return BMPC_ERR_INVALID;
+  plan->stream = reinterpret_cast<hipStream_t>(stream);
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_factor(bmpc_plan p, const double* D, const double* E, const double* C,
+                        const double* R) {
+  if (!p || !D || !C || !R || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
+  if (p->fp64)
+    enqueue_factor<double>(p, D, E, C, R);
+  else
+    enqueue_factor<float>(p, D, E, C, R);
+  const bmpc_status st = last_error_status();
+  if (st == BMPC_OK) p->factored = true;
+  return st;
+}
+
+bmpc_status bmpc_solve(bmpc_plan p, const double* b, double* x) {
+  if (!p || !b || !x) return BMPC_ERR_INVALID;
+  if (!p->factored) return BMPC_ERR_STATE;
+  SolveArgs a = solve_args(p, b, x);
+  if (p->fp64)
+    enqueue_solve<double>(p, a);
+  else
+    enqueue_solve<float>(p, a);
+  return last_error_status();
+}
+
+bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const double* C,
+                        const double* R, const double* b, double* x, double tol,
+                        int32_t max_iters) {
+  if (!p || !D || !C || !R || !b || !x || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
+  if (max_iters < 0 || max_iters > 100 || !(tol >= 0.0) || x == b) return BMPC_ERR_INVALID;
+  if (!p->factored) return BMPC_ERR_STATE;
+  hipStream_t st = p->stream;
+  const int nrhs = p->d.nrhs;
+  double* rnorm = p->norms;
+  double* dnorm = p->norms + nrhs;
+  double* xnorm = p->norms + 2 * nrhs;
+  timed(p, KC_REFINE_MISC, [&] { launch_refine_reset(p->norms, 3 * nrhs, p->flags, 1, st); });
+  SolveArgs a = solve_args(p, b, x);
+  if (p->fp64)
+    enqueue_solve<double>(p, a);
+  else
+    enqueue_solve<float>(p, a);
+  ResidualArgs ra{};
+  ra.S = p->d.S;
+  ra.N = p->d.N;
+  ra.n = p->d.n;
+  ra.nrhs = nrhs;
+  ra.D = D;
+  ra.E = E;
+  ra.C = C;
+  ra.R = R;
+  ra.b = b;
+  ra.x = x;
+  ra.r = p->rbuf;
+  ra.w = p->w;
+  ra.rnorm = rnorm;
+  ra.done = p->flags;
+  SolveArgs c = solve_args(p, p->rbuf, x);
+  c.rnorm = rnorm;
+  c.dnorm = dnorm;
+  c.xnorm = xnorm;
+  c.done = p->flags;
+  c.accumulate = 1;
+  for (int it = 0; it < max_iters; ++it) {
+    timed(p, KC_REFINE_MISC,
+          [&] { launch_refine_reset(p->norms, 3 * nrhs, p->flags, 0, st); });
+    timed(p, KC_RESIDUAL, [&] { launch_residual(ra, p->nmax, st); });
+    timed(p, KC_RESIDUAL_ROOT, [&] { launch_residual_root(ra, st); });
+    if (p->fp64)
+      enqueue_solve<double>(p, c);
+    else
+      enqueue_solve<float>(p, c);
+    timed(p, KC_REFINE_MISC, [&] {
+      launch_refine_check(dnorm, xnorm, nrhs, tol, p->flags, p->relcorr, st);
+    });
+  }
+  p->last_max_iters = max_iters;
+  return last_error_status();
+}
+
+bmpc_status bmpc_get_info(bmpc_plan p, int64_t* info) {
+  if (!p || !info) return BMPC_ERR_INVALID;
+  unsigned long long v = 0;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
+  if (hipMemcpy(&v, p->d_info, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+    return BMPC_ERR_DEVICE;
+  if (v == ~0ull || !p->factored) {
+    *info = 0;
+    return BMPC_OK;
+  }
+  const int64_t Nn = (int64_t)p->d.N * p->d.n, n = p->d.n;
+  const int64_t p0 = (int64_t)v - 1;
+  if (p0 < (int64_t)p->d.S * Nn) {
+    const int64_t s = p0 / Nn, rem = p0 % Nn, pos = rem / n, i = rem % n;
+    *info = s * Nn + (int64_t)p->perm[pos] * n + i + 1;
+  } else {
+    *info = (int64_t)v;
+  }
+  return BMPC_ERR_NOT_SPD;
+}
+
+bmpc_status bmpc_get_stats(bmpc_plan p, int32_t* iters, double* rel_correction) {
+  if (!p) return BMPC_ERR_INVALID;
+  int flags[2] = {0, 0};
+  double rel = 0.0;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
+  if (hipMemcpy(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&rel, p->relcorr, sizeof(rel), hipMemcpyDeviceToHost) != hipSuccess)
+    return BMPC_ERR_DEVICE;
+  if (iters) *iters = flags[1];
+  if (rel_correction) *rel_correction = rel;
+  if (p->last_max_iters > 0 && !flags[0]) return BMPC_ERR_NOT_CONVERGED;
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_query_perm(bmpc_plan p, int32_t* perm) {
+  if (!p || !perm) return BMPC_ERR_INVALID;
+  for (int i = 0; i < p->d.N; ++i) perm[i] = p->perm[i];
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_query_cost(bmpc_plan p, bmpc_cost* cost) {
+  if (!p || !cost) return BMPC_ERR_INVALID;
+  std::memset(cost, 0, sizeof(*cost));
+  cost->factor_flops = p->costs.factor_flops;
+  cost->solve_flops = p->costs.solve_flops;
+  cost->factor_bytes = p->costs.factor_bytes;
+  cost->solve_bytes = p->costs.solve_bytes;
+  cost->residual_bytes = p->costs.residual_bytes;
+  cost->levels = p->costs.levels;
+  cost->passes = (int32_t)p->costs.passes.size();
+  cost->window_depth = p->Tw;
+  cost->workspace_bytes = p->workspace_bytes;
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_query_kernel_cost(bmpc_plan p, int32_t cls, double* bytes, double* flops) {
+  if (!p || cls < 0 || cls >= KC_COUNT) return BMPC_ERR_INVALID;
+  if (bytes) *bytes = p->costs.pass_bytes[cls];
+  if (flops) *flops = p->costs.pass_flops[cls];
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_export_tail_factor(bmpc_plan p, int32_t s, double* L, double* F) {
+  if (!p || !L || !F || s < 0 || s >= p->d.S) return BMPC_ERR_INVALID;
+  if (!p->factored) return BMPC_ERR_STATE;
+  const int N = p->d.N, n = p->d.n, m = p->m;
+  const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
+  const size_t gblocks = (size_t)(N > 1 ? N - 1 : 1);
+  std::vector<unsigned char> li(N * nn * tb), gl(gblocks * nn * tb), gr(gblocks * nn * tb),
+      f(nn * tb);
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
+  auto cp = [&](void* dst, const void* src, size_t off, size_t bytes) {
+    return hipMemcpy(dst, (const unsigned char*)src + off, bytes, hipMemcpyDeviceToHost) ==
+           hipSuccess;
+  };
+  if (!cp(li.data(), p->Linv, (size_t)s * N * nn * tb, li.size()) ||
+      !cp(gl.data(), p->Gl, (size_t)s * gblocks * nn * tb, gl.size()) ||
+      !cp(gr.data(), p->Gr, (size_t)s * gblocks * nn * tb, gr.size()) ||
+      !cp(f.data(), p->F, (size_t)s * nn * tb, f.size()))
+    return BMPC_ERR_DEVICE;
+  auto val = [&](const std::vector<unsigned char>& buf, size_t idx) -> double {
+    if (p->fp64) return reinterpret_cast<const double*>(buf.data())[idx];
+    return (double)reinterpret_cast<const float*>(buf.data())[idx];
+  };
+  const size_t Nn = (size_t)N * n;
+  std::memset(L, 0, sizeof(double) * Nn * Nn);
+  auto put = [&](int rowpos, int colpos, const std::vector<unsigned char>& buf, size_t blk) {
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c)
+        L[((size_t)rowpos * n + r) * Nn + (size_t)colpos * n + c] = val(buf, blk * nn + r * n + c);
+  };
+  const std::vector<int>& pp = p->permpos;
+  for (int j = 1; j <= N; ++j) put(pp[j - 1], pp[j - 1], li, j - 1);
+  for (int j = 1; j <= m; ++j) {
+    const int v = ctz_host((unsigned)j);
+    const int jl = j - (1 << v), jr = j + (1 << v);
+    if (jl >= 1) put(pp[jl - 1], pp[j - 1], gl, j - 1);
+    put(jr <= m ? pp[jr - 1] : pp[N - 1], pp[j - 1], gr, j - 1);
+  }
+  for (size_t e = 0; e < nn; ++e) F[e] = val(f, e);
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_export_root_factor(bmpc_plan p, double* LR) {
+  if (!p || !LR) return BMPC_ERR_INVALID;
+  if (!p->factored) return BMPC_ERR_STATE;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
+  if (hipMemcpy(LR, p->LR, (size_t)p->d.n * p->d.n * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return BMPC_ERR_DEVICE;
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_set_profiling(bmpc_plan p, int32_t enable) {
+  if (!p) return BMPC_ERR_INVALID;
+  if (!enable) collect_timings(p);
+  p->profiling = enable != 0;
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_get_kernel_times(bmpc_plan p, int32_t max_classes, int64_t* launches,
+                                  double* total_ms) {
+  if (!p || max_classes < 0 || (max_classes > 0 && (!launches || !total_ms)))
+    return BMPC_ERR_INVALID;
+  collect_timings(p);
+  for (int c = 0; c < std::min<int>(max_classes, KC_COUNT); ++c) {
+    launches[c] = p->launches[c];
+    total_ms[c] = p->total_ms[c];
+  }
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_reset_kernel_times(bmpc_plan p) {
+  if (!p) return BMPC_ERR_INVALID;
+  collect_timings(p);
+  for (int c = 0; c < KC_COUNT; ++c) {
+    p->launches[c] = 0;
+    p->total_ms[c] = 0.0;
+  }
+  return BMPC_OK;
+}
+
+int32_t bmpc_kernel_class_count(void) { return KC_COUNT; }
+
+const char* bmpc_kernel_class_name(int32_t cls) {
+  static const char* names[KC_COUNT] = {
+      "factor_init",  "factor_first_pass", "factor_mid_pass", "factor_final_pass",
+      "root_reduce",  "root_potrf",        "solve_fwd",       "solve_x_fwd",
+      "solve_root",   "solve_x_bwd",       "solve_bwd",       "residual",
+      "residual_root", "refine_misc"};
+  if (cls < 0 || cls >= KC_COUNT) return "";
+  return names[cls];
+}
+
+bmpc_status bmpc_destroy(bmpc_plan p) {
+  if (!p) return BMPC_ERR_INVALID;
+  (void)hipStreamSynchronize(p->stream);
+  free_plan_memory(p);
+  delete p;
+  return BMPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal declarations of the bmpc HIP library (gfx950).
+//
+// Chain notation used by every kernel (Section IV-A).  Tail s is reversed
+// (Omega_i) so that chain position j = 1..m, m = N-1, holds stage N-j; the
+// root-coupled stage 0 (the paper's x_1) is kept last and is called X below
+// (position N).  The coupling from chain position j to its successor is
+// K[pos j+1, pos j] = E[s][N-1-j]^T (for j = m the successor is X).  Under
+// Gamma_{N-1} position j is eliminated at level tz(j)+1 (tz = trailing zeros):
+// level 1 takes the odd positions, level 2 the positions 2*odd, ... (the groups of
+// the recursion in Section II), and X comes last.  When position j (level t+1) is
+// eliminated, its current neighbours are j-2^t (left, if >= 1) and j+2^t (right,
+// or X when j+2^t > m).
+//
+// Factor storage (plan-owned, precision T of the tail factor):
+//   Linv[S][N][n][n]  L_jj^{-1} of position j at index j-1, X at index N-1
+//   Gl  [S][m][n][n]  factor block of the left neighbour's row, G_l = K[left,j] L_jj^{-T}
+//   Gr  [S][m][n][n]  factor block of the right neighbour's row (or X's row)
+//   F   [S][n][n]     F_{s,1} = C_s L_X^{-T} (the only block of the root row, Thm 1)
+//   U   [S][n][n]     F F^T in FP64;  LR[n][n] = chol(R - sum U) in FP64
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmpc {
+
+constexpr int kFactorThreads = 256;
+constexpr int kSolveThreads = 64;
+constexpr int kMaxRhs = 8;
+constexpr int kMaxWindowDepth = 6;
+
+// Kernel classes for per-kernel event timing.
+enum KernelClass : int {
+  KC_FACTOR_INIT = 0,
+  KC_FACTOR_FIRST,   // first factor pass when it is not also the last
+  KC_FACTOR_MID,     // intermediate factor passes
+  KC_FACTOR_FINAL,   // last factor pass + the x_1 step (F, U)
+  KC_ROOT_REDUCE,    // partial sums of U over scenario groups
+  KC_ROOT_POTRF,     // R~ = R - sum U, L_R = chol(R~)
+  KC_SOLVE_FWD,      // tail forward substitution, one launch per level
+  KC_SOLVE_X_FWD,    // x_1 forward step + F y products
+  KC_SOLVE_ROOT,     // root reduction and root triangular solves
+  KC_SOLVE_X_BWD,    // root propagation and x_1 backward step
+  KC_SOLVE_BWD,      // tail backward substitution, one launch per level
+  KC_RESIDUAL,       // FP64 tail residual b - K x
+  KC_RESIDUAL_ROOT,  // FP64 root residual
+  KC_REFINE_MISC,    // refinement bookkeeping (norm reset, stop test)
+  KC_COUNT
+};
+
+struct FactorPassArgs {
+  int S, N, n, m;       // m = N - 1
+  int Tw;               // window depth (levels per pass)
+  int pass, npass;      // index of this pass and total passes
+  int mk, shift;        // reduced chain length, position stride log2
+  int windows;          // windows per chain
+  int is_final;
+  const double* D;
+  const double* E;
+  const double* C;
+  // reduced-chain inputs written by the previous pass (null for pass 0)
+  const void* accR_in;  // [S][stride] : update of a node from the window on its left
+  const void* accL_in;  // [S][stride] : update of a node from the window on its right
+  const void* fill_in;  // [S][stride] : coupling from node q to its successor
+  void* accR_out;
+  void* accL_out;
+  void* fill_out;
+  int stride;           // blocks per chain in the reduced-chain buffers
+  void* accX;           // [S][npass] : X updates of each pass
+  void* Linv;
+  void* Gl;
+  void* Gr;
+  void* F;
+  double* U;
+  const int* permpos;   // [N] permuted position of chain position j at j-1 (X at N-1)
+  unsigned long long* info;
+};
+
+struct SolveArgs {
+  int S, N, n, m, nrhs;
+  const void* Linv;
+  const void* Gl;
+  const void* Gr;
+  const void* F;
+  const double* LR;
+  const double* b;       // [nrhs][len] FP64 input
+  double* x;             // [nrhs][len] FP64 output
+  void* y;               // [S][N][nrhs][n] scratch, precision T
+  double* w;             // [S][nrhs][n] FP64 products F_s y_X
+  double* x0;            // [nrhs][n]
+  const double* rnorm;   // refinement: input scale 1/rnorm, output x += rnorm * d
+  double* dnorm;         // refinement: max |rnorm * d| per rhs
+  double* xnorm;         // refinement: max |x| per rhs after the update
+  const int* done;       // refinement stop flag (null outside refinement)
+  int accumulate;        // 0: x = d ; 1: x += rnorm * d (refinement update)
+};
+
+struct ResidualArgs {
+  int S, N, n, nrhs;
+  const double* D;
+  const double* E;
+  const double* C;
+  const double* R;
+  const double* b;
+  const double* x;
+  double* r;             // [nrhs][len]
+  double* w;             // [S][nrhs][n] products C_s x_{s,0}
+  double* rnorm;         // [nrhs] max |r|
+  const int* done;
+};
+
+// launchers (defined next to their kernels)
+template <typename T>
+void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st);
+void launch_factor_init(unsigned long long* info, hipStream_t st);
+void launch_root_reduce(const double* U, double* part, int S, int n, int groups,
+                        hipStream_t st);
+void launch_root_potrf(const double* R, const double* part, int groups, int n,
+                       double* LR, int64_t row_base, unsigned long long* info,
+                       hipStream_t st);
+
+template <typename T>
+void launch_solve_fwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st);
+template <typename T>
+void launch_solve_x_fwd(const SolveArgs& a, int nmax, hipStream_t st);
+void launch_solve_root(const SolveArgs& a, hipStream_t st);
+template <typename T>
+void launch_solve_x_bwd(const SolveArgs& a, int nmax, hipStream_t st);
+template <typename T>
+void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st);
+
+void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st);
+void launch_residual_root(const ResidualArgs& a, hipStream_t st);
+void launch_refine_reset(double* norms, int count, int* flags, int reset_iters,
+                         hipStream_t st);
+void launch_refine_check(const double* dnorm, const double* xnorm, int nrhs,
+                         double tol, int* flags, double* relcorr, hipStream_t st);
+
+// number of chain positions eliminated at level l (1-based) of a chain of length m
+inline int level_count(int m, int l) {
+  int ml = m >> (l - 1);
+  return (ml + 1) >> 1;
+}
+inline int chain_levels(int m) {
+  int L = 0;
+  while ((m >> L) > 0) ++L;
+  return L;  // floor(log2 m) + 1 for m >= 1, 0 for m = 0
+}
+
+}  // namespace bmpc

@@ -1,0 +1,80 @@
+"""Host-side checks of the HIP library: exports, ordering, structure, cost model.
+
+These call only host functions of libbmpc.so (no device is touched)."""
+import os
+import re
+
+import pytest
+
+from oracle import symbolic
+from paper_2609_29977_amd import bmpc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    with open(os.path.join(ROOT, "include", "bmpc.h")) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(bmpc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_header_symbol():
+    L = bmpc.lib()
+    names = header_symbols()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(bmpc.EXPORTED) == names
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 7, 8, 9, 16, 31, 32, 33, 100, 128, 255, 256, 257])
+def test_ordering_bit_exact_with_oracle(N):
+    assert bmpc.ordering(N) == symbolic.tail_perm(N)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 8, 9, 16, 17, 64, 100, 256])
+def test_structure_bit_exact_with_elimination_game(N):
+    assert bmpc.structure(N) == symbolic.tail_structure(N, "d")
+
+
+def _flops_from_structure(S, N, n):
+    """Method flop count from the oracle's symbolic factor structure: every eliminated
+    block variable costs a potrf, a trsm + syrk per later neighbour and a gemm per
+    pair of later neighbours; the root adds the reduction and its Cholesky."""
+    potrf = n ** 3 / 3 + n ** 2 / 2 + n / 6
+    trsm, syrk, gemm = n ** 3, n ** 3 + n ** 2, 2 * n ** 3
+    order = [(0, k) for k in symbolic.tail_perm(N)] + [symbolic.ROOT]
+    adj = {v: set(nb) for v, nb in symbolic.block_graph(1, N).items()}
+    done, per_tail = set(), 0.0
+    for v in order[:-1]:
+        later = [u for u in adj[v] if u not in done]
+        per_tail += potrf + len(later) * (trsm + syrk) + gemm * len(later) * (len(later) - 1) / 2
+        for a in later:
+            for c in later:
+                if a != c:
+                    adj[a].add(c)
+        done.add(v)
+    return S * per_tail + S * n * n + potrf
+
+
+@pytest.mark.parametrize("S,N,n", [(4, 16, 8), (256, 128, 16), (512, 256, 32), (3, 1, 5),
+                                   (2, 2, 3), (7, 100, 13)])
+def test_cost_model_flops(S, N, n):
+    c = bmpc.cost_model(S, N, n, 1, "fp64")
+    assert c.factor_flops == pytest.approx(_flops_from_structure(S, N, n), rel=1e-12)
+    assert c.levels == (N - 1).bit_length() + 1
+
+
+def test_metric_workload_counts():
+    c = bmpc.cost_model(512, 256, 32, 1, "fp64")
+    assert c.factor_flops == pytest.approx(26.93e9, rel=2e-4)
+    assert c.solve_flops == pytest.approx(1.323e9, rel=1e-3)
+    assert c.factor_bytes == pytest.approx(4.29e9, rel=1e-3)
+
+
+@pytest.mark.parametrize("dims", [(0, 4, 4, 1), (4, 0, 4, 1), (4, 4, 0, 1), (4, 4, 33, 1),
+                                  (4, 4, 4, 0), (4, 4, 4, 9)])
+def test_cost_model_rejects_bad_dims(dims):
+    with pytest.raises(bmpc.BmpcError) as e:
+        bmpc.cost_model(*dims)
+    assert e.value.status == bmpc.ERR_INVALID
