@@ -150,12 +150,15 @@ bmpc_status bmpc_get_stats(bmpc_plan plan, int32_t* iters, double* rel_correctio
 bmpc_status bmpc_query_perm(bmpc_plan plan, int32_t* perm);
 bmpc_status bmpc_query_cost(bmpc_plan plan, bmpc_cost* cost);
 
-/* Algorithmic HBM bytes and flops of one bmpc_factor call attributed to kernel class
- * cls (see bmpc_kernel_class_name): for the factor passes, the D blocks read and
- * the factor blocks written by the positions the pass eliminates (the first pass
- * also reads every E block).  Zero for classes without a model. */
+/* Algorithmic HBM bytes and flops that kernel class cls (see bmpc_kernel_class_name)
+ * moves / performs in one call of the entry point that launches it (bmpc_factor for
+ * the factor classes, one solve sweep for the solve classes, one residual for the
+ * residual classes), and the number of launches of that class per such call.  For
+ * the factor passes: the D blocks read and the factor blocks written by the
+ * positions the pass eliminates (the first pass also reads every E block).  Any
+ * output pointer may be NULL. */
 bmpc_status bmpc_query_kernel_cost(bmpc_plan plan, int32_t cls, double* bytes,
-                                   double* flops);
+                                   double* flops, int32_t* launches);
 
 /* Copy the factor of tail s to host memory (synchronizes): L [N*n][N*n] row-major
  * in permuted order (lower block structure of L_i; the DIAGONAL blocks are given as

@@ -89,7 +89,7 @@ def lib():
         "bmpc_get_stats": [vp, P(i32), P(dbl)],
         "bmpc_query_perm": [vp, P(i32)],
         "bmpc_query_cost": [vp, P(_Cost)],
-        "bmpc_query_kernel_cost": [vp, i32, P(dbl), P(dbl)],
+        "bmpc_query_kernel_cost": [vp, i32, P(dbl), P(dbl), P(i32)],
         "bmpc_export_tail_factor": [vp, i32, P(dbl), P(dbl)],
         "bmpc_export_root_factor": [vp, P(dbl)],
         "bmpc_set_profiling": [vp, i32],
@@ -280,10 +280,12 @@ class Plan:
         return _cost(c)
 
     def kernel_cost(self, cls: int):
-        b, f = ctypes.c_double(0), ctypes.c_double(0)
+        """(bytes, flops, launches) of kernel class cls per call of its entry point."""
+        b, f, k = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int32(0)
         _check(lib().bmpc_query_kernel_cost(self._h, int(cls), ctypes.byref(b),
-                                            ctypes.byref(f)), "bmpc_query_kernel_cost")
-        return float(b.value), float(f.value)
+                                            ctypes.byref(f), ctypes.byref(k)),
+               "bmpc_query_kernel_cost")
+        return float(b.value), float(f.value), int(k.value)
 
     def export_tail_factor(self, s: int):
         import numpy as np

@@ -70,6 +70,7 @@ struct Costs {
   double factor_flops = 0, solve_flops = 0, factor_bytes = 0, solve_bytes = 0,
          residual_bytes = 0, L_bytes = 0;
   double pass_flops[KC_COUNT] = {0}, pass_bytes[KC_COUNT] = {0};
+  int launches[KC_COUNT] = {0};
   int levels = 0, Tw = 0;
 };
 
@@ -130,6 +131,25 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw) {
   c.solve_flops = d.nrhs * ((double)S * (2.0 * N * nn + 4.0 * nG * nn + 4.0 * nn) +
                             (double)S * n + 2.0 * nn);
   c.levels = chain_levels(m) + 1;
+  // Per-call solve / residual classes: factor blocks read once per sweep, the
+  // right-hand side gathered once, x scattered once, the y scratch written and read.
+  const double q = d.nrhs, vec_t = tb * n * q;
+  const double chain_blocks = (double)S * (m * tri + nG * nn) * tb;
+  c.pass_bytes[KC_SOLVE_FWD] = chain_blocks + (double)S * m * (8.0 * n * q + vec_t) +
+                               (double)S * nG * vec_t;
+  c.pass_flops[KC_SOLVE_FWD] = q * (double)S * (2.0 * m * nn + 2.0 * nG * nn);
+  c.pass_bytes[KC_SOLVE_BWD] = chain_blocks + (double)S * m * (8.0 * n * q + 2.0 * vec_t) +
+                               (double)S * nG * vec_t;
+  c.pass_flops[KC_SOLVE_BWD] = c.pass_flops[KC_SOLVE_FWD];
+  c.pass_bytes[KC_SOLVE_X_FWD] = (double)S * (2.0 * tb * nn + 8.0 * n * q + 8.0 * n * q);
+  c.pass_bytes[KC_SOLVE_X_BWD] = (double)S * (2.0 * tb * nn + 8.0 * n * q + vec_t);
+  c.pass_bytes[KC_SOLVE_ROOT] = 8.0 * ((double)S * n * q + 2.0 * n * q + tri);
+  c.pass_bytes[KC_RESIDUAL] = K_bytes - 8.0 * tri + 3.0 * 8.0 * (double)S * N * n * q;
+  c.pass_bytes[KC_RESIDUAL_ROOT] = 8.0 * (tri + (double)S * n * q + 3.0 * n * q);
+  const int L = chain_levels(m);
+  for (int k = 0; k < KC_COUNT; ++k) c.launches[k] = 1;
+  c.launches[KC_SOLVE_FWD] = L;
+  c.launches[KC_SOLVE_BWD] = L;
   return c;
 }
 
@@ -616,10 +636,12 @@ bmpc_status bmpc_query_cost(bmpc_plan p, bmpc_cost* cost) {
   return BMPC_OK;
 }
 
-bmpc_status bmpc_query_kernel_cost(bmpc_plan p, int32_t cls, double* bytes, double* flops) {
+bmpc_status bmpc_query_kernel_cost(bmpc_plan p, int32_t cls, double* bytes, double* flops,
+                                   int32_t* launches) {
   if (!p || cls < 0 || cls >= KC_COUNT) return BMPC_ERR_INVALID;
   if (bytes) *bytes = p->costs.pass_bytes[cls];
   if (flops) *flops = p->costs.pass_flops[cls];
+  if (launches) *launches = p->costs.launches[cls];
   return BMPC_OK;
 }
 

@@ -12,8 +12,11 @@
 // Schur updates to them and the coupling (fill) between them to the next pass, which
 // runs the same walk on the reduced chain of boundary positions (levels Tw+1..2Tw),
 // and so on.  A boundary node's updates from all earlier passes ride along in the
-// left accumulator of the window it starts, so its A is always D + all updates.  The last pass also eliminates x_1 (position X) and forms the coupling
-// solve F = C L_X^{-T} and the local Schur update U = F F^T (Algorithm 1, lines 4-5).
+// left accumulator of the window it starts, so its A is always D + all updates.
+// The last pass also eliminates x_1 (position X) and forms the coupling solve
+// F = C L_X^{-T} and the local Schur update U = F F^T (Algorithm 1, lines 4-5).
+// FIRST (the pass reading D and E) and FINAL are template flags so that each pass
+// kind is its own kernel symbol in profiles.
 //
 // Elimination of position j with neighbours l (left, optional) and r (right),
 // Section IV-B in block form:
@@ -78,7 +81,7 @@ __device__ inline void eliminate(T* Aj, T* Cj, T* Al, T* Cl, T* Ar, int n, T* gL
   }
 }
 
-template <typename T, int NMAX>
+template <typename T, int NMAX, bool FIRST, bool FINAL>
 __global__ void __launch_bounds__(NT) factor_pass_kernel(FactorPassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Slots<T, NMAX> sl{reinterpret_cast<T*>(smem_raw), a.Tw};
@@ -103,7 +106,7 @@ __global__ void __launch_bounds__(NT) factor_pass_kernel(FactorPassArgs a) {
   auto load_node = [&](T* dst, int q) {
     const int j = q << a.shift;
     lds_load_sym_lower<T, NMAX, NT>(dst, a.D + ((size_t)s * N + (N - j)) * nn, n);
-    if (a.pass > 0) {
+    if (!FIRST) {
       __syncthreads();
       const T* ar = reinterpret_cast<const T*>(a.accR_in) + ((size_t)s * a.stride + q) * nn;
       const T* al = reinterpret_cast<const T*>(a.accL_in) + ((size_t)s * a.stride + q) * nn;
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(NT) factor_pass_kernel(FactorPassArgs a) {
     }
   };
   auto load_coupling = [&](T* dst, int q) {
-    if (a.pass == 0) {
+    if (FIRST) {
       // K[pos q+1, pos q] = E[s][N-1-q]^T
       lds_load<T, NMAX, NT>(dst, a.E + ((size_t)s * (N - 1) + (N - 1 - q)) * nn, n, true);
     } else {
@@ -124,7 +127,7 @@ __global__ void __launch_bounds__(NT) factor_pass_kernel(FactorPassArgs a) {
   if (has_left) {
     // The left boundary node keeps the updates it received while it was a window
     // boundary in earlier passes; they travel with it in its left accumulator.
-    if (a.pass > 0) {
+    if (!FIRST) {
       const size_t base = (size_t)s * a.stride + lo;
       lds_load<T, NMAX, NT>(sl.AL(), reinterpret_cast<const T*>(a.accR_in) + base * nn, n,
                             false);
@@ -179,7 +182,7 @@ __global__ void __launch_bounds__(NT) factor_pass_kernel(FactorPassArgs a) {
     elim_level(t, pos, sl.AR());
   }
 
-  if (!a.is_final) {
+  if (!FINAL) {
     const size_t base = (size_t)s * a.stride;
     if (has_left) {
       lds_store<T, NMAX, NT>(reinterpret_cast<T*>(a.accL_out) + (base + w) * nn, sl.AL(), n);
@@ -282,17 +285,32 @@ size_t pass_lds_bytes(int Tw) {
   return (size_t)(2 * Tw + 3) * Lay<NMAX>::SZ * sizeof(T);
 }
 
-template <typename T, int NMAX>
-void launch_pass_t(const FactorPassArgs& a, hipStream_t st) {
+template <typename T, int NMAX, bool FIRST, bool FINAL>
+void launch_pass_k(const FactorPassArgs& a, hipStream_t st) {
   const size_t lds = pass_lds_bytes<T, NMAX>(a.Tw);
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&factor_pass_kernel<T, NMAX>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&factor_pass_kernel<T, NMAX, FIRST, FINAL>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   const unsigned grid = (unsigned)a.S * (unsigned)a.windows;
-  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX>), dim3(grid), dim3(NT), lds, st, a);
+  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX, FIRST, FINAL>), dim3(grid), dim3(NT), lds,
+                     st, a);
+}
+
+template <typename T, int NMAX>
+void launch_pass_t(const FactorPassArgs& a, hipStream_t st) {
+  const bool first = a.pass == 0;
+  if (first && a.is_final)
+    launch_pass_k<T, NMAX, true, true>(a, st);
+  else if (first)
+    launch_pass_k<T, NMAX, true, false>(a, st);
+  else if (a.is_final)
+    launch_pass_k<T, NMAX, false, true>(a, st);
+  else
+    launch_pass_k<T, NMAX, false, false>(a, st);
 }
 
 }  // namespace
