@@ -65,111 +65,192 @@ __device__ inline void lds_store(T* __restrict__ dst, const T* src, int n) {
   }
 }
 
-// ---- block products ------------------------------------------------------------
+// ---- wave-uniform broadcast and reciprocal square root ---------------------------
 
-// out = alpha * op(X) * Y^T           (accumulate == false)
-// out = out + alpha * op(X) * Y^T     (accumulate == true)
-// with op(X)[r][k] = X[k][r] if transX else X[r][k].  out may alias X or Y: the
-// products are formed in registers and written after a barrier.
-template <typename T, int NMAX, int NT>
-__device__ inline void lds_gemm_nt(T* out, const T* X, bool transX, const T* Y, T alpha,
-                                   bool accumulate, int n) {
-  constexpr int LD = Lay<NMAX>::LD;
-  constexpr int OUTS = (NMAX * NMAX + NT - 1) / NT;   // outputs per thread
-  constexpr int CPT = OUTS < 1 ? 1 : OUTS;            // consecutive columns per thread
-  constexpr int TPR = NMAX / CPT;                     // threads per row
-  const int tid = threadIdx.x;
-  const int r = tid / TPR;
-  const int c0 = (tid - r * TPR) * CPT;
-  const bool active = (tid < NMAX * TPR) && (r < n);
-  T acc[CPT];
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) acc[q] = T(0);
-  if (active) {
-    for (int k = 0; k < n; ++k) {
-      const T xv = transX ? X[k * LD + r] : X[r * LD + k];
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) acc[q] += xv * Y[(c0 + q) * LD + k];
-    }
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int c = c0 + q;
-      if (c < n) {
-        T* o = &out[r * LD + c];
-        *o = accumulate ? *o + alpha * acc[q] : alpha * acc[q];
-      }
-    }
-  }
-  __syncthreads();
+__device__ inline float wave_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ inline double wave_bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/sqrt(x): hardware estimate refined by Newton steps y <- y (3 - x y^2) / 2
+// (one step for FP32, two for FP64: the estimate's error squares each step).
+__device__ inline float rsqrt_refined(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  y = y * (1.5f - 0.5f * x * y * y);
+  return y;
+}
+__device__ inline double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
 }
 
 // ---- Cholesky of one block (one wave, lane = row) ------------------------------
 
-// In place: A (symmetric, lower triangle read) := L with L L^T = A, zeros above the
-// diagonal.  Returns (on every lane) the 0-based row of the first non-positive
-// pivot, or -1.  Must be called by all 64 lanes of one wave.
+// In place: A (symmetric NMAX x NMAX, lower triangle read; pad smaller blocks with an
+// identity block) := L with L L^T = A, zeros above the diagonal.  One wave, lane i
+// keeps row i; column k of L is broadcast with readlane.  Returns (on every lane)
+// the 0-based row of the first non-positive pivot, or -1.
 template <typename T, int NMAX>
-__device__ inline int wave_potrf(T* A, int n) {
+__device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
   constexpr int LD = Lay<NMAX>::LD;
   const int lane = threadIdx.x & 63;
+  const int row = lane < NMAX ? lane : NMAX - 1;
   T a[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c)
-    a[c] = (lane < n && c < n && c <= lane) ? A[lane * LD + c] : T(0);
+  for (int c = 0; c < NMAX; ++c) a[c] = A[row * LD + c];
   int fail = -1;
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
-    if (k < n) {
-      const T piv = __shfl(a[k], k);
-      if (fail < 0 && !(piv > T(0))) fail = k;
-      const T d = sqrt(piv);
-      const T inv = T(1) / d;
-      const T lik = (lane == k) ? d : a[k] * inv;
-      if (lane >= k) a[k] = lik;
+    const T piv = wave_bcast(a[k], k);
+    if (fail < 0 && !(piv > T(0))) fail = k;
+    const T d = sqrt(piv);
+    const T lik = (lane == k) ? d : a[k] / d;
+    a[k] = lik;
 #pragma unroll
-      for (int c = k + 1; c < NMAX; ++c) {
-        if (c < n) {
-          const T lck = __shfl(lik, c);
-          if (lane >= c) a[c] -= lik * lck;
-        }
-      }
-    }
+    for (int c = k + 1; c < NMAX; ++c) a[c] -= lik * wave_bcast(lik, c);
   }
-  if (lane < n) {
+  if (lane < NMAX) {
 #pragma unroll
-    for (int c = 0; c < NMAX; ++c)
-      if (c < n) A[lane * LD + c] = (c <= lane) ? a[c] : T(0);
+    for (int c = 0; c < NMAX; ++c) A[lane * LD + c] = (c <= lane) ? a[c] : T(0);
   }
   return fail;
 }
 
-// In place: L (lower triangular) := L^{-1}.  One wave; lane j forms column j by
-// forward substitution L x = e_j with the rows of L read as LDS broadcasts.
+// In place: A (symmetric NMAX x NMAX, lower triangle read) := L^{-1} with L L^T = A.
+// One wave; lane i < NMAX keeps row i of A and row i of Z (Z := I initially) in
+// registers.  Step k forms column k of L (right-looking Cholesky) and applies the
+// same row operations to Z (forward elimination of L Z = I), so Z ends as L^{-1}.
+// Z's rows are kept unscaled: row k is divided by L[k][k] only at the end, and the
+// multiplier used on the rows below carries that division instead.  Rows are
+// broadcast with readlane (wave-uniform scalars), so there are no LDS round trips
+// and no per-lane branches: the trailing update runs on every lane and only ever
+// writes garbage above the diagonal (never read for the result), and the Z update is
+// masked through its multiplier.  Blocks smaller than NMAX must be padded with an
+// identity block.  Returns (on every lane) the 0-based row of the first non-positive
+// pivot, or -1.
 template <typename T, int NMAX>
-__device__ inline void wave_trtri(T* A, int n) {
+__device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
   constexpr int LD = Lay<NMAX>::LD;
   const int lane = threadIdx.x & 63;
-  T x[NMAX];
+  const int row = lane < NMAX ? lane : NMAX - 1;
+  T a[NMAX], z[NMAX];
 #pragma unroll
-  for (int i = 0; i < NMAX; ++i) {
-    if (i < n) {
-      T s = (i == lane) ? T(1) : T(0);
-#pragma unroll
-      for (int k = 0; k < i; ++k) s -= A[i * LD + k] * x[k];
-      x[i] = s / A[i * LD + i];
-    } else {
-      x[i] = T(0);
-    }
+  for (int c = 0; c < NMAX; ++c) {
+    a[c] = A[row * LD + c];
+    z[c] = (c == lane) ? T(1) : T(0);
   }
-  // all lanes have finished reading L (the wave runs in lockstep); write columns
-  __builtin_amdgcn_wave_barrier();
-  if (lane < n) {
+  int fail = -1;
+  T myinv = T(1);
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-      if (i < n) A[i * LD + lane] = (i >= lane) ? x[i] : T(0);
+  for (int k = 0; k < NMAX; ++k) {
+    const T piv = wave_bcast(a[k], k);
+    if (fail < 0 && !(piv > T(0))) fail = k;
+    const T inv = rsqrt_refined(piv);
+    const T lik = a[k] * inv;  // L[lane][k] for lane >= k (lane k: sqrt(piv))
+    a[k] = lik;
+    myinv = (lane == k) ? inv : myinv;
+    T lc[NMAX], zk[NMAX];
+#pragma unroll
+    for (int c = k + 1; c < NMAX; ++c) lc[c] = wave_bcast(lik, c);
+#pragma unroll
+    for (int c = 0; c <= k; ++c) zk[c] = wave_bcast(z[c], k);
+#pragma unroll
+    for (int c = k + 1; c < NMAX; ++c) a[c] -= lik * lc[c];
+    const T zm = (lane > k) ? lik * inv : T(0);
+#pragma unroll
+    for (int c = 0; c <= k; ++c) z[c] -= zm * zk[c];
+  }
+  if (lane < NMAX) {
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) A[lane * LD + c] = (c <= lane) ? z[c] * myinv : T(0);
+  }
+  return fail;
+}
+
+// ---- MFMA block products (16x16x4 tiles) ------------------------------------------
+
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef mf32x4 acc_t;
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of accumulator element v held by lane l (column is l % 16)
+  __device__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct Mfma<double> {
+  typedef mf64x4 acc_t;
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+
+// Threads per workgroup of the blocked kernels: one wave per 16x16 output tile.
+template <int NMAX>
+struct TileCfg {
+  static constexpr int TILES = (NMAX + 15) / 16;     // tiles per dimension
+  static constexpr int NT = 64 * TILES * TILES;      // one wave per output tile
+  static constexpr int KSTEPS = NMAX / 4;            // MFMA k-steps (4 k per step)
+};
+
+// This wave's 16x16 tile of op(X) Y^T (NMAX x NMAX blocks in LDS, zero padded beyond
+// the used size) in MFMA accumulator layout, op(X)[r][k] = X[k][r] if transX.  The
+// contraction index is distributed as k = KSTEPS*(lane/16) + s over the MFMA steps s,
+// identically for both operands.  Blocks smaller than a tile (NMAX = 8) are masked.
+template <typename T, int NMAX, bool TRANSX>
+__device__ __attribute__((always_inline)) inline typename Mfma<T>::acc_t mfma_tile_nt(
+    const T* X, const T* Y) {
+  constexpr int LD = Lay<NMAX>::LD;
+  constexpr int KS = TileCfg<NMAX>::KSTEPS;
+  const int w = (threadIdx.x >> 6) % (TileCfg<NMAX>::TILES * TileCfg<NMAX>::TILES);
+  const int l = threadIdx.x & 63;
+  const int ti = w / TileCfg<NMAX>::TILES, tj = w % TileCfg<NMAX>::TILES;
+  const int g = l >> 4, i = l & 15;
+  const int r = ti * 16 + i, c = tj * 16 + i;
+  const bool rin = NMAX >= 16 || r < NMAX, cin = NMAX >= 16 || c < NMAX;
+  const int rr = rin ? r : 0, cc = cin ? c : 0;
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = KS * g + s;
+    T a = TRANSX ? X[k * LD + rr] : X[rr * LD + k];
+    T b = Y[cc * LD + k];
+    if (!rin) a = T(0);
+    if (!cin) b = T(0);
+    acc = Mfma<T>::mma(a, b, acc);
+  }
+  return acc;
+}
+
+// out[tile] = alpha * acc  or  out[tile] += alpha * acc (NMAX x NMAX blocks)
+template <typename T, int NMAX, bool ACCUMULATE>
+__device__ __attribute__((always_inline)) inline void mfma_tile_store(
+    T* out, const typename Mfma<T>::acc_t& acc, T alpha) {
+  constexpr int LD = Lay<NMAX>::LD;
+  const int w = (threadIdx.x >> 6) % (TileCfg<NMAX>::TILES * TileCfg<NMAX>::TILES);
+  const int l = threadIdx.x & 63;
+  const int ti = w / TileCfg<NMAX>::TILES, tj = w % TileCfg<NMAX>::TILES;
+  const int c = tj * 16 + (l & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = ti * 16 + Mfma<T>::row(l, v);
+    if (NMAX >= 16 || (r < NMAX && c < NMAX)) {
+      T* o = &out[r * LD + c];
+      *o = ACCUMULATE ? *o + alpha * acc[v] : alpha * acc[v];
+    }
   }
 }
 

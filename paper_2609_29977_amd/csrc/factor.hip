@@ -22,14 +22,14 @@
 // Section IV-B in block form:
 //   L_jj = chol(A_j);  G_l = K[l,j] L_jj^{-T};  G_r = K[r,j] L_jj^{-T}
 //   A_l -= G_l G_l^T;  A_r -= G_r G_r^T;  K[r,l] = -G_r G_l^T (fill)
+#include <type_traits>
+
 #include "bmpc_internal.h"
 #include "blockops.h"
 
 namespace bmpc {
 
 namespace {
-
-constexpr int NT = kFactorThreads;
 
 template <typename T, int NMAX>
 struct Slots {
@@ -43,50 +43,173 @@ struct Slots {
   __device__ T* AR() const { return base + (2 * Tw + 2) * SZ; }
 };
 
-__device__ inline void record_failure(unsigned long long* info, unsigned long long row) {
-  atomicMin(info, row);
+// Per-thread share of an NMAX x NMAX block: element e = threadIdx.x + j*NT.
+template <int NMAX>
+struct Share {
+  static constexpr int NT = TileCfg<NMAX>::NT;
+  static constexpr int ELEMS = (NMAX * NMAX + NT - 1) / NT;
+  __device__ static int elem(int j) { return threadIdx.x + j * NT; }
+};
+
+// Zero an NMAX x NMAX slot (padding included).
+template <typename T, int NMAX>
+__device__ inline void slot_zero(T* dst) {
+  constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+  for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
+    const int e = Share<NMAX>::elem(j);
+    if (e < NMAX * NMAX) dst[(e / NMAX) * LD + e % NMAX] = T(0);
+  }
 }
 
-// potrf + inverse of the diagonal block in place, failure recorded with the
-// 1-based permuted row index.
+// dst = src (n x n global, type S, optionally added to dst), zero padding.
+template <typename T, int NMAX, typename S>
+__device__ inline void slot_load(T* dst, const S* __restrict__ src, int n, bool add) {
+  constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+  for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
+    const int e = Share<NMAX>::elem(j);
+    if (e < NMAX * NMAX) {
+      const int r = e / NMAX, c = e % NMAX;
+      const T v = (r < n && c < n) ? static_cast<T>(src[r * n + c]) : T(0);
+      dst[r * LD + c] = add ? dst[r * LD + c] + v : v;
+    }
+  }
+}
+
+// Register prefetch of one chain node: its diagonal block (D + carried updates) and
+// its coupling to the successor.  Issued one node ahead so that the global loads
+// overlap the eliminations of the current node.
+template <typename T, int NMAX, bool FIRST>
+struct NodeFetch {
+  static constexpr int EL = Share<NMAX>::ELEMS;
+  typedef typename std::conditional<FIRST, double, T>::type CT;
+  double d[EL];
+  T ar[EL], al[EL];
+  CT cp[EL];
+
+  __device__ void issue(const FactorPassArgs& a, int s, int q) {
+    const int n = a.n, N = a.N;
+    const size_t nn = (size_t)n * n;
+    const int j = q << a.shift;
+    const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
+    const T* accR = nullptr;
+    const T* accL = nullptr;
+    const CT* cpl;
+    if constexpr (FIRST) {
+      cpl = a.E + ((size_t)s * (N - 1) + (N - 1 - q)) * nn;  // K[q+1,q] = E[s][N-1-q]^T
+    } else {
+      const size_t o = ((size_t)s * a.stride + q) * nn;
+      accR = reinterpret_cast<const T*>(a.accR_in) + o;
+      accL = reinterpret_cast<const T*>(a.accL_in) + o;
+      cpl = reinterpret_cast<const T*>(a.fill_in) + o;
+    }
+#pragma unroll
+    for (int jj = 0; jj < EL; ++jj) {
+      const int e = Share<NMAX>::elem(jj);
+      const int r = e / NMAX, c = e % NMAX;
+      const bool in = e < NMAX * NMAX && r < n && c < n;
+      const bool lower = in && r >= c;
+      d[jj] = lower ? D[r * n + c] : 0.0;
+      if constexpr (!FIRST) {
+        ar[jj] = lower ? accR[r * n + c] : T(0);
+        al[jj] = lower ? accL[r * n + c] : T(0);
+      }
+      cp[jj] = in ? cpl[r * n + c] : CT(0);
+    }
+  }
+
+  __device__ void commit(T* A, T* C, int n) const {
+    constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+    for (int jj = 0; jj < EL; ++jj) {
+      const int e = Share<NMAX>::elem(jj);
+      if (e >= NMAX * NMAX) continue;
+      const int r = e / NMAX, c = e % NMAX;
+      const bool in = r < n && c < n;
+      if (in && r >= c) {
+        T v = static_cast<T>(d[jj]);
+        if constexpr (!FIRST) v = (v + ar[jj]) + al[jj];
+        A[r * LD + c] = v;
+        A[c * LD + r] = v;
+      } else if (!in) {
+        A[r * LD + c] = (r == c) ? T(1) : T(0);  // identity padding of diagonal blocks
+      }
+      const T cv = static_cast<T>(cp[jj]);
+      if constexpr (FIRST)
+        C[c * LD + r] = cv;
+      else
+        C[r * LD + c] = cv;
+    }
+  }
+};
+
 template <typename T, int NMAX>
-__device__ inline void factor_diag(T* A, int n, unsigned long long perm_row0,
+__device__ inline void slot_store(T* __restrict__ dst, const T* src, int n) {
+  constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+  for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
+    const int e = Share<NMAX>::elem(j);
+    if (e < NMAX * NMAX) {
+      const int r = e / NMAX, c = e % NMAX;
+      if (r < n && c < n) dst[r * n + c] = src[r * LD + c];
+    }
+  }
+}
+
+// L_jj^{-1} of the block in Aj (in place) by one wave; which wave does it rotates
+// with the workgroup index so that the latency-bound factorizations of the resident
+// workgroups spread over the SIMDs.
+template <typename T, int NMAX>
+__device__ inline void factor_diag(T* A, unsigned long long perm_row0, int n,
                                    unsigned long long* info) {
-  if (threadIdx.x < 64) {
-    const int fail = wave_potrf<T, NMAX>(A, n);
-    if (fail >= 0 && threadIdx.x == 0) record_failure(info, perm_row0 + fail + 1);
-    wave_trtri<T, NMAX>(A, n);
+  constexpr int NW = TileCfg<NMAX>::NT / 64;
+  if ((threadIdx.x >> 6) == (int)(blockIdx.x % NW)) {
+    const int fail = wave_potrf_inv<T, NMAX>(A);
+    if (fail >= 0 && fail < n && (threadIdx.x & 63) == 0) atomicMin(info, perm_row0 + fail + 1);
   }
   __syncthreads();
 }
 
+// One elimination (Section IV-B in block form): Aj := L_jj^{-1};
+// G_r = K[r,j] L^{-T} (into Cj), G_l = K[l,j] L^{-T} (into Cl, which holds K[j,l]);
+// A_r -= G_r G_r^T; A_l -= G_l G_l^T; K[r,l] = -G_r G_l^T (into Cl).
 template <typename T, int NMAX>
 __device__ inline void eliminate(T* Aj, T* Cj, T* Al, T* Cl, T* Ar, int n, T* gLinv,
                                  T* gGl, T* gGr, unsigned long long perm_row0,
                                  unsigned long long* info) {
-  factor_diag<T, NMAX>(Aj, n, perm_row0, info);  // Aj := L_jj^{-1}
-  // G_r = K[r,j] L^{-T}: Cj holds K[r,j]
-  lds_gemm_nt<T, NMAX, NT>(Cj, Cj, false, Aj, T(1), false, n);
-  if (Cl) {
-    // G_l = K[l,j] L^{-T} = (K[j,l])^T L^{-T}: Cl holds K[j,l]
-    lds_gemm_nt<T, NMAX, NT>(Cl, Cl, true, Aj, T(1), false, n);
+  typedef typename Mfma<T>::acc_t acc_t;
+  factor_diag<T, NMAX>(Aj, perm_row0, n, info);
+  const bool left = Cl != nullptr;
+  acc_t gr = mfma_tile_nt<T, NMAX, false>(Cj, Aj);
+  acc_t gl = {0, 0, 0, 0};
+  if (left) gl = mfma_tile_nt<T, NMAX, true>(Cl, Aj);
+  __syncthreads();
+  mfma_tile_store<T, NMAX, false>(Cj, gr, T(1));
+  if (left) mfma_tile_store<T, NMAX, false>(Cl, gl, T(1));
+  __syncthreads();
+  slot_store<T, NMAX>(gLinv, Aj, n);
+  slot_store<T, NMAX>(gGr, Cj, n);
+  if (left) slot_store<T, NMAX>(gGl, Cl, n);
+  acc_t ur = mfma_tile_nt<T, NMAX, false>(Cj, Cj);
+  acc_t ul = {0, 0, 0, 0}, uf = {0, 0, 0, 0};
+  if (left) {
+    ul = mfma_tile_nt<T, NMAX, false>(Cl, Cl);
+    uf = mfma_tile_nt<T, NMAX, false>(Cj, Cl);
   }
-  lds_store<T, NMAX, NT>(gLinv, Aj, n);
-  lds_store<T, NMAX, NT>(gGr, Cj, n);
-  if (Cl) lds_store<T, NMAX, NT>(gGl, Cl, n);
-  lds_gemm_nt<T, NMAX, NT>(Ar, Cj, false, Cj, T(-1), true, n);     // A_r -= G_r G_r^T
-  if (Cl) {
-    lds_gemm_nt<T, NMAX, NT>(Al, Cl, false, Cl, T(-1), true, n);   // A_l -= G_l G_l^T
-    lds_gemm_nt<T, NMAX, NT>(Cl, Cj, false, Cl, T(-1), false, n);  // K[r,l] = -G_r G_l^T
+  __syncthreads();
+  mfma_tile_store<T, NMAX, true>(Ar, ur, T(-1));
+  if (left) {
+    mfma_tile_store<T, NMAX, true>(Al, ul, T(-1));
+    mfma_tile_store<T, NMAX, false>(Cl, uf, T(-1));
   }
+  __syncthreads();
 }
 
 template <typename T, int NMAX, bool FIRST, bool FINAL>
-__global__ void __launch_bounds__(NT) factor_pass_kernel(FactorPassArgs a) {
+__global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Slots<T, NMAX> sl{reinterpret_cast<T*>(smem_raw), a.Tw};
-  constexpr int SZ = Lay<NMAX>::SZ;
-  (void)SZ;
   const int n = a.n, N = a.N;
   const size_t nn = (size_t)n * n;
   const int s = blockIdx.x / a.windows;
@@ -102,130 +225,131 @@ __global__ void __launch_bounds__(NT) factor_pass_kernel(FactorPassArgs a) {
   T* Gr = reinterpret_cast<T*>(a.Gr) + (size_t)s * (N > 1 ? N - 1 : 1) * nn;
   const unsigned long long chain_row0 = (unsigned long long)s * N * n;
 
-  // Loads of a node (reduced position q) and of its coupling to its successor.
-  auto load_node = [&](T* dst, int q) {
-    const int j = q << a.shift;
-    lds_load_sym_lower<T, NMAX, NT>(dst, a.D + ((size_t)s * N + (N - j)) * nn, n);
-    if (!FIRST) {
-      __syncthreads();
-      const T* ar = reinterpret_cast<const T*>(a.accR_in) + ((size_t)s * a.stride + q) * nn;
-      const T* al = reinterpret_cast<const T*>(a.accL_in) + ((size_t)s * a.stride + q) * nn;
-      lds_load<T, NMAX, NT>(dst, ar, n, false, true);
-      lds_load<T, NMAX, NT>(dst, al, n, false, true);
-    }
-  };
-  auto load_coupling = [&](T* dst, int q) {
-    if (FIRST) {
-      // K[pos q+1, pos q] = E[s][N-1-q]^T
-      lds_load<T, NMAX, NT>(dst, a.E + ((size_t)s * (N - 1) + (N - 1 - q)) * nn, n, true);
-    } else {
-      const T* f = reinterpret_cast<const T*>(a.fill_in) + ((size_t)s * a.stride + q) * nn;
-      lds_load<T, NMAX, NT>(dst, f, n, false);
-    }
-  };
+  NodeFetch<T, NMAX, FIRST> pf;
+  if (lo + 1 <= hi) pf.issue(a, s, lo + 1);
 
   if (has_left) {
     // The left boundary node keeps the updates it received while it was a window
     // boundary in earlier passes; they travel with it in its left accumulator.
-    if (!FIRST) {
+    if constexpr (!FIRST) {
       const size_t base = (size_t)s * a.stride + lo;
-      lds_load<T, NMAX, NT>(sl.AL(), reinterpret_cast<const T*>(a.accR_in) + base * nn, n,
-                            false);
-      __syncthreads();
-      lds_load<T, NMAX, NT>(sl.AL(), reinterpret_cast<const T*>(a.accL_in) + base * nn, n,
-                            false, true);
+      slot_load<T, NMAX>(sl.AL(), reinterpret_cast<const T*>(a.accR_in) + base * nn, n, false);
+      slot_load<T, NMAX>(sl.AL(), reinterpret_cast<const T*>(a.accL_in) + base * nn, n, true);
     } else {
-      lds_zero<T, NMAX, NT>(sl.AL(), n);
+      slot_zero<T, NMAX>(sl.AL());
     }
-    load_coupling(sl.CL(), lo);
+    // coupling of the left boundary to its successor
+    if constexpr (FIRST) {
+      constexpr int LD = Lay<NMAX>::LD;
+      const double* E = a.E + ((size_t)s * (N - 1) + (N - 1 - lo)) * nn;
+#pragma unroll
+      for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
+        const int e = Share<NMAX>::elem(j);
+        if (e < NMAX * NMAX) {
+          const int r = e / NMAX, c = e % NMAX;
+          sl.CL()[c * LD + r] = (r < n && c < n) ? static_cast<T>(E[r * n + c]) : T(0);
+        }
+      }
+    } else {
+      slot_load<T, NMAX>(sl.CL(), reinterpret_cast<const T*>(a.fill_in) +
+                                      ((size_t)s * a.stride + lo) * nn, n, false);
+    }
   }
-  lds_zero<T, NMAX, NT>(sl.AR(), n);
+  slot_zero<T, NMAX>(sl.AR());
   __syncthreads();
 
   unsigned live = 0u;
-  // Eliminate the live node of level t whose right neighbour's A slot is Ar.
-  auto elim_level = [&](int t, int pos_q, T* Ar) {
-    const unsigned above = live & ~((2u << t) - 1u);
-    T* Al = nullptr;
-    T* Cl = nullptr;
-    if (above) {
-      const int u = __builtin_ctz(above);
-      Al = sl.A(u);
-      Cl = sl.Cp(u);
-    } else if (has_left) {
-      Al = sl.AL();
-      Cl = sl.CL();
+  // Position q is read at step q; step hi+1 reads the right boundary.  After a read,
+  // every live level below the new node's level is eliminated, lowest first, with the
+  // new node as right neighbour (Gamma order: level tz(j)+1).
+  for (int q = lo + 1; q <= hi + 1; ++q) {
+    const bool is_rb = q > hi;
+    int v = 0;
+    unsigned todo;
+    if (!is_rb) {
+      v = __builtin_ctz((unsigned)q);
+      pf.commit(sl.A(v), sl.Cp(v), n);
+      __syncthreads();
+      if (q + 1 <= hi) pf.issue(a, s, q + 1);
+      todo = live & ((1u << v) - 1u);
+    } else {
+      todo = live;
     }
-    const int j = pos_q << a.shift;  // original chain position
-    const unsigned long long prow = chain_row0 + (unsigned long long)a.permpos[j - 1] * n;
-    eliminate<T, NMAX>(sl.A(t), sl.Cp(t), Al, Cl, Ar, n, Linv + (size_t)(j - 1) * nn,
-                       Gl + (size_t)(j - 1) * nn, Gr + (size_t)(j - 1) * nn, prow, a.info);
-    live &= ~(1u << t);
-  };
-
-  for (int q = lo + 1; q <= hi; ++q) {
-    const int v = __builtin_ctz((unsigned)q);
-    load_node(sl.A(v), q);
-    load_coupling(sl.Cp(v), q);
-    __syncthreads();
-    for (int t = 0; t < v; ++t) {
-      if (live & (1u << t)) elim_level(t, q - (1 << t), sl.A(v));
+    T* Ar = is_rb ? sl.AR() : sl.A(v);
+    while (todo) {
+      const int t = __builtin_ctz(todo);
+      todo &= todo - 1u;
+      const unsigned above = live & ~((2u << t) - 1u);
+      T* Al = nullptr;
+      T* Cl = nullptr;
+      if (above) {
+        const int u = __builtin_ctz(above);
+        Al = sl.A(u);
+        Cl = sl.Cp(u);
+      } else if (has_left) {
+        Al = sl.AL();
+        Cl = sl.CL();
+      }
+      // position of the live node of level t
+      const int pos = !is_rb ? q - (1 << t) : (rb_is_x ? ((hi >> t) << t) : rb - (1 << t));
+      const int j = pos << a.shift;  // original chain position
+      const unsigned long long prow = chain_row0 + (unsigned long long)a.permpos[j - 1] * n;
+      eliminate<T, NMAX>(sl.A(t), sl.Cp(t), Al, Cl, Ar, n, Linv + (size_t)(j - 1) * nn,
+                         Gl + (size_t)(j - 1) * nn, Gr + (size_t)(j - 1) * nn, prow, a.info);
+      live &= ~(1u << t);
     }
-    live |= (1u << v);
-  }
-  // Right boundary read: eliminate every remaining live level, lowest first.
-  while (live) {
-    const int t = __builtin_ctz(live);
-    // position of the live node of level t: rb - 2^t for a node boundary; for X the
-    // live nodes are the ones whose level-neighbour lies beyond the chain end.
-    const int pos = rb_is_x ? ((hi >> t) << t) : rb - (1 << t);
-    elim_level(t, pos, sl.AR());
+    if (!is_rb) live |= (1u << v);
   }
 
-  if (!FINAL) {
+  if constexpr (!FINAL) {
     const size_t base = (size_t)s * a.stride;
     if (has_left) {
-      lds_store<T, NMAX, NT>(reinterpret_cast<T*>(a.accL_out) + (base + w) * nn, sl.AL(), n);
-      lds_store<T, NMAX, NT>(reinterpret_cast<T*>(a.fill_out) + (base + w) * nn, sl.CL(), n);
+      slot_store<T, NMAX>(reinterpret_cast<T*>(a.accL_out) + (base + w) * nn, sl.AL(), n);
+      slot_store<T, NMAX>(reinterpret_cast<T*>(a.fill_out) + (base + w) * nn, sl.CL(), n);
     }
     if (!rb_is_x) {
-      lds_store<T, NMAX, NT>(reinterpret_cast<T*>(a.accR_out) + (base + w + 1) * nn, sl.AR(), n);
+      slot_store<T, NMAX>(reinterpret_cast<T*>(a.accR_out) + (base + w + 1) * nn, sl.AR(), n);
     } else {
-      lds_store<T, NMAX, NT>(reinterpret_cast<T*>(a.accX) + ((size_t)s * a.npass + a.pass) * nn,
-                             sl.AR(), n);
+      slot_store<T, NMAX>(reinterpret_cast<T*>(a.accX) + ((size_t)s * a.npass + a.pass) * nn,
+                          sl.AR(), n);
     }
     return;
-  }
-
-  // ---- last pass: x_1 step (Algorithm 1, lines 3-5 for the terminal block) ----
-  T* Ax = sl.A(0);
-  T* Cx = sl.Cp(0);
-  lds_load_sym_lower<T, NMAX, NT>(Ax, a.D + ((size_t)s * N + 0) * nn, n);
-  __syncthreads();
-  for (int p = 0; p < a.pass; ++p)
-    lds_load<T, NMAX, NT>(Ax, reinterpret_cast<const T*>(a.accX) + ((size_t)s * a.npass + p) * nn,
-                          n, false, true);
-  __syncthreads();
-  {
+  } else {
+    // ---- last pass: x_1 step (Algorithm 1, lines 3-5 for the terminal block) ----
     constexpr int LD = Lay<NMAX>::LD;
-    for (int e = threadIdx.x; e < n * n; e += NT) {
-      const int r = e / n, c = e - (e / n) * n;
-      Ax[r * LD + c] += sl.AR()[r * LD + c];
+    T* Ax = sl.A(0);
+    T* Cx = sl.Cp(0);
+    const double* D0 = a.D + ((size_t)s * N + 0) * nn;
+#pragma unroll
+    for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
+      const int e = Share<NMAX>::elem(j);
+      if (e < NMAX * NMAX) {
+        const int r = e / NMAX, c = e % NMAX;
+        T v;
+        if (r < n && c < n) {
+          v = static_cast<T>(r >= c ? D0[r * n + c] : D0[c * n + r]);
+          for (int p = 0; p < a.pass; ++p)
+            v += reinterpret_cast<const T*>(a.accX)[((size_t)s * a.npass + p) * nn + r * n + c];
+          v += sl.AR()[r * LD + c];
+        } else {
+          v = (r == c) ? T(1) : T(0);
+        }
+        Ax[r * LD + c] = v;
+      }
     }
-  }
-  __syncthreads();
-  factor_diag<T, NMAX>(Ax, n, chain_row0 + (unsigned long long)a.permpos[N - 1] * n, a.info);
-  lds_store<T, NMAX, NT>(Linv + (size_t)(N - 1) * nn, Ax, n);
-  // F = C L_X^{-T}
-  lds_load<T, NMAX, NT>(Cx, a.C + (size_t)s * nn, n, false);
-  __syncthreads();
-  lds_gemm_nt<T, NMAX, NT>(Cx, Cx, false, Ax, T(1), false, n);
-  lds_store<T, NMAX, NT>(reinterpret_cast<T*>(a.F) + (size_t)s * nn, Cx, n);
-  // U = F F^T in FP64 from the stored F
-  {
-    constexpr int LD = Lay<NMAX>::LD;
+    slot_load<T, NMAX>(Cx, a.C + (size_t)s * nn, n, false);
+    __syncthreads();
+    factor_diag<T, NMAX>(Ax, chain_row0 + (unsigned long long)a.permpos[N - 1] * n, n, a.info);
+    slot_store<T, NMAX>(Linv + (size_t)(N - 1) * nn, Ax, n);
+    // F = C L_X^{-T}
+    typename Mfma<T>::acc_t f = mfma_tile_nt<T, NMAX, false>(Cx, Ax);
+    __syncthreads();
+    mfma_tile_store<T, NMAX, false>(Cx, f, T(1));
+    __syncthreads();
+    slot_store<T, NMAX>(reinterpret_cast<T*>(a.F) + (size_t)s * nn, Cx, n);
+    // U = F F^T in FP64 from the stored F
     double* U = a.U + (size_t)s * nn;
-    for (int e = threadIdx.x; e < n * n; e += NT) {
+    for (int e = threadIdx.x; e < n * n; e += TileCfg<NMAX>::NT) {
       const int r = e / n, c = e - (e / n) * n;
       double acc = 0.0;
       for (int k = 0; k < n; ++k)
@@ -261,17 +385,23 @@ __global__ void __launch_bounds__(256) root_potrf_kernel(const double* __restric
                                                          unsigned long long* info) {
   __shared__ double A[32 * 33];
   constexpr int LD = 33;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int r = e / n, c = e - (e / n) * n;
-    const double rv = (r >= c) ? R[r * n + c] : R[c * n + r];
-    double acc = 0.0;
-    for (int g = 0; g < groups; ++g) acc += part[(size_t)g * n * n + e];
-    A[r * LD + c] = rv - acc;
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int r = e / 32, c = e % 32;
+    double v;
+    if (r < n && c < n) {
+      const double rv = (r >= c) ? R[r * n + c] : R[c * n + r];
+      double acc = 0.0;
+      for (int g = 0; g < groups; ++g) acc += part[(size_t)g * n * n + r * n + c];
+      v = rv - acc;
+    } else {
+      v = (r == c) ? 1.0 : 0.0;  // identity padding
+    }
+    A[r * LD + c] = v;
   }
   __syncthreads();
   if (threadIdx.x < 64) {
-    const int fail = wave_potrf<double, 32>(A, n);
-    if (fail >= 0 && threadIdx.x == 0) atomicMin(info, row_base + fail + 1);
+    const int fail = wave_potrf<double, 32>(A);
+    if (fail >= 0 && fail < n && threadIdx.x == 0) atomicMin(info, row_base + fail + 1);
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -296,8 +426,8 @@ void launch_pass_k(const FactorPassArgs& a, hipStream_t st) {
     attr_set = true;
   }
   const unsigned grid = (unsigned)a.S * (unsigned)a.windows;
-  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX, FIRST, FINAL>), dim3(grid), dim3(NT), lds,
-                     st, a);
+  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX, FIRST, FINAL>), dim3(grid),
+                     dim3(TileCfg<NMAX>::NT), lds, st, a);
 }
 
 template <typename T, int NMAX>
