@@ -181,6 +181,7 @@ struct bmpc_plan_s {
   double* x0 = nullptr;
   double* rbuf = nullptr;
   double* norms = nullptr;  // rnorm, dnorm, xnorm: 3 * nrhs
+  double* npart = nullptr;  // partial maxima: 2 * nrhs * kNormBlocks
   int* flags = nullptr;     // done, iterations
   double* relcorr = nullptr;
   std::vector<void*> allocs;
@@ -469,6 +470,7 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
             dalloc(p, (void**)&p->x0, (size_t)nrhs * n * 8) &&
             dalloc(p, (void**)&p->rbuf, (size_t)nrhs * len * 8) &&
             dalloc(p, (void**)&p->norms, (size_t)3 * nrhs * 8) &&
+            dalloc(p, (void**)&p->npart, (size_t)2 * nrhs * kNormBlocks * 8) &&
             dalloc(p, (void**)&p->flags, 2 * sizeof(int)) &&
             dalloc(p, (void**)&p->relcorr, sizeof(double));
   if (ok && npass > 1) {
@@ -533,10 +535,11 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
   if (!p->factored) return BMPC_ERR_STATE;
   hipStream_t st = p->stream;
   const int nrhs = p->d.nrhs;
+  const size_t len = ((size_t)p->d.S * p->d.N + 1) * p->d.n;
   double* rnorm = p->norms;
   double* dnorm = p->norms + nrhs;
   double* xnorm = p->norms + 2 * nrhs;
-  timed(p, KC_REFINE_MISC, [&] { launch_refine_reset(p->norms, 3 * nrhs, p->flags, 1, st); });
+  timed(p, KC_REFINE_MISC, [&] { launch_refine_reset(p->flags, st); });
   SolveArgs a = solve_args(p, b, x);
   if (p->fp64)
     enqueue_solve<double>(p, a);
@@ -547,6 +550,7 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
   ra.N = p->d.N;
   ra.n = p->d.n;
   ra.nrhs = nrhs;
+  ra.chunk = 16;
   ra.D = D;
   ra.E = E;
   ra.C = C;
@@ -555,23 +559,26 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
   ra.x = x;
   ra.r = p->rbuf;
   ra.w = p->w;
-  ra.rnorm = rnorm;
   ra.done = p->flags;
+  // correction solve: reads r / |r|, adds |r| d to x and keeps |r| d in place of r
   SolveArgs c = solve_args(p, p->rbuf, x);
   c.rnorm = rnorm;
-  c.dnorm = dnorm;
-  c.xnorm = xnorm;
+  c.dstore = p->rbuf;
   c.done = p->flags;
   c.accumulate = 1;
   for (int it = 0; it < max_iters; ++it) {
-    timed(p, KC_REFINE_MISC,
-          [&] { launch_refine_reset(p->norms, 3 * nrhs, p->flags, 0, st); });
     timed(p, KC_RESIDUAL, [&] { launch_residual(ra, p->nmax, st); });
     timed(p, KC_RESIDUAL_ROOT, [&] { launch_residual_root(ra, st); });
+    timed(p, KC_REFINE_MISC, [&] {
+      launch_maxabs(p->rbuf, nullptr, nrhs, len, p->npart, rnorm, nullptr, p->flags, st);
+    });
     if (p->fp64)
       enqueue_solve<double>(p, c);
     else
       enqueue_solve<float>(p, c);
+    timed(p, KC_REFINE_MISC, [&] {
+      launch_maxabs(p->rbuf, x, nrhs, len, p->npart, dnorm, xnorm, p->flags, st);
+    });
     timed(p, KC_REFINE_MISC, [&] {
       launch_refine_check(dnorm, xnorm, nrhs, tol, p->flags, p->relcorr, st);
     });

@@ -89,14 +89,14 @@ struct SolveArgs {
   double* w;             // [S][nrhs][n] FP64 products F_s y_X
   double* x0;            // [nrhs][n]
   const double* rnorm;   // refinement: input scale 1/rnorm, output x += rnorm * d
-  double* dnorm;         // refinement: max |rnorm * d| per rhs
-  double* xnorm;         // refinement: max |x| per rhs after the update
+  double* dstore;        // refinement: rnorm * d stored here ([nrhs][len], may alias b)
   const int* done;       // refinement stop flag (null outside refinement)
   int accumulate;        // 0: x = d ; 1: x += rnorm * d (refinement update)
 };
 
 struct ResidualArgs {
   int S, N, n, nrhs;
+  int chunk;             // stages per work item of the tail residual
   const double* D;
   const double* E;
   const double* C;
@@ -105,7 +105,6 @@ struct ResidualArgs {
   const double* x;
   double* r;             // [nrhs][len]
   double* w;             // [S][nrhs][n] products C_s x_{s,0}
-  double* rnorm;         // [nrhs] max |r|
   const int* done;
 };
 
@@ -131,17 +130,21 @@ void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t
 
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st);
 void launch_residual_root(const ResidualArgs& a, hipStream_t st);
-void launch_refine_reset(double* norms, int count, int* flags, int reset_iters,
-                         hipStream_t st);
+void launch_refine_reset(int* flags, hipStream_t st);
+// out[q] = max_i |v[q][i]| (and, if v2, out2[q] = max |v2[q][i]|), two stages through
+// partial[2][nrhs][kNormBlocks]; skipped when *done is set.
+constexpr int kNormBlocks = 256;
+void launch_maxabs(const double* v, const double* v2, int nrhs, size_t len, double* partial,
+                   double* out, double* out2, const int* done, hipStream_t st);
 void launch_refine_check(const double* dnorm, const double* xnorm, int nrhs,
                          double tol, int* flags, double* relcorr, hipStream_t st);
 
 // number of chain positions eliminated at level l (1-based) of a chain of length m
-inline int level_count(int m, int l) {
+__host__ __device__ inline int level_count(int m, int l) {
   int ml = m >> (l - 1);
   return (ml + 1) >> 1;
 }
-inline int chain_levels(int m) {
+__host__ __device__ inline int chain_levels(int m) {
   int L = 0;
   while ((m >> L) > 0) ++L;
   return L;  // floor(log2 m) + 1 for m >= 1, 0 for m = 0

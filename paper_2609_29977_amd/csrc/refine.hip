@@ -4,10 +4,13 @@
 // eq. (root_coupled_matrix) / eq. (tail_block_tridiagonal): row block (s,k) of a
 // tail is D_{s,k} x_{s,k} + E_{s,k-1} x_{s,k-1} + E_{s,k}^T x_{s,k+1} (+ C_s^T x_0
 // for k = 0); the root row block is R x_0 + sum_s C_s x_{s,0}, with the sum over s
-// taken in scenario order.  The infinity norms needed by the refinement loop are
-// maxima, which are order independent, so device atomics keep them deterministic.
+// taken in scenario order.  One wave walks a chunk of consecutive stages of one tail,
+// so each E block is fetched from HBM once and used for both rows it touches; the
+// blocks of the next stage are loaded while the current one is applied.  Infinity
+// norms are maxima taken by a two-stage reduction (per-block partial maxima, then
+// one block), so they are deterministic and need no atomics.
 #include "bmpc_internal.h"
-#include "blockops.h"
+#include "regblock.h"
 
 namespace bmpc {
 
@@ -15,93 +18,118 @@ namespace {
 
 constexpr int NT = 64;
 
-__device__ inline double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-
-__device__ inline void atomic_max_nonneg(double* addr, double v) {
-  atomicMax(reinterpret_cast<unsigned long long*>(addr),
-            static_cast<unsigned long long>(__double_as_longlong(v)));
+// Register block of a symmetric matrix stored by its lower triangle, normal mapping:
+// lane holds row o, columns base..base+EPL of sym(D).
+template <int NMAX>
+__device__ inline void load_sym(RegBlock<double, NMAX>& rb, const double* __restrict__ g, int n) {
+  typedef RegBlock<double, NMAX> RB;
+  const int o = RB::out_index(), b = RB::base();
+#pragma unroll
+  for (int e = 0; e < RB::EPL; ++e) {
+    const int c = b + e;
+    rb.v[e] = (o < n && c < n) ? (c <= o ? g[o * n + c] : g[c * n + o]) : 0.0;
+  }
 }
 
 template <int NMAX>
-struct ResSmem {
-  double blk[Lay<NMAX>::SZ];
-  double xv[3][kMaxRhs][NMAX];  // x_{k-1}, x_k, x_{k+1}
-  double acc[kMaxRhs][NMAX];
+struct StageBlocks {
+  RegBlock<double, NMAX> d, en, et;  // D_k (sym), E_k (normal), E_k (transposed)
+  __device__ void load(const ResidualArgs& a, int s, int k) {
+    const int n = a.n, N = a.N;
+    const size_t nn = (size_t)n * n;
+    load_sym<NMAX>(d, a.D + ((size_t)s * N + k) * nn, n);
+    if (k + 1 < N) {
+      const double* E = a.E + ((size_t)s * (N - 1) + k) * nn;
+      en.template load<false>(E, n);
+      et.template load<true>(E, n);
+    }
+  }
 };
 
-// acc[q][row] -= op(B) xin[q]; B is a global n x n FP64 block (sym: lower triangle)
 template <int NMAX>
-__device__ inline void sub_block_product(ResSmem<NMAX>& sm, const double* __restrict__ B,
-                                         int mode, double (*xin)[NMAX], int n, int nrhs) {
-  constexpr int LD = Lay<NMAX>::LD;
-  // mode 0: B (general), 1: B^T, 2: symmetric from lower triangle
-  if (mode == 2)
-    lds_load_sym_lower<double, NMAX, NT>(sm.blk, B, n);
-  else
-    lds_load<double, NMAX, NT>(sm.blk, B, n, false);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-    const int q = idx / n, row = idx - (idx / n) * n;
-    double t = 0.0;
-    if (mode == 1) {
-      for (int k = 0; k < n; ++k) t += sm.blk[k * LD + row] * xin[q][k];
-    } else {
-      for (int k = 0; k < n; ++k) t += sm.blk[row * LD + k] * xin[q][k];
-    }
-    sm.acc[q][row] -= t;
-  }
-  __syncthreads();
-}
-
-template <int NMAX>
-__global__ void __launch_bounds__(NT) residual_kernel(ResidualArgs a) {
+__global__ void __launch_bounds__(NT) residual_kernel(ResidualArgs a, int chunks) {
   if (a.done && *a.done) return;
-  __shared__ ResSmem<NMAX> sm;
+  typedef RegBlock<double, NMAX> RB;
+  __shared__ double xs[3][kMaxRhs][NMAX];  // x_{k-1}, x_k, x_{k+1} (rotating)
+  __shared__ double x0s[kMaxRhs][NMAX];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
   const size_t nn = (size_t)n * n;
   const size_t len = ((size_t)S * N + 1) * n;
-  const int s = blockIdx.x / N;
-  const int k = blockIdx.x - s * N;
-  const size_t off = ((size_t)s * N + k) * n;
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-    const int q = idx / n, i = idx - (idx / n) * n;
-    sm.acc[q][i] = a.b[(size_t)q * len + off + i];
-    sm.xv[1][q][i] = a.x[(size_t)q * len + off + i];
-    if (k >= 1) sm.xv[0][q][i] = a.x[(size_t)q * len + off - n + i];
-    if (k + 1 < N) sm.xv[2][q][i] = a.x[(size_t)q * len + off + n + i];
-    if (k == 0) sm.xv[0][q][i] = a.x[(size_t)q * len + (size_t)S * N * n + i];  // x_0
-  }
-  sub_block_product<NMAX>(sm, a.D + ((size_t)s * N + k) * nn, 2, sm.xv[1], n, nrhs);
-  if (k >= 1)
-    sub_block_product<NMAX>(sm, a.E + ((size_t)s * (N - 1) + (k - 1)) * nn, 0, sm.xv[0], n,
-                            nrhs);
-  if (k + 1 < N)
-    sub_block_product<NMAX>(sm, a.E + ((size_t)s * (N - 1) + k) * nn, 1, sm.xv[2], n, nrhs);
-  if (k == 0) {
-    sub_block_product<NMAX>(sm, a.C + (size_t)s * nn, 1, sm.xv[0], n, nrhs);
-    // w_s = C_s x_{s,0} for the root row
-    constexpr int LD = Lay<NMAX>::LD;
-    lds_load<double, NMAX, NT>(sm.blk, a.C + (size_t)s * nn, n, false);
+  const int s = blockIdx.x / chunks;
+  const int ch = blockIdx.x - s * chunks;
+  const int k0 = ch * a.chunk, k1 = min(N, k0 + a.chunk);
+  const int o = RB::out_index(), b = RB::base();
+
+  auto load_x = [&](double (*dst)[NMAX], int k) {
+    for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
+      const int q = idx / NMAX, i = idx % NMAX;
+      dst[q][i] = (k >= 0 && k < N && i < n) ? a.x[(size_t)q * len + ((size_t)s * N + k) * n + i]
+                                             : 0.0;
+    }
+  };
+  int ip = 0, ic = 1, in = 2;  // rotating indices of x_{k-1}, x_k, x_{k+1}
+  load_x(xs[ip], k0 - 1);
+  load_x(xs[ic], k0);
+  if (k0 == 0)
+    for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
+      const int q = idx / NMAX, i = idx % NMAX;
+      x0s[q][i] = i < n ? a.x[(size_t)q * len + (size_t)S * N * n + i] : 0.0;
+    }
+  // carry: E_{k0-1} x_{k0-1}, partial sums for row k0
+  double carry[kMaxRhs];
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) carry[q] = 0.0;
+  StageBlocks<NMAX> cur;
+  cur.load(a, s, k0);
+  if (k0 > 0) {
+    RB ep;
+    ep.template load<false>(a.E + ((size_t)s * (N - 1) + (k0 - 1)) * nn, n);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-      const int q = idx / n, row = idx - (idx / n) * n;
-      double t = 0.0;
-      for (int c = 0; c < n; ++c) t += sm.blk[row * LD + c] * sm.xv[1][q][c];
-      a.w[((size_t)s * nrhs + q) * n + row] = t;
-    }
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q)
+      if (q < nrhs) carry[q] = ep.dot(xs[ip][q]);
   }
-  for (int q = 0; q < nrhs; ++q) {
-    double mx = 0.0;
-    for (int i = threadIdx.x; i < n; i += NT) {
-      const double v = sm.acc[q][i];
-      a.r[(size_t)q * len + off + i] = v;
-      mx = fmax(mx, fabs(v));
+  for (int k = k0; k < k1; ++k) {
+    load_x(xs[in], k + 1);
+    StageBlocks<NMAX> nxt;
+    if (k + 1 < k1) nxt.load(a, s, k + 1);
+    __syncthreads();
+    const size_t off = ((size_t)s * N + k) * n;
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) {
+      if (q < nrhs) {
+        double p = cur.d.dot(xs[ic][q]) + carry[q];
+        if (k + 1 < N) {
+          p += cur.et.dot(xs[in][q]);
+          carry[q] = cur.en.dot(xs[ic][q]);
+        }
+        p = lane_group_sum<RB::LPR>(p);
+        if (b == 0 && o < n) a.r[(size_t)q * len + off + o] = a.b[(size_t)q * len + off + o] - p;
+      }
     }
-    mx = wave_max(mx);
-    if (threadIdx.x == 0) atomic_max_nonneg(&a.rnorm[q], mx);
+    if (k == 0) {
+      // C_s^T x_0 enters row 0; w_s = C_s x_{s,0} feeds the root row
+      RB ct, cn;
+      ct.template load<true>(a.C + (size_t)s * nn, n);
+      cn.template load<false>(a.C + (size_t)s * nn, n);
+#pragma unroll
+      for (int q = 0; q < kMaxRhs; ++q) {
+        if (q < nrhs) {
+          const double pc = lane_group_sum<RB::LPR>(ct.dot(x0s[q]));
+          const double pw = lane_group_sum<RB::LPR>(cn.dot(xs[ic][q]));
+          if (b == 0 && o < n) {
+            a.r[(size_t)q * len + off + o] -= pc;
+            a.w[((size_t)s * nrhs + q) * n + o] = pw;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    cur = nxt;
+    const int t = ip;
+    ip = ic;
+    ic = in;
+    in = t;
   }
 }
 
@@ -119,7 +147,6 @@ __global__ void __launch_bounds__(256) residual_root_kernel(ResidualArgs a) {
       for (int s = g; s < S; s += tpe) acc += a.w[((size_t)s * nrhs + q) * n + i];
     part[threadIdx.x] = acc;
     __syncthreads();
-    double mx = 0.0;
     if (threadIdx.x < n) {
       const int row = threadIdx.x;
       double sum = 0.0;
@@ -129,29 +156,63 @@ __global__ void __launch_bounds__(256) residual_root_kernel(ResidualArgs a) {
         const double rv = (row >= c) ? a.R[row * n + c] : a.R[c * n + row];
         rx += rv * a.x[(size_t)q * len + root + c];
       }
-      const double v = a.b[(size_t)q * len + root + row] - rx - sum;
-      a.r[(size_t)q * len + root + row] = v;
-      mx = fabs(v);
-    }
-    if (threadIdx.x < 64) {
-      mx = wave_max(mx);
-      if (threadIdx.x == 0) atomic_max_nonneg(&a.rnorm[q], mx);
+      a.r[(size_t)q * len + root + row] = a.b[(size_t)q * len + root + row] - rx - sum;
     }
     __syncthreads();
   }
 }
 
-// flags[0] = done, flags[1] = corrections applied
-__global__ void refine_reset_kernel(double* norms, int count, int* flags, int reset_iters) {
-  if (reset_iters) {
-    if (threadIdx.x == 0) {
-      flags[0] = 0;
-      flags[1] = 0;
+__device__ inline double block_max(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[wv] = v;
+  __syncthreads();
+  double m = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, sh[i]);
+  __syncthreads();
+  return m;
+}
+
+// partial[t][q][blk] = max over this block's slice of |v_t[q][.]| (t = 0: v, 1: v2)
+__global__ void __launch_bounds__(256) maxabs_partial_kernel(const double* v, const double* v2,
+                                                             int nrhs, size_t len,
+                                                             double* partial, const int* done) {
+  if (done && *done) return;
+  __shared__ double sh[4];
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (int t = 0; t < (v2 ? 2 : 1); ++t) {
+    const double* src = t == 0 ? v : v2;
+    for (int q = 0; q < nrhs; ++q) {
+      double mx = 0.0;
+      for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+        mx = fmax(mx, fabs(src[(size_t)q * len + i]));
+      mx = block_max(mx, sh);
+      if (threadIdx.x == 0) partial[((size_t)t * nrhs + q) * gridDim.x + blockIdx.x] = mx;
     }
-    return;
   }
-  if (flags[0]) return;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) norms[i] = 0.0;
+}
+
+__global__ void __launch_bounds__(64) maxabs_final_kernel(const double* partial, int blocks,
+                                                          int nrhs, int two, double* out,
+                                                          double* out2, const int* done) {
+  if (done && *done) return;
+  for (int t = 0; t < two; ++t)
+    for (int q = 0; q < nrhs; ++q) {
+      double mx = 0.0;
+      for (int i = threadIdx.x; i < blocks; i += 64)
+        mx = fmax(mx, partial[((size_t)t * nrhs + q) * blocks + i]);
+      for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+      if (threadIdx.x == 0) (t == 0 ? out : out2)[q] = mx;
+    }
+}
+
+// flags[0] = done, flags[1] = corrections applied
+__global__ void refine_reset_kernel(int* flags) {
+  if (threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[1] = 0;
+  }
 }
 
 __global__ void refine_check_kernel(const double* dnorm, const double* xnorm, int nrhs,
@@ -172,23 +233,30 @@ __global__ void refine_check_kernel(const double* dnorm, const double* xnorm, in
 }  // namespace
 
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
-  const dim3 grid((unsigned)a.S * (unsigned)a.N);
+  const int chunks = (a.N + a.chunk - 1) / a.chunk;
+  const dim3 grid((unsigned)a.S * (unsigned)chunks);
   if (nmax <= 8)
-    hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(NT), 0, st, a, chunks);
   else if (nmax <= 16)
-    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(NT), 0, st, a, chunks);
   else
-    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(NT), 0, st, a, chunks);
 }
 
 void launch_residual_root(const ResidualArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(residual_root_kernel, dim3(1), dim3(256), 0, st, a);
 }
 
-void launch_refine_reset(double* norms, int count, int* flags, int reset_iters,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(refine_reset_kernel, dim3(1), dim3(64), 0, st, norms, count, flags,
-                     reset_iters);
+void launch_maxabs(const double* v, const double* v2, int nrhs, size_t len, double* partial,
+                   double* out, double* out2, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(maxabs_partial_kernel, dim3(kNormBlocks), dim3(256), 0, st, v, v2, nrhs,
+                     len, partial, done);
+  hipLaunchKernelGGL(maxabs_final_kernel, dim3(1), dim3(64), 0, st, partial, kNormBlocks, nrhs,
+                     v2 ? 2 : 1, out, out2, done);
+}
+
+void launch_refine_reset(int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(refine_reset_kernel, dim3(1), dim3(64), 0, st, flags);
 }
 
 void launch_refine_check(const double* dnorm, const double* xnorm, int nrhs, double tol,

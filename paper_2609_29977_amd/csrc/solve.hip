@@ -10,8 +10,13 @@
 // levels in reverse; position j reads the already known x of its two neighbours.
 // The permutation Pi_i (Algorithm 2, lines 2 and 11) is applied as an index map:
 // chain position j reads and writes stage N-j of the natural-order vectors.
+//
+// One wave per position.  Factor blocks are held in registers (RegBlock) and the next
+// block is loaded while the current one is applied; the neighbour vectors go through
+// a double-buffered LDS array so that their loads also overlap the products.
 #include "bmpc_internal.h"
 #include "blockops.h"
+#include "regblock.h"
 
 namespace bmpc {
 
@@ -19,109 +24,129 @@ namespace {
 
 constexpr int NT = kSolveThreads;
 
-template <typename T, int NMAX>
-struct SolveSmem {
-  T M[Lay<NMAX>::SZ];
-  T v[kMaxRhs][NMAX];
-  T r[kMaxRhs][NMAX];
-};
-
-__device__ inline double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-
-__device__ inline void atomic_max_nonneg(double* addr, double v) {
-  atomicMax(reinterpret_cast<unsigned long long*>(addr),
-            static_cast<unsigned long long>(__double_as_longlong(v)));
-}
-
-// out[q][row] (+)= alpha * op(M) vin[q] with M an n x n block in global memory.
-template <typename T, int NMAX>
-__device__ inline void gemv(SolveSmem<T, NMAX>& sm, const T* __restrict__ gM, bool trans,
-                            T (*vin)[NMAX], T (*out)[NMAX], T alpha, bool accumulate, int n,
-                            int nrhs) {
-  constexpr int LD = Lay<NMAX>::LD;
-  lds_load<T, NMAX, NT>(sm.M, gM, n, false);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-    const int q = idx / n, row = idx - (idx / n) * n;
-    T acc = T(0);
-    if (trans) {
-      for (int k = 0; k < n; ++k) acc += sm.M[k * LD + row] * vin[q][k];
-    } else {
-      for (int k = 0; k < n; ++k) acc += sm.M[row * LD + k] * vin[q][k];
-    }
-    out[q][row] = accumulate ? out[q][row] + alpha * acc : alpha * acc;
-  }
-  __syncthreads();
-}
-
-template <typename T, int NMAX>
-__device__ inline void load_vec(T (*dst)[NMAX], const T* __restrict__ src, int n, int nrhs) {
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-    const int q = idx / n, i = idx - (idx / n) * n;
-    dst[q][i] = src[idx];
-  }
-}
-
-template <typename T, int NMAX>
-__device__ inline void store_vec(T* __restrict__ dst, T (*src)[NMAX], int n, int nrhs) {
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-    const int q = idx / n, i = idx - (idx / n) * n;
-    dst[idx] = src[q][i];
-  }
-}
-
-// r[q] = scale_q * b[q][off .. off+n)
+// Gathered right-hand side of a position: dst[q][i] = scale_q * b[q][off + i], zero
+// padded to NMAX.
 template <typename T, int NMAX>
 __device__ inline void gather_rhs(const SolveArgs& a, T (*dst)[NMAX], size_t off) {
   const size_t len = ((size_t)a.S * a.N + 1) * a.n;
-  for (int idx = threadIdx.x; idx < a.n * a.nrhs; idx += NT) {
-    const int q = idx / a.n, i = idx - (idx / a.n) * a.n;
-    double v = a.b[(size_t)q * len + off + i];
-    if (a.rnorm) {
-      const double rn = a.rnorm[q];
-      v = rn > 0.0 ? v / rn : 0.0;
+  for (int idx = threadIdx.x; idx < a.nrhs * NMAX; idx += NT) {
+    const int q = idx / NMAX, i = idx % NMAX;
+    T v = T(0);
+    if (i < a.n) {
+      double bv = a.b[(size_t)q * len + off + i];
+      if (a.rnorm) {
+        const double rn = a.rnorm[q];
+        bv = rn > 0.0 ? bv / rn : 0.0;
+      }
+      v = static_cast<T>(bv);
     }
-    dst[q][i] = static_cast<T>(v);
+    dst[q][i] = v;
+  }
+}
+
+// Per-lane staging of one neighbour vector (nrhs x n values, zero padded).
+template <typename T, int NMAX>
+struct VecStage {
+  static constexpr int PER = (kMaxRhs * NMAX + NT - 1) / NT;
+  T v[PER];
+  __device__ void load(const T* __restrict__ src, int n, int nrhs) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = threadIdx.x + k * NT;
+      const int q = idx / NMAX, i = idx % NMAX;
+      v[k] = (q < nrhs && i < n) ? src[q * n + i] : T(0);
+    }
+  }
+  __device__ void store(T (*dst)[NMAX], int nrhs) const {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = threadIdx.x + k * NT;
+      const int q = idx / NMAX;
+      if (q < nrhs) dst[q][idx % NMAX] = v[k];
+    }
+  }
+};
+
+// Accumulate sum_p op(M_p) v_p over a list of pulls with a two-deep pipeline.
+// pull(p, &blk, &vec) returns false when pull p does not exist.
+template <typename T, int NMAX, bool TRANS, typename PullFn>
+__device__ inline void pull_products(int npull, PullFn pull, int n, int nrhs,
+                                     T (*vbuf)[kMaxRhs][NMAX], T* part) {
+  typedef RegBlock<T, NMAX> RB;
+  const T* blk = nullptr;
+  const T* vec = nullptr;
+  int p = 0;
+  while (p < npull && !pull(p, blk, vec)) ++p;
+  if (p >= npull) return;
+  RB cur;
+  cur.template load<TRANS>(blk, n);
+  {
+    VecStage<T, NMAX> vs;
+    vs.load(vec, n, nrhs);
+    vs.store(vbuf[0], nrhs);
+  }
+  __syncthreads();
+  int buf = 0;
+  while (p < npull) {
+    int pn = p + 1;
+    const T* nblk = nullptr;
+    const T* nvec = nullptr;
+    while (pn < npull && !pull(pn, nblk, nvec)) ++pn;
+    RB nxt;
+    VecStage<T, NMAX> vs;
+    if (pn < npull) {
+      nxt.template load<TRANS>(nblk, n);
+      vs.load(nvec, n, nrhs);
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q)
+      if (q < nrhs) part[q] += cur.dot(vbuf[buf][q]);
+    if (pn < npull) vs.store(vbuf[buf ^ 1], nrhs);
+    __syncthreads();
+    cur = nxt;
+    buf ^= 1;
+    p = pn;
+  }
+}
+
+// dst[q][o] -= (reduced partial sums); lanes of one output index share a sum.
+template <typename T, int NMAX>
+__device__ inline void subtract_reduced(T (*dst)[NMAX], const T* part, int nrhs) {
+  typedef RegBlock<T, NMAX> RB;
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nrhs) {
+      const T s = lane_group_sum<RB::LPR>(part[q]);
+      if (RB::base() == 0) dst[q][RB::out_index()] -= s;
+    }
   }
 }
 
 template <typename T, int NMAX>
-__device__ inline void scatter_x(const SolveArgs& a, T (*src)[NMAX], size_t off) {
+struct SolveSmem {
+  T vbuf[2][kMaxRhs][NMAX];
+  T rhs[kMaxRhs][NMAX];
+};
+
+// x[q][off + o] = d  or  x += rnorm_q * d with rnorm_q * d kept in dstore.
+__device__ inline void scatter_value(const SolveArgs& a, int q, size_t off, double d) {
   const size_t len = ((size_t)a.S * a.N + 1) * a.n;
-  for (int q = 0; q < a.nrhs; ++q) {
-    double dmax = 0.0, xmax = 0.0;
-    for (int i = threadIdx.x; i < a.n; i += NT) {
-      const size_t idx = (size_t)q * len + off + i;
-      const double d = static_cast<double>(src[q][i]);
-      if (a.accumulate) {
-        const double dd = a.rnorm[q] * d;
-        const double xn = a.x[idx] + dd;
-        a.x[idx] = xn;
-        dmax = fmax(dmax, fabs(dd));
-        xmax = fmax(xmax, fabs(xn));
-      } else {
-        a.x[idx] = d;
-      }
-    }
-    if (a.accumulate) {
-      dmax = wave_max(dmax);
-      xmax = wave_max(xmax);
-      if (threadIdx.x == 0) {
-        atomic_max_nonneg(&a.dnorm[q], dmax);
-        atomic_max_nonneg(&a.xnorm[q], xmax);
-      }
-    }
+  const size_t idx = (size_t)q * len + off;
+  if (a.accumulate) {
+    const double dd = a.rnorm[q] * d;
+    a.x[idx] += dd;
+    a.dstore[idx] = dd;
+  } else {
+    a.x[idx] = d;
   }
 }
 
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(NT) solve_fwd_level_kernel(SolveArgs a, int level, int count) {
   if (a.done && *a.done) return;
+  typedef RegBlock<T, NMAX> RB;
   __shared__ SolveSmem<T, NMAX> sm;
-  const int n = a.n, N = a.N, nrhs = a.nrhs;
+  const int n = a.n, N = a.N, nrhs = a.nrhs, m = a.m;
   const size_t nn = (size_t)n * n;
   const int s = blockIdx.x / count;
   const int i = blockIdx.x - s * count;
@@ -132,26 +157,39 @@ __global__ void __launch_bounds__(NT) solve_fwd_level_kernel(SolveArgs a, int le
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
 
-  gather_rhs<T, NMAX>(a, sm.r, ((size_t)s * N + (N - j)) * n);
-  for (int t = 0; t + 1 < level; ++t) {
-    const int cl = j - (1 << t);  // its right neighbour at level t+1 is j
-    __syncthreads();
-    load_vec<T, NMAX>(sm.v, y + (size_t)(cl - 1) * nrhs * n, n, nrhs);
-    gemv<T, NMAX>(sm, Gr + (size_t)(cl - 1) * nn, false, sm.v, sm.r, T(-1), true, n, nrhs);
-    const int cr = j + (1 << t);  // its left neighbour at level t+1 is j
-    if (cr <= a.m) {
-      load_vec<T, NMAX>(sm.v, y + (size_t)(cr - 1) * nrhs * n, n, nrhs);
-      gemv<T, NMAX>(sm, Gl + (size_t)(cr - 1) * nn, false, sm.v, sm.r, T(-1), true, n, nrhs);
+  RB lin;
+  lin.template load<false>(Linv + (size_t)(j - 1) * nn, n);
+  gather_rhs<T, NMAX>(a, sm.rhs, ((size_t)s * N + (N - j)) * n);
+  T part[kMaxRhs];
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) part[q] = T(0);
+  // pull 2t: left neighbour j-2^t (row j holds its G_r); 2t+1: right j+2^t (its G_l)
+  auto pull = [&](int p, const T*& blk, const T*& vec) -> bool {
+    const int t = p >> 1;
+    const int c = (p & 1) ? j + (1 << t) : j - (1 << t);
+    if (c > m) return false;
+    blk = ((p & 1) ? Gl : Gr) + (size_t)(c - 1) * nn;
+    vec = y + (size_t)(c - 1) * nrhs * n;
+    return true;
+  };
+  pull_products<T, NMAX, false>(2 * (level - 1), pull, n, nrhs, sm.vbuf, part);
+  __syncthreads();
+  subtract_reduced<T, NMAX>(sm.rhs, part, nrhs);
+  __syncthreads();
+  T* yj = y + (size_t)(j - 1) * nrhs * n;
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nrhs) {
+      const T v = lane_group_sum<RB::LPR>(lin.dot(sm.rhs[q]));
+      if (RB::base() == 0 && RB::out_index() < n) yj[q * n + RB::out_index()] = v;
     }
   }
-  __syncthreads();
-  gemv<T, NMAX>(sm, Linv + (size_t)(j - 1) * nn, false, sm.r, sm.v, T(1), false, n, nrhs);
-  store_vec<T, NMAX>(y + (size_t)(j - 1) * nrhs * n, sm.v, n, nrhs);
 }
 
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   if (a.done && *a.done) return;
+  typedef RegBlock<T, NMAX> RB;
   __shared__ SolveSmem<T, NMAX> sm;
   const int n = a.n, N = a.N, nrhs = a.nrhs, m = a.m;
   const size_t nn = (size_t)n * n;
@@ -161,29 +199,49 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
 
-  gather_rhs<T, NMAX>(a, sm.r, ((size_t)s * N + 0) * n);
+  RB lin, fb;
+  lin.template load<false>(Linv + (size_t)(N - 1) * nn, n);
+  fb.template load<false>(reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n);
+  gather_rhs<T, NMAX>(a, sm.rhs, ((size_t)s * N + 0) * n);
+  T part[kMaxRhs];
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) part[q] = T(0);
   // The last position of level t+1 has X as its right neighbour iff floor(m/2^t) is odd.
-  for (int t = 0; (m >> t) > 0; ++t) {
-    if ((m >> t) & 1) {
-      const int c = (m >> t) << t;
-      __syncthreads();
-      load_vec<T, NMAX>(sm.v, y + (size_t)(c - 1) * nrhs * n, n, nrhs);
-      gemv<T, NMAX>(sm, Gr + (size_t)(c - 1) * nn, false, sm.v, sm.r, T(-1), true, n, nrhs);
+  auto pull = [&](int t, const T*& blk, const T*& vec) -> bool {
+    if (((m >> t) & 1) == 0) return false;
+    const int c = (m >> t) << t;
+    blk = Gr + (size_t)(c - 1) * nn;
+    vec = y + (size_t)(c - 1) * nrhs * n;
+    return true;
+  };
+  pull_products<T, NMAX, false>(chain_levels(m), pull, n, nrhs, sm.vbuf, part);
+  __syncthreads();
+  subtract_reduced<T, NMAX>(sm.rhs, part, nrhs);
+  __syncthreads();
+  T* yx = y + (size_t)(N - 1) * nrhs * n;
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nrhs) {
+      const T v = lane_group_sum<RB::LPR>(lin.dot(sm.rhs[q]));
+      if (RB::base() == 0 && RB::out_index() < n) {
+        yx[q * n + RB::out_index()] = v;
+        sm.vbuf[0][q][RB::out_index()] = v;
+      }
     }
   }
   __syncthreads();
-  gemv<T, NMAX>(sm, Linv + (size_t)(N - 1) * nn, false, sm.r, sm.v, T(1), false, n, nrhs);
-  store_vec<T, NMAX>(y + (size_t)(N - 1) * nrhs * n, sm.v, n, nrhs);
   // w_s = F_s y_X in FP64 (root reduction input, Algorithm 2 line 5)
-  constexpr int LD = Lay<NMAX>::LD;
-  lds_load<T, NMAX, NT>(sm.M, reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n, false);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-    const int q = idx / n, row = idx - (idx / n) * n;
-    double acc = 0.0;
-    for (int k = 0; k < n; ++k)
-      acc += static_cast<double>(sm.M[row * LD + k]) * static_cast<double>(sm.v[q][k]);
-    a.w[((size_t)s * nrhs + q) * n + row] = acc;
+  const int b = RB::base(), o = RB::out_index();
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nrhs) {
+      double p = 0.0;
+#pragma unroll
+      for (int e = 0; e < RB::EPL; ++e)
+        p += static_cast<double>(fb.v[e]) * static_cast<double>(sm.vbuf[0][q][b + e]);
+      p = lane_group_sum<RB::LPR>(p);
+      if (b == 0 && o < n) a.w[((size_t)s * nrhs + q) * n + o] = p;
+    }
   }
 }
 
@@ -197,7 +255,7 @@ __global__ void __launch_bounds__(256) solve_root_kernel(SolveArgs a) {
   const size_t root_off = (size_t)S * a.N * n;
   // sum_s w_s for every (q, i): 8 thread groups over scenario slices, then a fixed
   // combination order.
-  const int tpe = 256 / 32;  // threads per element slot
+  const int tpe = 256 / 32;
   for (int q = 0; q < nrhs; ++q) {
     const int i = threadIdx.x / tpe, g = threadIdx.x - (threadIdx.x / tpe) * tpe;
     double acc = 0.0;
@@ -236,63 +294,60 @@ __global__ void __launch_bounds__(256) solve_root_kernel(SolveArgs a) {
   for (int idx = threadIdx.x; idx < n * nrhs; idx += 256) {
     const int q = idx / n, i = idx - (idx / n) * n;
     a.x0[idx] = r0[q][i];
-  }
-  for (int q = 0; q < nrhs; ++q) {
-    double dmax = 0.0, xmax = 0.0;
-    if (threadIdx.x < n) {
-      const size_t idx = (size_t)q * len + root_off + threadIdx.x;
-      const double d = r0[q][threadIdx.x];
-      if (a.accumulate) {
-        const double dd = a.rnorm[q] * d;
-        const double xn = a.x[idx] + dd;
-        a.x[idx] = xn;
-        dmax = fabs(dd);
-        xmax = fabs(xn);
-      } else {
-        a.x[idx] = d;
-      }
-    }
-    if (a.accumulate && threadIdx.x < 64) {
-      dmax = wave_max(dmax);
-      xmax = wave_max(xmax);
-      if (threadIdx.x == 0) {
-        atomic_max_nonneg(&a.dnorm[q], dmax);
-        atomic_max_nonneg(&a.xnorm[q], xmax);
-      }
-    }
+    scatter_value(a, q, root_off + i, r0[q][i]);
   }
 }
 
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
   if (a.done && *a.done) return;
+  typedef RegBlock<T, NMAX> RB;
   __shared__ SolveSmem<T, NMAX> sm;
-  constexpr int LD = Lay<NMAX>::LD;
+  __shared__ double x0s[kMaxRhs][NMAX];
   const int n = a.n, N = a.N, nrhs = a.nrhs;
   const size_t nn = (size_t)n * n;
   const int s = blockIdx.x;
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
-  T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
-  // dy_X -= F^T x_0 (root propagation, Algorithm 2 line 9), product in FP64
-  lds_load<T, NMAX, NT>(sm.M, reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n, false);
-  load_vec<T, NMAX>(sm.r, y + (size_t)(N - 1) * nrhs * n, n, nrhs);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += NT) {
-    const int q = idx / n, row = idx - (idx / n) * n;
-    double acc = 0.0;
-    for (int k = 0; k < n; ++k)
-      acc += static_cast<double>(sm.M[k * LD + row]) * a.x0[q * n + k];
-    sm.v[q][row] = static_cast<T>(static_cast<double>(sm.r[q][row]) - acc);
+  T* yx = reinterpret_cast<T*>(a.y) + ((size_t)s * N + (N - 1)) * nrhs * n;
+  RB lin, fb;
+  lin.template load<true>(Linv + (size_t)(N - 1) * nn, n);
+  fb.template load<true>(reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n);
+  for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
+    const int q = idx / NMAX, i = idx % NMAX;
+    x0s[q][i] = i < n ? a.x0[q * n + i] : 0.0;
+    sm.rhs[q][i] = i < n ? yx[q * n + i] : T(0);
   }
   __syncthreads();
-  gemv<T, NMAX>(sm, Linv + (size_t)(N - 1) * nn, true, sm.v, sm.r, T(1), false, n, nrhs);
-  store_vec<T, NMAX>(y + (size_t)(N - 1) * nrhs * n, sm.r, n, nrhs);
-  scatter_x<T, NMAX>(a, sm.r, ((size_t)s * N + 0) * n);
+  // dy_X -= F^T x_0 (root propagation, Algorithm 2 line 9), product in FP64
+  const int b = RB::base(), o = RB::out_index();
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nrhs) {
+      double p = 0.0;
+#pragma unroll
+      for (int e = 0; e < RB::EPL; ++e) p += static_cast<double>(fb.v[e]) * x0s[q][b + e];
+      p = lane_group_sum<RB::LPR>(p);
+      if (b == 0) sm.rhs[q][o] = static_cast<T>(static_cast<double>(sm.rhs[q][o]) - p);
+    }
+  }
+  __syncthreads();
+  const size_t off = ((size_t)s * N + 0) * n;
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nrhs) {
+      const T v = lane_group_sum<RB::LPR>(lin.dot(sm.rhs[q]));
+      if (b == 0 && o < n) {
+        yx[q * n + o] = v;
+        scatter_value(a, q, off + o, static_cast<double>(v));
+      }
+    }
+  }
 }
 
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(NT) solve_bwd_level_kernel(SolveArgs a, int level, int count) {
   if (a.done && *a.done) return;
+  typedef RegBlock<T, NMAX> RB;
   __shared__ SolveSmem<T, NMAX> sm;
   const int n = a.n, N = a.N, nrhs = a.nrhs;
   const size_t nn = (size_t)n * n;
@@ -305,20 +360,46 @@ __global__ void __launch_bounds__(NT) solve_bwd_level_kernel(SolveArgs a, int le
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
 
-  load_vec<T, NMAX>(sm.r, y + (size_t)(j - 1) * nrhs * n, n, nrhs);
+  RB lin;
+  lin.template load<true>(Linv + (size_t)(j - 1) * nn, n);
+  T* yj = y + (size_t)(j - 1) * nrhs * n;
+  for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
+    const int q = idx / NMAX, ii = idx % NMAX;
+    sm.rhs[q][ii] = ii < n ? yj[q * n + ii] : T(0);
+  }
   const int jl = j - (1 << (level - 1));
   const int jr = j + (1 << (level - 1));
   const int ir = jr <= a.m ? jr - 1 : N - 1;
+  T part[kMaxRhs];
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) part[q] = T(0);
+  // pull 0: G_l(j)^T x_left ; pull 1: G_r(j)^T x_right (or x_X)
+  auto pull = [&](int p, const T*& blk, const T*& vec) -> bool {
+    if (p == 0) {
+      if (jl < 1) return false;
+      blk = Gl + (size_t)(j - 1) * nn;
+      vec = y + (size_t)(jl - 1) * nrhs * n;
+    } else {
+      blk = Gr + (size_t)(j - 1) * nn;
+      vec = y + (size_t)ir * nrhs * n;
+    }
+    return true;
+  };
+  pull_products<T, NMAX, true>(2, pull, n, nrhs, sm.vbuf, part);
   __syncthreads();
-  if (jl >= 1) {
-    load_vec<T, NMAX>(sm.v, y + (size_t)(jl - 1) * nrhs * n, n, nrhs);
-    gemv<T, NMAX>(sm, Gl + (size_t)(j - 1) * nn, true, sm.v, sm.r, T(-1), true, n, nrhs);
+  subtract_reduced<T, NMAX>(sm.rhs, part, nrhs);
+  __syncthreads();
+  const size_t off = ((size_t)s * N + (N - j)) * n;
+#pragma unroll
+  for (int q = 0; q < kMaxRhs; ++q) {
+    if (q < nrhs) {
+      const T v = lane_group_sum<RB::LPR>(lin.dot(sm.rhs[q]));
+      if (RB::base() == 0 && RB::out_index() < n) {
+        yj[q * n + RB::out_index()] = v;
+        scatter_value(a, q, off + RB::out_index(), static_cast<double>(v));
+      }
+    }
   }
-  load_vec<T, NMAX>(sm.v, y + (size_t)ir * nrhs * n, n, nrhs);
-  gemv<T, NMAX>(sm, Gr + (size_t)(j - 1) * nn, true, sm.v, sm.r, T(-1), true, n, nrhs);
-  gemv<T, NMAX>(sm, Linv + (size_t)(j - 1) * nn, true, sm.r, sm.v, T(1), false, n, nrhs);
-  store_vec<T, NMAX>(y + (size_t)(j - 1) * nrhs * n, sm.v, n, nrhs);
-  scatter_x<T, NMAX>(a, sm.v, ((size_t)s * N + (N - j)) * n);
 }
 
 #define BMPC_DISPATCH_NMAX(nmax, FN, ...) \
