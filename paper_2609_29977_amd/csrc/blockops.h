@@ -134,9 +134,8 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
 // masked through its multiplier.  Blocks smaller than NMAX must be padded with an
 // identity block.  Returns (on every lane) the 0-based row of the first non-positive
 // pivot, or -1.
-template <typename T, int NMAX>
-__device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
-  constexpr int LD = Lay<NMAX>::LD;
+template <typename T, int NMAX, int LD = Lay<NMAX>::LD>
+__device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   const int lane = threadIdx.x & 63;
   const int row = lane < NMAX ? lane : NMAX - 1;
   T a[NMAX], z[NMAX];
@@ -155,16 +154,30 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
     const T lik = a[k] * inv;  // L[lane][k] for lane >= k (lane k: sqrt(piv))
     a[k] = lik;
     myinv = (lane == k) ? inv : myinv;
-    T lc[NMAX], zk[NMAX];
-#pragma unroll
-    for (int c = k + 1; c < NMAX; ++c) lc[c] = wave_bcast(lik, c);
-#pragma unroll
-    for (int c = 0; c <= k; ++c) zk[c] = wave_bcast(z[c], k);
-#pragma unroll
-    for (int c = k + 1; c < NMAX; ++c) a[c] -= lik * lc[c];
     const T zm = (lane > k) ? lik * inv : T(0);
+    // broadcasts in groups of BG: the scalar reads of a group are issued together
+    // (hiding the read-after-write wait) with bounded temporaries
+    constexpr int BG = 8;
 #pragma unroll
-    for (int c = 0; c <= k; ++c) z[c] -= zm * zk[c];
+    for (int c0 = k + 1; c0 < NMAX; c0 += BG) {
+      T lc[BG];
+#pragma unroll
+      for (int u = 0; u < BG; ++u)
+        if (c0 + u < NMAX) lc[u] = wave_bcast(lik, c0 + u);
+#pragma unroll
+      for (int u = 0; u < BG; ++u)
+        if (c0 + u < NMAX) a[c0 + u] -= lik * lc[u];
+    }
+#pragma unroll
+    for (int c0 = 0; c0 <= k; c0 += BG) {
+      T zk[BG];
+#pragma unroll
+      for (int u = 0; u < BG; ++u)
+        if (c0 + u <= k) zk[u] = wave_bcast(z[c0 + u], k);
+#pragma unroll
+      for (int u = 0; u < BG; ++u)
+        if (c0 + u <= k) z[c0 + u] -= zm * zk[u];
+    }
   }
   if (lane < NMAX) {
 #pragma unroll
@@ -251,6 +264,89 @@ __device__ __attribute__((always_inline)) inline void mfma_tile_store(
       T* o = &out[r * LD + c];
       *o = ACCUMULATE ? *o + alpha * acc[v] : alpha * acc[v];
     }
+  }
+}
+
+// ---- blocked potrf + inverse ------------------------------------------------------
+
+__device__ __attribute__((always_inline)) inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// In place: A (NMAX x NMAX symmetric in LDS, padded with an identity block if smaller)
+// := L^{-1}.  For NMAX = 32 the block is split 2 x 2 into 16 x 16 blocks:
+//   L11^{-1} by the lane-per-row leaf;  L21 = A21 L11^{-T} (MFMA);
+//   S = A22 - L21 L21^T (MFMA);  L22^{-1} by the leaf on S;
+//   (L^{-1})21 = -L22^{-1} (L21 L11^{-1}) (two MFMA products).
+// The leaves do two 16-row factorizations instead of one 32-row one, which halves
+// their per-lane state and cuts the scalar broadcasts; the rest runs on the matrix
+// cores.  One wave.  Returns the 0-based row of the first non-positive pivot, or -1.
+template <typename T, int NMAX>
+__device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
+  if constexpr (NMAX < 32) {
+    return wave_potrf_inv_leaf<T, NMAX>(A);
+  } else {
+    constexpr int LD = Lay<NMAX>::LD;
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+    T* A21 = A + 16 * LD;
+    T* A22 = A + 16 * LD + 16;
+    int fail = wave_potrf_inv_leaf<T, 16, LD>(A);  // A11 := L11^{-1}
+    wave_lds_fence();
+    // L21 = A21 L11^{-T}: out[r][c] = sum_k A21[r][k] Linv11[c][k]
+    acc_t t = {0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      t = Mfma<T>::mma(A21[i * LD + k], A[i * LD + k], t);
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A21[Mfma<T>::row(l, v) * LD + i] = t[v];
+    wave_lds_fence();
+    // S = A22 - L21 L21^T
+    acc_t sacc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sacc[v] = A22[Mfma<T>::row(l, v) * LD + i];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      sacc = Mfma<T>::mma(-A21[i * LD + k], A21[i * LD + k], sacc);
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A22[Mfma<T>::row(l, v) * LD + i] = sacc[v];
+    wave_lds_fence();
+    const int fail2 = wave_potrf_inv_leaf<T, 16, LD>(A22);  // A22 := L22^{-1}
+    wave_lds_fence();
+    // W = L21 L11^{-1}: out[r][c] = sum_k L21[r][k] Linv11[k][c]
+    acc_t w = {0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      w = Mfma<T>::mma(A21[i * LD + k], A[k * LD + i], w);
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A21[Mfma<T>::row(l, v) * LD + i] = w[v];
+    wave_lds_fence();
+    // (L^{-1})21 = -L22^{-1} W: out[r][c] = sum_k Linv22[r][k] W[k][c]
+    acc_t x = {0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      x = Mfma<T>::mma(-A22[i * LD + k], A21[k * LD + i], x);
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      A21[Mfma<T>::row(l, v) * LD + i] = x[v];
+      A[Mfma<T>::row(l, v) * LD + 16 + i] = T(0);  // upper right block
+    }
+    wave_lds_fence();
+    if (fail >= 0) return fail;
+    return fail2 >= 0 ? 16 + fail2 : -1;
   }
 }
 

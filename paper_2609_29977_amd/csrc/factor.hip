@@ -88,11 +88,15 @@ struct NodeFetch {
   T ar[EL], al[EL];
   CT cp[EL];
 
+  bool pre;  // the node's L^{-1} was formed by the window prologue (then held in d)
+
   __device__ void issue(const FactorPassArgs& a, int s, int q) {
     const int n = a.n, N = a.N;
     const size_t nn = (size_t)n * n;
     const int j = q << a.shift;
+    pre = (q & 1) != 0;
     const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
+    const T* Li = reinterpret_cast<const T*>(a.Linv) + ((size_t)s * N + (j - 1)) * nn;
     const T* accR = nullptr;
     const T* accL = nullptr;
     const CT* cpl;
@@ -110,10 +114,14 @@ struct NodeFetch {
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
       const bool lower = in && r >= c;
-      d[jj] = lower ? D[r * n + c] : 0.0;
-      if constexpr (!FIRST) {
-        ar[jj] = lower ? accR[r * n + c] : T(0);
-        al[jj] = lower ? accL[r * n + c] : T(0);
+      if (pre) {
+        d[jj] = in ? static_cast<double>(Li[r * n + c]) : 0.0;
+      } else {
+        d[jj] = lower ? D[r * n + c] : 0.0;
+        if constexpr (!FIRST) {
+          ar[jj] = lower ? accR[r * n + c] : T(0);
+          al[jj] = lower ? accL[r * n + c] : T(0);
+        }
       }
       cp[jj] = in ? cpl[r * n + c] : CT(0);
     }
@@ -127,7 +135,9 @@ struct NodeFetch {
       if (e >= NMAX * NMAX) continue;
       const int r = e / NMAX, c = e % NMAX;
       const bool in = r < n && c < n;
-      if (in && r >= c) {
+      if (pre) {
+        A[r * LD + c] = in ? static_cast<T>(d[jj]) : ((r == c) ? T(1) : T(0));
+      } else if (in && r >= c) {
         T v = static_cast<T>(d[jj]);
         if constexpr (!FIRST) v = (v + ar[jj]) + al[jj];
         A[r * LD + c] = v;
@@ -161,7 +171,7 @@ __device__ inline void slot_store(T* __restrict__ dst, const T* src, int n) {
 // with the workgroup index so that the latency-bound factorizations of the resident
 // workgroups spread over the SIMDs.
 template <typename T, int NMAX>
-__device__ inline void factor_diag(T* A, unsigned long long perm_row0, int n,
+__device__ __attribute__((always_inline)) inline void factor_diag(T* A, unsigned long long perm_row0, int n,
                                    unsigned long long* info) {
   constexpr int NW = TileCfg<NMAX>::NT / 64;
   if ((threadIdx.x >> 6) == (int)(blockIdx.x % NW)) {
@@ -175,11 +185,11 @@ __device__ inline void factor_diag(T* A, unsigned long long perm_row0, int n,
 // G_r = K[r,j] L^{-T} (into Cj), G_l = K[l,j] L^{-T} (into Cl, which holds K[j,l]);
 // A_r -= G_r G_r^T; A_l -= G_l G_l^T; K[r,l] = -G_r G_l^T (into Cl).
 template <typename T, int NMAX>
-__device__ inline void eliminate(T* Aj, T* Cj, T* Al, T* Cl, T* Ar, int n, T* gLinv,
+__device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T* Al, T* Cl, T* Ar, int n, T* gLinv,
                                  T* gGl, T* gGr, unsigned long long perm_row0,
-                                 unsigned long long* info) {
+                                 unsigned long long* info, bool have_inverse) {
   typedef typename Mfma<T>::acc_t acc_t;
-  factor_diag<T, NMAX>(Aj, perm_row0, n, info);
+  if (!have_inverse) factor_diag<T, NMAX>(Aj, perm_row0, n, info);
   const bool left = Cl != nullptr;
   acc_t gr = mfma_tile_nt<T, NMAX, false>(Cj, Aj);
   acc_t gl = {0, 0, 0, 0};
@@ -188,7 +198,7 @@ __device__ inline void eliminate(T* Aj, T* Cj, T* Al, T* Cl, T* Ar, int n, T* gL
   mfma_tile_store<T, NMAX, false>(Cj, gr, T(1));
   if (left) mfma_tile_store<T, NMAX, false>(Cl, gl, T(1));
   __syncthreads();
-  slot_store<T, NMAX>(gLinv, Aj, n);
+  if (!have_inverse) slot_store<T, NMAX>(gLinv, Aj, n);
   slot_store<T, NMAX>(gGr, Cj, n);
   if (left) slot_store<T, NMAX>(gGl, Cl, n);
   acc_t ur = mfma_tile_nt<T, NMAX, false>(Cj, Cj);
@@ -225,6 +235,58 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
   T* Gr = reinterpret_cast<T*>(a.Gr) + (size_t)s * (N > 1 ? N - 1 : 1) * nn;
   const unsigned long long chain_row0 = (unsigned long long)s * N * n;
 
+  // Prologue: the pass-local level-1 positions (odd q) see no update from inside the
+  // window, so their diagonal blocks (D plus updates carried from earlier passes) are
+  // factored and inverted up front, one block per wave and all waves in parallel,
+  // staged through the window's still unused LDS slots; the inverses go straight to
+  // the factor storage and the streaming phase below reloads them.
+  {
+    constexpr int NW = TileCfg<NMAX>::NT / 64;
+    constexpr int LD = Lay<NMAX>::LD;
+    constexpr int SZ = Lay<NMAX>::SZ;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    T* mine = sl.base + wv * SZ;
+    const int nodd = (hi - lo + 1) / 2;
+    for (int r0 = 0; r0 < nodd; r0 += NW) {
+      const int i = r0 + wv;
+      const bool active = i < nodd;
+      const int q = lo + 1 + 2 * i;
+      const int j = q << a.shift;
+      if (active) {
+        const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
+        for (int e = lane; e < NMAX * NMAX; e += 64) {
+          const int r = e / NMAX, c = e % NMAX;
+          T v;
+          if (r < n && c < n) {
+            const int o = c <= r ? r * n + c : c * n + r;
+            v = static_cast<T>(D[o]);
+            if constexpr (!FIRST) {
+              const size_t b = ((size_t)s * a.stride + q) * nn;
+              v = (v + reinterpret_cast<const T*>(a.accR_in)[b + o]) +
+                  reinterpret_cast<const T*>(a.accL_in)[b + o];
+            }
+          } else {
+            v = (r == c) ? T(1) : T(0);
+          }
+          mine[r * LD + c] = v;
+        }
+      }
+      __syncthreads();
+      if (active) {
+        const int fail = wave_potrf_inv<T, NMAX>(mine);
+        if (fail >= 0 && fail < n && lane == 0)
+          atomicMin(a.info, chain_row0 + (unsigned long long)a.permpos[j - 1] * n + fail + 1);
+      }
+      __syncthreads();
+      if (active) {
+        T* Lo = Linv + (size_t)(j - 1) * nn;
+        for (int e = lane; e < n * n; e += 64) Lo[e] = mine[(e / n) * LD + e % n];
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
   NodeFetch<T, NMAX, FIRST> pf;
   if (lo + 1 <= hi) pf.issue(a, s, lo + 1);
 
@@ -295,7 +357,8 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
       const int j = pos << a.shift;  // original chain position
       const unsigned long long prow = chain_row0 + (unsigned long long)a.permpos[j - 1] * n;
       eliminate<T, NMAX>(sl.A(t), sl.Cp(t), Al, Cl, Ar, n, Linv + (size_t)(j - 1) * nn,
-                         Gl + (size_t)(j - 1) * nn, Gr + (size_t)(j - 1) * nn, prow, a.info);
+                         Gl + (size_t)(j - 1) * nn, Gr + (size_t)(j - 1) * nn, prow, a.info,
+                         (pos & 1) != 0);
       live &= ~(1u << t);
     }
     if (!is_rb) live |= (1u << v);
