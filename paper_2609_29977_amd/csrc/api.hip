@@ -448,7 +448,7 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
   p->costs = make_costs(*dims, p->fp64, p->Tw);
   p->perm = make_perm(dims->N);
   p->permpos = make_permpos(dims->N);
-  p->groups = std::min(dims->S, 64);
+  p->groups = std::min(dims->S, 32);
   const int S = dims->S, N = dims->N, n = dims->n, nrhs = dims->nrhs;
   const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
   const size_t len = ((size_t)S * N + 1) * n;

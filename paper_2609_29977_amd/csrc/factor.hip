@@ -441,36 +441,39 @@ __global__ void __launch_bounds__(256) root_reduce_kernel(const double* __restri
 }
 
 // R~ = R - sum_g part[g] (group order), L_R = chol(R~) in FP64 (Algorithm 1, 7-8).
-__global__ void __launch_bounds__(256) root_potrf_kernel(const double* __restrict__ R,
-                                                         const double* __restrict__ part,
-                                                         int groups, int n, double* LR,
-                                                         unsigned long long row_base,
-                                                         unsigned long long* info) {
+// 1024 threads: thread e owns element e and loads all group partials at once.
+__global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restrict__ R,
+                                                          const double* __restrict__ part,
+                                                          int groups, int n, double* LR,
+                                                          unsigned long long row_base,
+                                                          unsigned long long* info) {
   __shared__ double A[32 * 33];
   constexpr int LD = 33;
-  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
-    const int r = e / 32, c = e % 32;
-    double v;
-    if (r < n && c < n) {
-      const double rv = (r >= c) ? R[r * n + c] : R[c * n + r];
-      double acc = 0.0;
-      for (int g = 0; g < groups; ++g) acc += part[(size_t)g * n * n + r * n + c];
-      v = rv - acc;
-    } else {
-      v = (r == c) ? 1.0 : 0.0;  // identity padding
+  const int e = threadIdx.x;
+  const int r = e / 32, c = e % 32;
+  double v = (r == c) ? 1.0 : 0.0;  // identity padding
+  if (r < n && c < n) {
+    constexpr int B = 16;
+    double acc = 0.0;
+    for (int g0 = 0; g0 < groups; g0 += B) {
+      double t[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        t[u] = (g0 + u < groups) ? part[(size_t)(g0 + u) * n * n + r * n + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < B; ++u) acc += t[u];
     }
-    A[r * LD + c] = v;
+    const double rv = (r >= c) ? R[r * n + c] : R[c * n + r];
+    v = rv - acc;
   }
+  A[r * LD + c] = v;
   __syncthreads();
   if (threadIdx.x < 64) {
     const int fail = wave_potrf<double, 32>(A);
     if (fail >= 0 && fail < n && threadIdx.x == 0) atomicMin(info, row_base + fail + 1);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int r = e / n, c = e - (e / n) * n;
-    LR[e] = A[r * LD + c];
-  }
+  if (r < n && c < n) LR[r * n + c] = A[r * LD + c];
 }
 
 template <typename T, int NMAX>
@@ -543,7 +546,7 @@ void launch_root_reduce(const double* U, double* part, int S, int n, int groups,
 
 void launch_root_potrf(const double* R, const double* part, int groups, int n, double* LR,
                        int64_t row_base, unsigned long long* info, hipStream_t st) {
-  hipLaunchKernelGGL(root_potrf_kernel, dim3(1), dim3(256), 0, st, R, part, groups, n, LR,
+  hipLaunchKernelGGL(root_potrf_kernel, dim3(1), dim3(1024), 0, st, R, part, groups, n, LR,
                      (unsigned long long)row_base, info);
 }
 

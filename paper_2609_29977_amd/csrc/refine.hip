@@ -16,40 +16,56 @@ namespace bmpc {
 
 namespace {
 
-constexpr int NT = 64;
+// Waves per tail work item: the rows of each block are split over WAVES waves so that
+// the three blocks of a stage and their prefetched successors take at most 12 doubles
+// per lane each (about 128 VGPRs at n = 32, four waves per SIMD for this HBM-bound
+// kernel).
+template <int NMAX>
+struct ResCfg {
+  static constexpr int WAVES = NMAX == 32 ? 4 : (NMAX == 16 ? 2 : 1);
+  static constexpr int NT = 64 * WAVES;
+  typedef RegBlock<double, NMAX, WAVES> RB;
+};
 
 // Register block of a symmetric matrix stored by its lower triangle, normal mapping:
 // lane holds row o, columns base..base+EPL of sym(D).
 template <int NMAX>
-__device__ inline void load_sym(RegBlock<double, NMAX>& rb, const double* __restrict__ g, int n) {
-  typedef RegBlock<double, NMAX> RB;
+__device__ inline void load_sym(typename ResCfg<NMAX>::RB& rb, const double* __restrict__ g,
+                                int n) {
+  typedef typename ResCfg<NMAX>::RB RB;
   const int o = RB::out_index(), b = RB::base();
+  const auto rs = block_rsrc(g, (unsigned)(n * n) * sizeof(double));
+  // element (o, c) is read from whichever triangle holds it; padding reads as zero
 #pragma unroll
   for (int e = 0; e < RB::EPL; ++e) {
     const int c = b + e;
-    rb.v[e] = (o < n && c < n) ? (c <= o ? g[o * n + c] : g[c * n + o]) : 0.0;
+    const int idx = c <= o ? o * n + c : c * n + o;
+    const unsigned off = (o < n && c < n) ? (unsigned)idx * sizeof(double) : kOutOfRange;
+    rb.v[e] = buf_load_f64(rs, off);
   }
 }
 
 template <int NMAX>
 struct StageBlocks {
-  RegBlock<double, NMAX> d, en, et;  // D_k (sym), E_k (normal), E_k (transposed)
+  typename ResCfg<NMAX>::RB d, en, et;  // D_k (sym), E_k (normal), E_k (transposed)
   __device__ void load(const ResidualArgs& a, int s, int k) {
     const int n = a.n, N = a.N;
     const size_t nn = (size_t)n * n;
     load_sym<NMAX>(d, a.D + ((size_t)s * N + k) * nn, n);
     if (k + 1 < N) {
-      const double* E = a.E + ((size_t)s * (N - 1) + k) * nn;
-      en.template load<false>(E, n);
-      et.template load<true>(E, n);
+      const auto rs = block_rsrc(a.E + ((size_t)s * (N - 1) + k) * nn,
+                                 (unsigned)nn * sizeof(double));
+      en.template load_buf<false>(rs, n);
+      et.template load_buf<true>(rs, n);
     }
   }
 };
 
 template <int NMAX>
-__global__ void __launch_bounds__(NT) residual_kernel(ResidualArgs a, int chunks) {
+__global__ void __launch_bounds__(ResCfg<NMAX>::NT) residual_kernel(ResidualArgs a, int chunks) {
   if (a.done && *a.done) return;
-  typedef RegBlock<double, NMAX> RB;
+  typedef typename ResCfg<NMAX>::RB RB;
+  constexpr int NT = ResCfg<NMAX>::NT;
   __shared__ double xs[3][kMaxRhs][NMAX];  // x_{k-1}, x_k, x_{k+1} (rotating)
   __shared__ double x0s[kMaxRhs][NMAX];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
@@ -75,19 +91,18 @@ __global__ void __launch_bounds__(NT) residual_kernel(ResidualArgs a, int chunks
       const int q = idx / NMAX, i = idx % NMAX;
       x0s[q][i] = i < n ? a.x[(size_t)q * len + (size_t)S * N * n + i] : 0.0;
     }
-  // carry: E_{k0-1} x_{k0-1}, partial sums for row k0
-  double carry[kMaxRhs];
-#pragma unroll
-  for (int q = 0; q < kMaxRhs; ++q) carry[q] = 0.0;
+  // carry: this lane's partial of E_{k0-1} x_{k0-1} for row k0, one slot per
+  // right-hand side (LDS, so the loop over right-hand sides need not be unrolled)
+  __shared__ double carry[kMaxRhs][NT];
+  double* my = &carry[0][threadIdx.x];
+  for (int q = 0; q < nrhs; ++q) my[q * NT] = 0.0;
   StageBlocks<NMAX> cur;
   cur.load(a, s, k0);
   if (k0 > 0) {
     RB ep;
     ep.template load<false>(a.E + ((size_t)s * (N - 1) + (k0 - 1)) * nn, n);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kMaxRhs; ++q)
-      if (q < nrhs) carry[q] = ep.dot(xs[ip][q]);
+    for (int q = 0; q < nrhs; ++q) my[q * NT] = ep.dot(xs[ip][q]);
   }
   for (int k = k0; k < k1; ++k) {
     load_x(xs[in], k + 1);
@@ -95,32 +110,28 @@ __global__ void __launch_bounds__(NT) residual_kernel(ResidualArgs a, int chunks
     if (k + 1 < k1) nxt.load(a, s, k + 1);
     __syncthreads();
     const size_t off = ((size_t)s * N + k) * n;
-#pragma unroll
-    for (int q = 0; q < kMaxRhs; ++q) {
-      if (q < nrhs) {
-        double p = cur.d.dot(xs[ic][q]) + carry[q];
-        if (k + 1 < N) {
-          p += cur.et.dot(xs[in][q]);
-          carry[q] = cur.en.dot(xs[ic][q]);
-        }
-        p = lane_group_sum<RB::LPR>(p);
-        if (b == 0 && o < n) a.r[(size_t)q * len + off + o] = a.b[(size_t)q * len + off + o] - p;
+#pragma unroll 1
+    for (int q = 0; q < nrhs; ++q) {
+      double p = cur.d.dot(xs[ic][q]) + my[q * NT];
+      if (k + 1 < N) {
+        p += cur.et.dot(xs[in][q]);
+        my[q * NT] = cur.en.dot(xs[ic][q]);
       }
+      p = lane_group_sum<RB::LPR>(p);
+      if (b == 0 && o < n) a.r[(size_t)q * len + off + o] = a.b[(size_t)q * len + off + o] - p;
     }
     if (k == 0) {
       // C_s^T x_0 enters row 0; w_s = C_s x_{s,0} feeds the root row
       RB ct, cn;
       ct.template load<true>(a.C + (size_t)s * nn, n);
       cn.template load<false>(a.C + (size_t)s * nn, n);
-#pragma unroll
-      for (int q = 0; q < kMaxRhs; ++q) {
-        if (q < nrhs) {
-          const double pc = lane_group_sum<RB::LPR>(ct.dot(x0s[q]));
-          const double pw = lane_group_sum<RB::LPR>(cn.dot(xs[ic][q]));
-          if (b == 0 && o < n) {
-            a.r[(size_t)q * len + off + o] -= pc;
-            a.w[((size_t)s * nrhs + q) * n + o] = pw;
-          }
+#pragma unroll 1
+      for (int q = 0; q < nrhs; ++q) {
+        const double pc = lane_group_sum<RB::LPR>(ct.dot(x0s[q]));
+        const double pw = lane_group_sum<RB::LPR>(cn.dot(xs[ic][q]));
+        if (b == 0 && o < n) {
+          a.r[(size_t)q * len + off + o] -= pc;
+          a.w[((size_t)s * nrhs + q) * n + o] = pw;
         }
       }
     }
@@ -133,24 +144,34 @@ __global__ void __launch_bounds__(NT) residual_kernel(ResidualArgs a, int chunks
   }
 }
 
-__global__ void __launch_bounds__(256) residual_root_kernel(ResidualArgs a) {
+__global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
   if (a.done && *a.done) return;
-  __shared__ double part[256];
+  __shared__ double part[32][33];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
   const size_t len = ((size_t)S * N + 1) * n;
   const size_t root = (size_t)S * N * n;
-  const int tpe = 8;
+  const int t = threadIdx.x, i = t & 31, g = t >> 5;
   for (int q = 0; q < nrhs; ++q) {
-    const int i = threadIdx.x / tpe, g = threadIdx.x - (threadIdx.x / tpe) * tpe;
     double acc = 0.0;
-    if (i < n)
-      for (int s = g; s < S; s += tpe) acc += a.w[((size_t)s * nrhs + q) * n + i];
-    part[threadIdx.x] = acc;
+    if (i < n) {
+      constexpr int B = 8;
+      for (int s0 = g; s0 < S; s0 += 32 * B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int sc = s0 + 32 * u;
+          v[u] = sc < S ? a.w[((size_t)sc * nrhs + q) * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) acc += v[u];
+      }
+    }
+    part[g][i] = acc;
     __syncthreads();
-    if (threadIdx.x < n) {
-      const int row = threadIdx.x;
+    if (t < n) {
+      const int row = t;
       double sum = 0.0;
-      for (int gg = 0; gg < tpe; ++gg) sum += part[row * tpe + gg];
+      for (int gg = 0; gg < 32; ++gg) sum += part[gg][row];
       double rx = 0.0;
       for (int c = 0; c < n; ++c) {
         const double rv = (row >= c) ? a.R[row * n + c] : a.R[c * n + row];
@@ -236,15 +257,15 @@ void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
   const int chunks = (a.N + a.chunk - 1) / a.chunk;
   const dim3 grid((unsigned)a.S * (unsigned)chunks);
   if (nmax <= 8)
-    hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(NT), 0, st, a, chunks);
+    hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(ResCfg<8>::NT), 0, st, a, chunks);
   else if (nmax <= 16)
-    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(NT), 0, st, a, chunks);
+    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(ResCfg<16>::NT), 0, st, a, chunks);
   else
-    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(NT), 0, st, a, chunks);
+    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(ResCfg<32>::NT), 0, st, a, chunks);
 }
 
 void launch_residual_root(const ResidualArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(residual_root_kernel, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(residual_root_kernel, dim3(1), dim3(1024), 0, st, a);
 }
 
 void launch_maxabs(const double* v, const double* v2, int nrhs, size_t len, double* partial,

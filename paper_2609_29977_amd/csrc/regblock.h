@@ -1,8 +1,10 @@
-// Register-resident n x n blocks for matrix-vector products on one wave (gfx950).
+// Register-resident n x n blocks for matrix-vector products on one or more waves
+// (gfx950).
 //
-// A block is split over the 64 lanes of a wave: LPR = 64/NMAX lanes share one output
-// index o = lane / LPR and each holds EPL = NMAX/LPR consecutive elements of the
-// contraction index, starting at base = (lane % LPR) * EPL.  In the normal mapping a
+// A block is split over the lanes of WAVES waves: wave w owns the RPW = NMAX/WAVES
+// output indices starting at w*RPW; within a wave LPR = 64/RPW lanes share one output
+// index o and each holds EPL = NMAX/LPR consecutive elements of the contraction index,
+// starting at base = (lane % LPR) * EPL.  In the normal mapping a
 // lane holds part of row o (products M v); in the transposed mapping part of column o
 // (products M^T v).  Both load coalesced from a row-major block and share the same
 // dot-product / reduction code.  Rows and columns >= n read as zero.
@@ -12,14 +14,39 @@
 
 namespace bmpc {
 
-template <typename T, int NMAX>
+// Raw buffer resource over `bytes` bytes at `base` (wave-uniform).  Loads through it
+// take a 32-bit byte offset; an offset at or past `bytes` reads as zero.
+__device__ inline __amdgpu_buffer_rsrc_t block_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+constexpr unsigned kOutOfRange = 0x80000000u;
+
+__device__ inline double buf_load_f64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  double d;
+  __builtin_memcpy(&d, &v, sizeof(d));
+  return d;
+}
+__device__ inline float buf_load_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  float f;
+  __builtin_memcpy(&f, &v, sizeof(f));
+  return f;
+}
+
+template <typename T, int NMAX, int WAVES = 1>
 struct RegBlock {
   static_assert(NMAX == 8 || NMAX == 16 || NMAX == 32, "block size bound");
-  static constexpr int LPR = 64 / NMAX;
+  static_assert(WAVES == 1 || WAVES == 2 || WAVES == 4, "waves per block");
+  static constexpr int RPW = NMAX / WAVES;
+  static constexpr int LPR = 64 / RPW;
   static constexpr int EPL = NMAX / LPR;
   T v[EPL];
 
-  __device__ static int out_index() { return (threadIdx.x & 63) / LPR; }
+  __device__ static int out_index() {
+    return (WAVES > 1 ? (int)(threadIdx.x >> 6) * RPW : 0) + (threadIdx.x & 63) / LPR;
+  }
   __device__ static int base() { return ((threadIdx.x & 63) % LPR) * EPL; }
 
   template <bool TRANS>
@@ -29,11 +56,30 @@ struct RegBlock {
 #pragma unroll
       for (int e = 0; e < EPL; ++e) v[e] = TRANS ? g[(b + e) * NMAX + o] : g[o * NMAX + b + e];
     } else {
+      // branch-free: out-of-range elements load element 0 and are replaced by zero
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         const int r = TRANS ? b + e : o, c = TRANS ? o : b + e;
-        v[e] = (r < n && c < n) ? g[r * n + c] : T(0);
+        const bool ok = r < n && c < n;
+        const T t = g[ok ? r * n + c : 0];
+        v[e] = ok ? t : T(0);
       }
+    }
+  }
+
+  // Same as load, through a buffer resource covering the n x n block (out-of-range
+  // elements read as zero without a branch or a select).
+  template <bool TRANS>
+  __device__ void load_buf(__amdgpu_buffer_rsrc_t rs, int n) {
+    const int o = out_index(), b = base();
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int r = TRANS ? b + e : o, c = TRANS ? o : b + e;
+      const unsigned off = (r < n && c < n) ? (unsigned)(r * n + c) * sizeof(T) : kOutOfRange;
+      if constexpr (sizeof(T) == 8)
+        v[e] = buf_load_f64(rs, off);
+      else
+        v[e] = buf_load_f32(rs, off);
     }
   }
 

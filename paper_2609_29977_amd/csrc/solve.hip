@@ -245,56 +245,73 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   }
 }
 
-// Root step in FP64 (Algorithm 2, lines 5-7).  One workgroup of 256 threads.
-__global__ void __launch_bounds__(256) solve_root_kernel(SolveArgs a) {
+// Root step in FP64 (Algorithm 2, lines 5-7).  One workgroup of 1024 threads:
+// r~_0 = r_0 - sum_s w_s with thread (g, i) summing the scenarios s = g mod 32 of
+// element i and the 32 group partials combined in order; then the two triangular
+// solves with L_R in LDS, one wave per right-hand side, lane i owning row i.
+__global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
   if (a.done && *a.done) return;
-  __shared__ double part[256];
+  __shared__ double part[32][33];
+  __shared__ double L[32 * 33];
   __shared__ double r0[kMaxRhs][32];
   const int n = a.n, S = a.S, nrhs = a.nrhs;
   const size_t len = ((size_t)S * a.N + 1) * n;
   const size_t root_off = (size_t)S * a.N * n;
-  // sum_s w_s for every (q, i): 8 thread groups over scenario slices, then a fixed
-  // combination order.
-  const int tpe = 256 / 32;
+  const int t = threadIdx.x, i = t & 31, g = t >> 5;
+  {
+    const int r = t / 32, c = t % 32;
+    L[r * 33 + c] = (r < n && c < n) ? a.LR[r * n + c] : 0.0;
+  }
   for (int q = 0; q < nrhs; ++q) {
-    const int i = threadIdx.x / tpe, g = threadIdx.x - (threadIdx.x / tpe) * tpe;
     double acc = 0.0;
-    if (i < n)
-      for (int s = g; s < S; s += tpe) acc += a.w[((size_t)s * nrhs + q) * n + i];
-    part[threadIdx.x] = acc;
+    if (i < n) {
+      constexpr int B = 8;
+      for (int s0 = g; s0 < S; s0 += 32 * B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int sc = s0 + 32 * u;
+          v[u] = sc < S ? a.w[((size_t)sc * nrhs + q) * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) acc += v[u];
+      }
+    }
+    part[g][i] = acc;
     __syncthreads();
-    if (threadIdx.x < n) {
-      double t = 0.0;
-      for (int gg = 0; gg < tpe; ++gg) t += part[threadIdx.x * tpe + gg];
-      double bv = a.b[(size_t)q * len + root_off + threadIdx.x];
+    if (t < n) {
+      double sum = 0.0;
+      for (int gg = 0; gg < 32; ++gg) sum += part[gg][t];
+      double bv = a.b[(size_t)q * len + root_off + t];
       if (a.rnorm) {
         const double rn = a.rnorm[q];
         bv = rn > 0.0 ? bv / rn : 0.0;
       }
-      r0[q][threadIdx.x] = bv - t;
+      r0[q][t] = bv - sum;
     }
     __syncthreads();
   }
-  // triangular solves with L_R, one thread per right-hand side
-  if (threadIdx.x < nrhs) {
-    const int q = threadIdx.x;
-    double* v = r0[q];
-    for (int i = 0; i < n; ++i) {
-      double t = v[i];
-      for (int k = 0; k < i; ++k) t -= a.LR[i * n + k] * v[k];
-      v[i] = t / a.LR[i * n + i];
+  // L_R y = r, then L_R^T x = y: wave q handles right-hand side q, lane k row k
+  const int wv = t >> 6, lane = t & 63;
+  if (wv < nrhs) {
+    double v = (lane < n) ? r0[wv][lane] : 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double xk = __shfl(v, k) / L[k * 33 + k];
+      if (lane == k) v = xk;
+      if (lane > k && lane < n) v -= L[lane * 33 + k] * xk;
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double t = v[i];
-      for (int k = i + 1; k < n; ++k) t -= a.LR[k * n + i] * v[k];
-      v[i] = t / a.LR[i * n + i];
+    for (int k = n - 1; k >= 0; --k) {
+      const double xk = __shfl(v, k) / L[k * 33 + k];
+      if (lane == k) v = xk;
+      if (lane < k) v -= L[k * 33 + lane] * xk;
     }
+    if (lane < n) r0[wv][lane] = v;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < n * nrhs; idx += 256) {
-    const int q = idx / n, i = idx - (idx / n) * n;
-    a.x0[idx] = r0[q][i];
-    scatter_value(a, q, root_off + i, r0[q][i]);
+  for (int idx = t; idx < n * nrhs; idx += 1024) {
+    const int q = idx / n, ii = idx - (idx / n) * n;
+    a.x0[idx] = r0[q][ii];
+    scatter_value(a, q, root_off + ii, r0[q][ii]);
   }
 }
 
@@ -454,7 +471,7 @@ void launch_solve_x_bwd(const SolveArgs& a, int nmax, hipStream_t st) {
   BMPC_DISPATCH_NMAX(nmax, x_bwd_t, a, st);
 }
 void launch_solve_root(const SolveArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(solve_root_kernel, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(solve_root_kernel, dim3(1), dim3(1024), 0, st, a);
 }
 
 template void launch_solve_fwd_level<double>(const SolveArgs&, int, int, hipStream_t);
