@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--window-depth", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (accuracy + CPU baseline)")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (counter calibration "
+                         "for the HBM traffic figures) and exit")
     return ap.parse_args()
 
 
@@ -78,6 +81,19 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.calibrate_copy > 0:
+        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+        # factor that turns the counters of the solver kernels into HBM bytes.
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 4}))
+        return
 
     from paper_2609_29977_amd import bmpc
     from synth.branch_system import CONFIGS, make_config

@@ -26,6 +26,7 @@
 
 #include "bmpc_internal.h"
 #include "blockops.h"
+#include "regblock.h"
 
 namespace bmpc {
 
@@ -77,31 +78,74 @@ __device__ inline void slot_load(T* dst, const S* __restrict__ src, int n, bool 
   }
 }
 
-// Register prefetch of one chain node: its diagonal block (D + carried updates) and
-// its coupling to the successor.  Issued one node ahead so that the global loads
-// overlap the eliminations of the current node.
+// Register prefetch of chain nodes, issued two positions ahead so that the global
+// loads overlap the work of the position in between.  Odd pass-local positions were
+// factored by the window prologue: their fetch reloads L^{-1} and the coupling to the
+// successor.  Even positions fetch D plus the updates carried from earlier passes and
+// the coupling.
 template <typename T, int NMAX, bool FIRST>
-struct NodeFetch {
+struct FetchOdd {
+  static constexpr int EL = Share<NMAX>::ELEMS;
+  typedef typename std::conditional<FIRST, double, T>::type CT;
+  T li[EL];
+  CT cp[EL];
+
+  __device__ void issue(const FactorPassArgs& a, int s, int q) {
+    const int n = a.n, N = a.N;
+    const size_t nn = (size_t)n * n;
+    const int j = q << a.shift;
+    const T* Li = reinterpret_cast<const T*>(a.Linv) + ((size_t)s * N + (j - 1)) * nn;
+    const CT* cpl;
+    if constexpr (FIRST)
+      cpl = a.E + ((size_t)s * (N - 1) + (N - 1 - q)) * nn;  // K[q+1,q] = E[s][N-1-q]^T
+    else
+      cpl = reinterpret_cast<const T*>(a.fill_in) + ((size_t)s * a.stride + q) * nn;
+#pragma unroll
+    for (int jj = 0; jj < EL; ++jj) {
+      const int e = Share<NMAX>::elem(jj);
+      const int r = e / NMAX, c = e % NMAX;
+      const bool in = e < NMAX * NMAX && r < n && c < n;
+      li[jj] = in ? Li[r * n + c] : T(0);
+      cp[jj] = in ? cpl[r * n + c] : CT(0);
+    }
+  }
+
+  __device__ void commit(T* A, T* C, int n) const {
+    constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+    for (int jj = 0; jj < EL; ++jj) {
+      const int e = Share<NMAX>::elem(jj);
+      if (e >= NMAX * NMAX) continue;
+      const int r = e / NMAX, c = e % NMAX;
+      const bool in = r < n && c < n;
+      A[r * LD + c] = in ? li[jj] : ((r == c) ? T(1) : T(0));
+      const T cv = static_cast<T>(cp[jj]);
+      if constexpr (FIRST)
+        C[c * LD + r] = cv;
+      else
+        C[r * LD + c] = cv;
+    }
+  }
+};
+
+template <typename T, int NMAX, bool FIRST>
+struct FetchEven {
   static constexpr int EL = Share<NMAX>::ELEMS;
   typedef typename std::conditional<FIRST, double, T>::type CT;
   double d[EL];
   T ar[EL], al[EL];
   CT cp[EL];
 
-  bool pre;  // the node's L^{-1} was formed by the window prologue (then held in d)
-
   __device__ void issue(const FactorPassArgs& a, int s, int q) {
     const int n = a.n, N = a.N;
     const size_t nn = (size_t)n * n;
     const int j = q << a.shift;
-    pre = (q & 1) != 0;
     const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
-    const T* Li = reinterpret_cast<const T*>(a.Linv) + ((size_t)s * N + (j - 1)) * nn;
     const T* accR = nullptr;
     const T* accL = nullptr;
     const CT* cpl;
     if constexpr (FIRST) {
-      cpl = a.E + ((size_t)s * (N - 1) + (N - 1 - q)) * nn;  // K[q+1,q] = E[s][N-1-q]^T
+      cpl = a.E + ((size_t)s * (N - 1) + (N - 1 - q)) * nn;
     } else {
       const size_t o = ((size_t)s * a.stride + q) * nn;
       accR = reinterpret_cast<const T*>(a.accR_in) + o;
@@ -114,14 +158,10 @@ struct NodeFetch {
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
       const bool lower = in && r >= c;
-      if (pre) {
-        d[jj] = in ? static_cast<double>(Li[r * n + c]) : 0.0;
-      } else {
-        d[jj] = lower ? D[r * n + c] : 0.0;
-        if constexpr (!FIRST) {
-          ar[jj] = lower ? accR[r * n + c] : T(0);
-          al[jj] = lower ? accL[r * n + c] : T(0);
-        }
+      d[jj] = lower ? D[r * n + c] : 0.0;
+      if constexpr (!FIRST) {
+        ar[jj] = lower ? accR[r * n + c] : T(0);
+        al[jj] = lower ? accL[r * n + c] : T(0);
       }
       cp[jj] = in ? cpl[r * n + c] : CT(0);
     }
@@ -135,9 +175,7 @@ struct NodeFetch {
       if (e >= NMAX * NMAX) continue;
       const int r = e / NMAX, c = e % NMAX;
       const bool in = r < n && c < n;
-      if (pre) {
-        A[r * LD + c] = in ? static_cast<T>(d[jj]) : ((r == c) ? T(1) : T(0));
-      } else if (in && r >= c) {
+      if (in && r >= c) {
         T v = static_cast<T>(d[jj]);
         if constexpr (!FIRST) v = (v + ar[jj]) + al[jj];
         A[r * LD + c] = v;
@@ -237,58 +275,99 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
 
   // Prologue: the pass-local level-1 positions (odd q) see no update from inside the
   // window, so their diagonal blocks (D plus updates carried from earlier passes) are
-  // factored and inverted up front, one block per wave and all waves in parallel,
-  // staged through the window's still unused LDS slots; the inverses go straight to
-  // the factor storage and the streaming phase below reloads them.
+  // factored and inverted up front.  Up to kBatch blocks at a time are loaded by the
+  // whole workgroup into the window's still unused LDS slots (all loads in flight at
+  // once), then each wave inverts its share of them, and the inverses go to the
+  // factor storage; the streaming phase below reloads them.
   {
     constexpr int NW = TileCfg<NMAX>::NT / 64;
     constexpr int LD = Lay<NMAX>::LD;
     constexpr int SZ = Lay<NMAX>::SZ;
+    constexpr int EL = Share<NMAX>::ELEMS;
+    constexpr int kBatch = 4;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    T* mine = sl.base + wv * SZ;
     const int nodd = (hi - lo + 1) / 2;
-    for (int r0 = 0; r0 < nodd; r0 += NW) {
-      const int i = r0 + wv;
-      const bool active = i < nodd;
-      const int q = lo + 1 + 2 * i;
-      const int j = q << a.shift;
-      if (active) {
-        const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
-        for (int e = lane; e < NMAX * NMAX; e += 64) {
-          const int r = e / NMAX, c = e % NMAX;
-          T v;
-          if (r < n && c < n) {
-            const int o = c <= r ? r * n + c : c * n + r;
-            v = static_cast<T>(D[o]);
-            if constexpr (!FIRST) {
-              const size_t b = ((size_t)s * a.stride + q) * nn;
-              v = (v + reinterpret_cast<const T*>(a.accR_in)[b + o]) +
-                  reinterpret_cast<const T*>(a.accL_in)[b + o];
-            }
-          } else {
-            v = (r == c) ? T(1) : T(0);
+    const int cap = min(kBatch, 2 * a.Tw + 3);
+    for (int i0 = 0; i0 < nodd; i0 += cap) {
+      const int cnt = min(cap, nodd - i0);
+      double dv[kBatch][EL];
+      T av[kBatch][EL];
+      // one 32-bit offset per element serves every block (buffer loads, the block
+      // bases stay scalar); out-of-range elements read as zero
+      unsigned off[EL];
+#pragma unroll
+      for (int jj = 0; jj < EL; ++jj) {
+        const int e = Share<NMAX>::elem(jj);
+        const int r = e / NMAX, c = e % NMAX;
+        const bool in = e < NMAX * NMAX && r < n && c < n;
+        off[jj] = in ? (unsigned)(c <= r ? r * n + c : c * n + r) : kOutOfRange / 8;
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (b < cnt) {
+          const int q = lo + 1 + 2 * (i0 + b);
+          const int j = q << a.shift;
+          const auto rd = block_rsrc(a.D + ((size_t)s * N + (N - j)) * nn,
+                                     (unsigned)nn * sizeof(double));
+          [[maybe_unused]] __amdgpu_buffer_rsrc_t rr, rl;
+          if constexpr (!FIRST) {
+            const size_t ob = ((size_t)s * a.stride + q) * nn;
+            rr = block_rsrc(reinterpret_cast<const T*>(a.accR_in) + ob, (unsigned)nn * sizeof(T));
+            rl = block_rsrc(reinterpret_cast<const T*>(a.accL_in) + ob, (unsigned)nn * sizeof(T));
           }
-          mine[r * LD + c] = v;
+#pragma unroll
+          for (int jj = 0; jj < EL; ++jj) {
+            dv[b][jj] = buf_load_f64(rd, off[jj] * 8u);
+            if constexpr (!FIRST) {
+              if constexpr (sizeof(T) == 8)
+                av[b][jj] = buf_load_f64(rr, off[jj] * 8u) + buf_load_f64(rl, off[jj] * 8u);
+              else
+                av[b][jj] = buf_load_f32(rr, off[jj] * 4u) + buf_load_f32(rl, off[jj] * 4u);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (b < cnt) {
+          T* dst = sl.base + b * SZ;
+#pragma unroll
+          for (int jj = 0; jj < EL; ++jj) {
+            const int e = Share<NMAX>::elem(jj);
+            if (e >= NMAX * NMAX) continue;
+            const int r = e / NMAX, c = e % NMAX;
+            T v;
+            if (r < n && c < n) {
+              v = static_cast<T>(dv[b][jj]);
+              if constexpr (!FIRST) v = v + av[b][jj];
+            } else {
+              v = (r == c) ? T(1) : T(0);
+            }
+            dst[r * LD + c] = v;
+          }
         }
       }
       __syncthreads();
-      if (active) {
-        const int fail = wave_potrf_inv<T, NMAX>(mine);
+      for (int b = wv; b < cnt; b += NW) {
+        const int j = (lo + 1 + 2 * (i0 + b)) << a.shift;
+        const int fail = wave_potrf_inv<T, NMAX>(sl.base + b * SZ);
         if (fail >= 0 && fail < n && lane == 0)
           atomicMin(a.info, chain_row0 + (unsigned long long)a.permpos[j - 1] * n + fail + 1);
       }
       __syncthreads();
-      if (active) {
-        T* Lo = Linv + (size_t)(j - 1) * nn;
-        for (int e = lane; e < n * n; e += 64) Lo[e] = mine[(e / n) * LD + e % n];
+      for (int b = 0; b < cnt; ++b) {
+        const int j = (lo + 1 + 2 * (i0 + b)) << a.shift;
+        slot_store<T, NMAX>(Linv + (size_t)(j - 1) * nn, sl.base + b * SZ, n);
       }
+      __syncthreads();
     }
     __threadfence_block();
-    __syncthreads();
   }
-  NodeFetch<T, NMAX, FIRST> pf;
-  if (lo + 1 <= hi) pf.issue(a, s, lo + 1);
+  FetchOdd<T, NMAX, FIRST> fo;
+  FetchEven<T, NMAX, FIRST> fe;
+  if (lo + 1 <= hi) fo.issue(a, s, lo + 1);
+  if (lo + 2 <= hi) fe.issue(a, s, lo + 2);
 
   if (has_left) {
     // The left boundary node keeps the updates it received while it was a window
@@ -330,9 +409,17 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
     unsigned todo;
     if (!is_rb) {
       v = __builtin_ctz((unsigned)q);
-      pf.commit(sl.A(v), sl.Cp(v), n);
+      if (q & 1)
+        fo.commit(sl.A(v), sl.Cp(v), n);
+      else
+        fe.commit(sl.A(v), sl.Cp(v), n);
       __syncthreads();
-      if (q + 1 <= hi) pf.issue(a, s, q + 1);
+      if (q + 2 <= hi) {
+        if (q & 1)
+          fo.issue(a, s, q + 2);
+        else
+          fe.issue(a, s, q + 2);
+      }
       todo = live & ((1u << v) - 1u);
     } else {
       todo = live;
