@@ -67,6 +67,21 @@ struct RegBlock {
     }
   }
 
+  // FULL (n == NMAX known at compile time): every element of the lane sits at a fixed
+  // offset from one lane base address.  Otherwise the block is read through a buffer
+  // resource and out-of-range elements read as zero.
+  template <bool TRANS, bool FULL>
+  __device__ void load_fixed(const T* __restrict__ g, int n) {
+    const int o = out_index(), b = base();
+    if constexpr (FULL) {
+      const T* p = TRANS ? g + b * NMAX + o : g + o * NMAX + b;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) v[e] = TRANS ? p[e * NMAX] : p[e];
+    } else {
+      load_buf<TRANS>(block_rsrc(g, (unsigned)(n * n) * sizeof(T)), n);
+    }
+  }
+
   // Same as load, through a buffer resource covering the n x n block (out-of-range
   // elements read as zero without a branch or a select).
   template <bool TRANS>

@@ -11,9 +11,11 @@
 // The permutation Pi_i (Algorithm 2, lines 2 and 11) is applied as an index map:
 // chain position j reads and writes stage N-j of the natural-order vectors.
 //
-// One wave per position.  Factor blocks are held in registers (RegBlock) and the next
-// block is loaded while the current one is applied; the neighbour vectors go through
-// a double-buffered LDS array so that their loads also overlap the products.
+// Factor blocks are held in registers (RegBlock).  In the level kernels every block
+// a position needs is loaded at once, spread over up to four waves; the x_1 kernels
+// pipeline their pulls two deep through a double-buffered LDS vector array.
+#include <algorithm>
+
 #include "bmpc_internal.h"
 #include "blockops.h"
 #include "regblock.h"
@@ -141,13 +143,64 @@ __device__ inline void scatter_value(const SolveArgs& a, int q, size_t off, doub
   }
 }
 
+// Level kernels of both sweeps.  A position applies its own L_jj^{-1} after
+// subtracting the products of the factor blocks it pulls, each with the vector of a
+// neighbour.  Forward (position j of level l): pull 2t is the G_r of the left
+// neighbour j-2^t, pull 2t+1 the G_l of the right neighbour j+2^t (t < l-1).
+// Backward: pull 0 is G_l(j)^T with x of the left neighbour, pull 1 is G_r(j)^T with
+// x of the right neighbour (or of X).  Each wave takes kPullsPerWave consecutive pulls
+// and issues all of their loads at once (wave 0 also loads L_jj^{-1}); the workgroup
+// has up to kLevelMaxWaves waves and further pulls go round in turns.  Partial sums
+// are combined in wave order.
+constexpr int kPullsPerWave = 2;
+constexpr int kLevelMaxWaves = 4;
+
+// Dynamic LDS of a level workgroup with W waves and nrhs right-hand sides:
+// vbuf[W][kPullsPerWave][nrhs][NMAX], partial[W][nrhs][NMAX], rhs[nrhs][NMAX].
 template <typename T, int NMAX>
-__global__ void __launch_bounds__(NT) solve_fwd_level_kernel(SolveArgs a, int level, int count) {
+inline size_t level_smem_bytes(int waves, int nrhs) {
+  return (size_t)(waves * kPullsPerWave + waves + 1) * nrhs * NMAX * sizeof(T);
+}
+
+// One neighbour vector (nrhs x n, zero padded) staged by the lanes of one wave.
+template <typename T, int NMAX>
+struct WaveVec {
+  static constexpr int PER = (kMaxRhs * NMAX + 63) / 64;
+  T v[PER];
+  __device__ void load(const T* __restrict__ src, int n, int nrhs) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = lane + k * 64;
+      const int q = idx / NMAX, i = idx % NMAX;
+      v[k] = (q < nrhs && i < n) ? src[q * n + i] : T(0);
+    }
+  }
+  __device__ void store(T (*dst)[NMAX], int nrhs) const {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = lane + k * 64;
+      const int q = idx / NMAX;
+      if (q < nrhs) dst[q][idx % NMAX] = v[k];
+    }
+  }
+};
+
+template <typename T, int NMAX, bool FWD, bool FULL>
+__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveArgs a, int level,
+                                                                         int count) {
   if (a.done && *a.done) return;
   typedef RegBlock<T, NMAX> RB;
-  __shared__ SolveSmem<T, NMAX> sm;
+  constexpr int P = kPullsPerWave;
   const int n = a.n, N = a.N, nrhs = a.nrhs, m = a.m;
   const size_t nn = (size_t)n * n;
+  const int W = blockDim.x >> 6, wv = threadIdx.x >> 6;
+  extern __shared__ __align__(16) unsigned char level_smem[];
+  typedef T Vec[NMAX];
+  Vec* vbuf = reinterpret_cast<Vec*>(level_smem);          // [(w * P + u) * nrhs + q]
+  Vec* partial = vbuf + (size_t)W * P * nrhs;              // [w * nrhs + q]
+  Vec* rhs = partial + (size_t)W * nrhs;                   // [q]
   const int s = blockIdx.x / count;
   const int i = blockIdx.x - s * count;
   const int j = (2 * i + 1) << (level - 1);
@@ -156,32 +209,109 @@ __global__ void __launch_bounds__(NT) solve_fwd_level_kernel(SolveArgs a, int le
   const T* Gr = reinterpret_cast<const T*>(a.Gr) + (size_t)s * gstride * nn;
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
+  T* yj = y + (size_t)(j - 1) * nrhs * n;
+  const int half = 1 << (level - 1);
+  const int npull = FWD ? 2 * (level - 1) : 2;
 
-  RB lin;
-  lin.template load<false>(Linv + (size_t)(j - 1) * nn, n);
-  gather_rhs<T, NMAX>(a, sm.rhs, ((size_t)s * N + (N - j)) * n);
-  T part[kMaxRhs];
-#pragma unroll
-  for (int q = 0; q < kMaxRhs; ++q) part[q] = T(0);
-  // pull 2t: left neighbour j-2^t (row j holds its G_r); 2t+1: right j+2^t (its G_l)
   auto pull = [&](int p, const T*& blk, const T*& vec) -> bool {
-    const int t = p >> 1;
-    const int c = (p & 1) ? j + (1 << t) : j - (1 << t);
-    if (c > m) return false;
-    blk = ((p & 1) ? Gl : Gr) + (size_t)(c - 1) * nn;
-    vec = y + (size_t)(c - 1) * nrhs * n;
+    if constexpr (FWD) {
+      const int t = p >> 1;
+      const int c = (p & 1) ? j + (1 << t) : j - (1 << t);
+      if (c > m) return false;
+      blk = ((p & 1) ? Gl : Gr) + (size_t)(c - 1) * nn;
+      vec = y + (size_t)(c - 1) * nrhs * n;
+    } else {
+      if (p == 0) {
+        if (j - half < 1) return false;
+        blk = Gl + (size_t)(j - 1) * nn;
+        vec = y + (size_t)(j - half - 1) * nrhs * n;
+      } else {
+        const int ir = j + half <= m ? j + half - 1 : N - 1;
+        blk = Gr + (size_t)(j - 1) * nn;
+        vec = y + (size_t)ir * nrhs * n;
+      }
+    }
     return true;
   };
-  pull_products<T, NMAX, false>(2 * (level - 1), pull, n, nrhs, sm.vbuf, part);
-  __syncthreads();
-  subtract_reduced<T, NMAX>(sm.rhs, part, nrhs);
-  __syncthreads();
-  T* yj = y + (size_t)(j - 1) * nrhs * n;
+
+  // right-hand side of the position: the gathered b (forward) or its dy (backward)
+  if (wv == 0) {
+    if constexpr (FWD) {
+      const size_t len = ((size_t)a.S * N + 1) * n;
+      const size_t off = ((size_t)s * N + (N - j)) * n;
+      for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += 64) {
+        const int q = idx / NMAX, ii = idx % NMAX;
+        T v = T(0);
+        if (ii < n) {
+          double bv = a.b[(size_t)q * len + off + ii];
+          if (a.rnorm) {
+            const double rn = a.rnorm[q];
+            bv = rn > 0.0 ? bv / rn : 0.0;
+          }
+          v = static_cast<T>(bv);
+        }
+        rhs[q][ii] = v;
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += 64) {
+        const int q = idx / NMAX, ii = idx % NMAX;
+        rhs[q][ii] = ii < n ? yj[q * n + ii] : T(0);
+      }
+    }
+  }
+
+  RB lin;
+  if (wv == 0) lin.template load_fixed<!FWD, FULL>(Linv + (size_t)(j - 1) * nn, n);
+  for (int base = 0; base == 0 || base < npull; base += W * P) {
+    RB blk[P];
+    WaveVec<T, NMAX> vs[P];
+    bool has[P];
 #pragma unroll
-  for (int q = 0; q < kMaxRhs; ++q) {
-    if (q < nrhs) {
-      const T v = lane_group_sum<RB::LPR>(lin.dot(sm.rhs[q]));
-      if (RB::base() == 0 && RB::out_index() < n) yj[q * n + RB::out_index()] = v;
+    for (int u = 0; u < P; ++u) {
+      const int p = base + wv * P + u;
+      const T* bp = nullptr;
+      const T* vp = nullptr;
+      has[u] = p < npull && pull(p, bp, vp);
+      if (has[u]) {
+        blk[u].template load_fixed<!FWD, FULL>(bp, n);
+        vs[u].load(vp, n, nrhs);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u)
+      if (has[u]) vs[u].store(vbuf + (size_t)(wv * P + u) * nrhs, nrhs);
+    wave_lds_fence();
+    // this wave's partial sums, accumulated over the rounds in its LDS row
+#pragma unroll 1
+    for (int q = 0; q < nrhs; ++q) {
+      T acc = T(0);
+#pragma unroll
+      for (int u = 0; u < P; ++u)
+        if (has[u]) acc += blk[u].dot(vbuf[(size_t)(wv * P + u) * nrhs + q]);
+      acc = lane_group_sum<RB::LPR>(acc);
+      if (RB::base() == 0) {
+        T* dst = &partial[wv * nrhs + q][RB::out_index()];
+        *dst = base == 0 ? acc : *dst + acc;
+      }
+    }
+    wave_lds_fence();
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += 64) {
+    const int q = idx / NMAX, ii = idx % NMAX;
+    T acc = partial[q][ii];
+    for (int w = 1; w < W; ++w) acc += partial[w * nrhs + q][ii];
+    rhs[q][ii] -= acc;
+  }
+  wave_lds_fence();
+  const size_t off = ((size_t)s * N + (N - j)) * n;
+#pragma unroll 1
+  for (int q = 0; q < nrhs; ++q) {
+    const T v = lane_group_sum<RB::LPR>(lin.dot(rhs[q]));
+    if (RB::base() == 0 && RB::out_index() < n) {
+      yj[q * n + RB::out_index()] = v;
+      if constexpr (!FWD) scatter_value(a, q, off + RB::out_index(), static_cast<double>(v));
     }
   }
 }
@@ -361,64 +491,6 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
   }
 }
 
-template <typename T, int NMAX>
-__global__ void __launch_bounds__(NT) solve_bwd_level_kernel(SolveArgs a, int level, int count) {
-  if (a.done && *a.done) return;
-  typedef RegBlock<T, NMAX> RB;
-  __shared__ SolveSmem<T, NMAX> sm;
-  const int n = a.n, N = a.N, nrhs = a.nrhs;
-  const size_t nn = (size_t)n * n;
-  const int s = blockIdx.x / count;
-  const int i = blockIdx.x - s * count;
-  const int j = (2 * i + 1) << (level - 1);
-  const size_t gstride = (size_t)(N > 1 ? N - 1 : 1);
-  const T* Gl = reinterpret_cast<const T*>(a.Gl) + (size_t)s * gstride * nn;
-  const T* Gr = reinterpret_cast<const T*>(a.Gr) + (size_t)s * gstride * nn;
-  const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
-  T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
-
-  RB lin;
-  lin.template load<true>(Linv + (size_t)(j - 1) * nn, n);
-  T* yj = y + (size_t)(j - 1) * nrhs * n;
-  for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
-    const int q = idx / NMAX, ii = idx % NMAX;
-    sm.rhs[q][ii] = ii < n ? yj[q * n + ii] : T(0);
-  }
-  const int jl = j - (1 << (level - 1));
-  const int jr = j + (1 << (level - 1));
-  const int ir = jr <= a.m ? jr - 1 : N - 1;
-  T part[kMaxRhs];
-#pragma unroll
-  for (int q = 0; q < kMaxRhs; ++q) part[q] = T(0);
-  // pull 0: G_l(j)^T x_left ; pull 1: G_r(j)^T x_right (or x_X)
-  auto pull = [&](int p, const T*& blk, const T*& vec) -> bool {
-    if (p == 0) {
-      if (jl < 1) return false;
-      blk = Gl + (size_t)(j - 1) * nn;
-      vec = y + (size_t)(jl - 1) * nrhs * n;
-    } else {
-      blk = Gr + (size_t)(j - 1) * nn;
-      vec = y + (size_t)ir * nrhs * n;
-    }
-    return true;
-  };
-  pull_products<T, NMAX, true>(2, pull, n, nrhs, sm.vbuf, part);
-  __syncthreads();
-  subtract_reduced<T, NMAX>(sm.rhs, part, nrhs);
-  __syncthreads();
-  const size_t off = ((size_t)s * N + (N - j)) * n;
-#pragma unroll
-  for (int q = 0; q < kMaxRhs; ++q) {
-    if (q < nrhs) {
-      const T v = lane_group_sum<RB::LPR>(lin.dot(sm.rhs[q]));
-      if (RB::base() == 0 && RB::out_index() < n) {
-        yj[q * n + RB::out_index()] = v;
-        scatter_value(a, q, off + RB::out_index(), static_cast<double>(v));
-      }
-    }
-  }
-}
-
 #define BMPC_DISPATCH_NMAX(nmax, FN, ...) \
   do {                                    \
     if ((nmax) <= 8)                      \
@@ -433,15 +505,28 @@ template <typename T, int NMAX>
 void fwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
   const int count = level_count(a.m, level);
   if (count <= 0) return;
-  hipLaunchKernelGGL((solve_fwd_level_kernel<T, NMAX>), dim3(a.S * count), dim3(NT), 0, st,
-                     a, level, count);
+  const int pulls = 2 * (level - 1);
+  const int waves =
+      std::max(1, std::min(kLevelMaxWaves, (pulls + kPullsPerWave - 1) / kPullsPerWave));
+  const size_t sh = level_smem_bytes<T, NMAX>(waves, a.nrhs);
+  if (a.n == NMAX)
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, true>), dim3(a.S * count),
+                       dim3(64 * waves), sh, st, a, level, count);
+  else
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, false>), dim3(a.S * count),
+                       dim3(64 * waves), sh, st, a, level, count);
 }
 template <typename T, int NMAX>
 void bwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
   const int count = level_count(a.m, level);
   if (count <= 0) return;
-  hipLaunchKernelGGL((solve_bwd_level_kernel<T, NMAX>), dim3(a.S * count), dim3(NT), 0, st,
-                     a, level, count);
+  const size_t sh = level_smem_bytes<T, NMAX>(1, a.nrhs);
+  if (a.n == NMAX)
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, true>), dim3(a.S * count), dim3(64),
+                       sh, st, a, level, count);
+  else
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, false>), dim3(a.S * count), dim3(64),
+                       sh, st, a, level, count);
 }
 template <typename T, int NMAX>
 void x_fwd_t(const SolveArgs& a, hipStream_t st) {
