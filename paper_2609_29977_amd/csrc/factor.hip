@@ -78,8 +78,8 @@ __device__ inline void slot_load(T* dst, const S* __restrict__ src, int n, bool 
   }
 }
 
-// Register prefetch of chain nodes, issued two positions ahead so that the global
-// loads overlap the work of the position in between.  Odd pass-local positions were
+// Register prefetch of chain nodes, issued a pair of positions ahead so that the
+// global loads overlap the eliminations in between.  Odd pass-local positions were
 // factored by the window prologue: their fetch reloads L^{-1} and the coupling to the
 // successor.  Even positions fetch D plus the updates carried from earlier passes and
 // the coupling.
@@ -409,16 +409,18 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
     unsigned todo;
     if (!is_rb) {
       v = __builtin_ctz((unsigned)q);
-      if (q & 1)
-        fo.commit(sl.A(v), sl.Cp(v), n);
-      else
-        fe.commit(sl.A(v), sl.Cp(v), n);
-      __syncthreads();
-      if (q + 2 <= hi) {
-        if (q & 1)
-          fo.issue(a, s, q + 2);
-        else
-          fe.issue(a, s, q + 2);
+      if (q & 1) {
+        // An odd step eliminates nothing, so it also places the even position q+1
+        // (its slot is free: the previous node of that level is already eliminated)
+        // and then fetches the next pair, which the eliminations of step q+1 hide.
+        fo.commit(sl.A(0), sl.Cp(0), n);
+        if (q + 1 <= hi) {
+          const int v1 = __builtin_ctz((unsigned)(q + 1));
+          fe.commit(sl.A(v1), sl.Cp(v1), n);
+        }
+        __syncthreads();
+        if (q + 2 <= hi) fo.issue(a, s, q + 2);
+        if (q + 3 <= hi) fe.issue(a, s, q + 3);
       }
       todo = live & ((1u << v) - 1u);
     } else {
