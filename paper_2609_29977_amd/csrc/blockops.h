@@ -123,38 +123,37 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
 }
 
 // In place: A (symmetric NMAX x NMAX, lower triangle read) := L^{-1} with L L^T = A.
-// One wave; lane i < NMAX keeps row i of A and row i of Z (Z := I initially) in
-// registers.  Step k forms column k of L (right-looking Cholesky) and applies the
-// same row operations to Z (forward elimination of L Z = I), so Z ends as L^{-1}.
-// Z's rows are kept unscaled: row k is divided by L[k][k] only at the end, and the
-// multiplier used on the rows below carries that division instead.  Rows are
-// broadcast with readlane (wave-uniform scalars), so there are no LDS round trips
-// and no per-lane branches: the trailing update runs on every lane and only ever
-// writes garbage above the diagonal (never read for the result), and the Z update is
-// masked through its multiplier.  Blocks smaller than NMAX must be padded with an
-// identity block.  Returns (on every lane) the 0-based row of the first non-positive
-// pivot, or -1.
+// One wave, two lane groups.  Lane i < NMAX keeps row i of A and runs the
+// right-looking Cholesky sweep: step k forms column k of L (L[i][k] on lane i).
+// Lane NMAX + j keeps column j of Z, the inverse being built by the same elimination
+// applied to the identity with unscaled rows: row c of Z loses (L[c][k] / L[k][k])
+// times row k, and row i is divided by L[i][i] at the end.  Both updates of step k
+// are "entry c -= L[c][k] * y" with a per-lane factor y (L[i][k] on a row lane,
+// Z[k][j] / L[k][k] on a column lane), so one readlane broadcast of L[c][k] and one
+// FMA per column c > k serve the factor and the inverse together.  No per-lane
+// branches: row lanes also update entries above the diagonal, which are never read.
+// Blocks smaller than NMAX must be padded with an identity block.  Returns (on
+// every lane) the 0-based row of the first non-positive pivot, or -1.
 template <typename T, int NMAX, int LD = Lay<NMAX>::LD>
 __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
+  static_assert(2 * NMAX <= 64, "two lane groups per wave");
   const int lane = threadIdx.x & 63;
-  const int row = lane < NMAX ? lane : NMAX - 1;
-  T a[NMAX], z[NMAX];
+  const bool rowl = lane < NMAX;
+  const int j = lane - NMAX;
+  const int idx = rowl ? lane : (j < NMAX ? j : NMAX - 1);
+  T v[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) {
-    a[c] = A[row * LD + c];
-    z[c] = (c == lane) ? T(1) : T(0);
-  }
+  for (int c = 0; c < NMAX; ++c) v[c] = rowl ? A[idx * LD + c] : ((c == idx) ? T(1) : T(0));
   int fail = -1;
-  T myinv = T(1);
+  T dinv[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
-    const T piv = wave_bcast(a[k], k);
+    const T piv = wave_bcast(v[k], k);
     if (fail < 0 && !(piv > T(0))) fail = k;
     const T inv = rsqrt_refined(piv);
-    const T lik = a[k] * inv;  // L[lane][k] for lane >= k (lane k: sqrt(piv))
-    a[k] = lik;
-    myinv = (lane == k) ? inv : myinv;
-    const T zm = (lane > k) ? lik * inv : T(0);
+    dinv[k] = inv;
+    const T lik = v[k] * inv;               // L[i][k] on row lane i (>= k)
+    const T y = rowl ? lik : inv * v[k];    // Z[k][j] / L[k][k] on column lane j
     // broadcasts in groups of BG: the scalar reads of a group are issued together
     // (hiding the read-after-write wait) with bounded temporaries
     constexpr int BG = 8;
@@ -166,22 +165,12 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
         if (c0 + u < NMAX) lc[u] = wave_bcast(lik, c0 + u);
 #pragma unroll
       for (int u = 0; u < BG; ++u)
-        if (c0 + u < NMAX) a[c0 + u] -= lik * lc[u];
-    }
-#pragma unroll
-    for (int c0 = 0; c0 <= k; c0 += BG) {
-      T zk[BG];
-#pragma unroll
-      for (int u = 0; u < BG; ++u)
-        if (c0 + u <= k) zk[u] = wave_bcast(z[c0 + u], k);
-#pragma unroll
-      for (int u = 0; u < BG; ++u)
-        if (c0 + u <= k) z[c0 + u] -= zm * zk[u];
+        if (c0 + u < NMAX) v[c0 + u] -= lc[u] * y;
     }
   }
-  if (lane < NMAX) {
+  if (!rowl && j < NMAX) {
 #pragma unroll
-    for (int c = 0; c < NMAX; ++c) A[lane * LD + c] = (c <= lane) ? z[c] * myinv : T(0);
+    for (int i = 0; i < NMAX; ++i) A[i * LD + j] = (i >= j) ? v[i] * dinv[i] : T(0);
   }
   return fail;
 }
