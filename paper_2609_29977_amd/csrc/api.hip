@@ -570,17 +570,15 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
     timed(p, KC_RESIDUAL, [&] { launch_residual(ra, p->nmax, st); });
     timed(p, KC_RESIDUAL_ROOT, [&] { launch_residual_root(ra, st); });
     timed(p, KC_REFINE_MISC, [&] {
-      launch_maxabs(p->rbuf, nullptr, nrhs, len, p->npart, rnorm, nullptr, p->flags, st);
+      launch_maxabs(p->rbuf, nrhs, len, p->npart, rnorm, p->flags, st);
     });
     if (p->fp64)
       enqueue_solve<double>(p, c);
     else
       enqueue_solve<float>(p, c);
     timed(p, KC_REFINE_MISC, [&] {
-      launch_maxabs(p->rbuf, x, nrhs, len, p->npart, dnorm, xnorm, p->flags, st);
-    });
-    timed(p, KC_REFINE_MISC, [&] {
-      launch_refine_check(dnorm, xnorm, nrhs, tol, p->flags, p->relcorr, st);
+      launch_refine_check(p->rbuf, x, nrhs, len, p->npart, tol, p->flags, p->relcorr, dnorm,
+                          xnorm, st);
     });
   }
   p->last_max_iters = max_iters;
@@ -682,7 +680,12 @@ bmpc_status bmpc_export_tail_factor(bmpc_plan p, int32_t s, double* L, double* F
         L[((size_t)rowpos * n + r) * Nn + (size_t)colpos * n + c] = val(buf, blk * nn + r * n + c);
   };
   const std::vector<int>& pp = p->permpos;
-  for (int j = 1; j <= N; ++j) put(pp[j - 1], pp[j - 1], li, j - 1);
+  // diagonal blocks (inverted) are stored packed by rows
+  for (int j = 1; j <= N; ++j)
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c <= r; ++c)
+        L[((size_t)pp[j - 1] * n + r) * Nn + (size_t)pp[j - 1] * n + c] =
+            val(li, (size_t)(j - 1) * nn + (size_t)r * (r + 1) / 2 + c);
   for (int j = 1; j <= m; ++j) {
     const int v = ctz_host((unsigned)j);
     const int jl = j - (1 << v), jr = j + (1 << v);

@@ -12,7 +12,8 @@
 // or X when j+2^t > m).
 //
 // Factor storage (plan-owned, precision T of the tail factor):
-//   Linv[S][N][n][n]  L_jj^{-1} of position j at index j-1, X at index N-1
+//   Linv[S][N][n][n]  L_jj^{-1} of position j at index j-1, X at index N-1, each
+//                     block packed by rows (element (r, c), c <= r, at r(r+1)/2 + c)
 //   Gl  [S][m][n][n]  factor block of the left neighbour's row, G_l = K[left,j] L_jj^{-T}
 //   Gr  [S][m][n][n]  factor block of the right neighbour's row (or X's row)
 //   F   [S][n][n]     F_{s,1} = C_s L_X^{-T} (the only block of the root row, Thm 1)
@@ -131,13 +132,18 @@ void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st);
 void launch_residual_root(const ResidualArgs& a, hipStream_t st);
 void launch_refine_reset(int* flags, hipStream_t st);
-// out[q] = max_i |v[q][i]| (and, if v2, out2[q] = max |v2[q][i]|), two stages through
-// partial[2][nrhs][kNormBlocks]; skipped when *done is set.
-constexpr int kNormBlocks = 256;
-void launch_maxabs(const double* v, const double* v2, int nrhs, size_t len, double* partial,
-                   double* out, double* out2, const int* done, hipStream_t st);
-void launch_refine_check(const double* dnorm, const double* xnorm, int nrhs,
-                         double tol, int* flags, double* relcorr, hipStream_t st);
+// Infinity norms by a two-stage maximum (kNormBlocks block partials, then one wave),
+// deterministic and NaN-propagating; skipped when *done is set.
+constexpr int kNormBlocks = 1024;
+// out[q] = max_i |v[q][i]|, through partial[nrhs][kNormBlocks]
+void launch_maxabs(const double* v, int nrhs, size_t len, double* partial, double* out,
+                   const int* done, hipStream_t st);
+// dnorm[q] = |d_q|_inf, xnorm[q] = |x_q|_inf (partials in partial[2][nrhs][kNormBlocks]),
+// then the stop test: flags[0] = 1 if dnorm <= tol * xnorm for every q; flags[1] counts
+// the corrections; relcorr = max_q dnorm / xnorm.
+void launch_refine_check(const double* d, const double* x, int nrhs, size_t len,
+                         double* partial, double tol, int* flags, double* relcorr,
+                         double* dnorm, double* xnorm, hipStream_t st);
 
 // number of chain positions eliminated at level l (1-based) of a chain of length m
 __host__ __device__ inline int level_count(int m, int l) {

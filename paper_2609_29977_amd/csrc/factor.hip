@@ -105,7 +105,7 @@ struct FetchOdd {
       const int e = Share<NMAX>::elem(jj);
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
-      li[jj] = in ? Li[r * n + c] : T(0);
+      li[jj] = (in && c <= r) ? Li[r * (r + 1) / 2 + c] : T(0);
       cp[jj] = in ? cpl[r * n + c] : CT(0);
     }
   }
@@ -205,6 +205,21 @@ __device__ inline void slot_store(T* __restrict__ dst, const T* src, int n) {
   }
 }
 
+// Lower triangle of an LDS block to global memory, packed by rows: element (r, c),
+// c <= r, at r (r + 1) / 2 + c (the storage of the inverted diagonal blocks).
+template <typename T, int NMAX>
+__device__ inline void slot_store_packed(T* __restrict__ dst, const T* src, int n) {
+  constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+  for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
+    const int e = Share<NMAX>::elem(j);
+    if (e < NMAX * NMAX) {
+      const int r = e / NMAX, c = e % NMAX;
+      if (r < n && c <= r) dst[r * (r + 1) / 2 + c] = src[r * LD + c];
+    }
+  }
+}
+
 // L_jj^{-1} of the block in Aj (in place) by one wave; which wave does it rotates
 // with the workgroup index so that the latency-bound factorizations of the resident
 // workgroups spread over the SIMDs.
@@ -236,7 +251,7 @@ __device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T*
   mfma_tile_store<T, NMAX, false>(Cj, gr, T(1));
   if (left) mfma_tile_store<T, NMAX, false>(Cl, gl, T(1));
   __syncthreads();
-  if (!have_inverse) slot_store<T, NMAX>(gLinv, Aj, n);
+  if (!have_inverse) slot_store_packed<T, NMAX>(gLinv, Aj, n);
   slot_store<T, NMAX>(gGr, Cj, n);
   if (left) slot_store<T, NMAX>(gGl, Cl, n);
   acc_t ur = mfma_tile_nt<T, NMAX, false>(Cj, Cj);
@@ -358,7 +373,7 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
       __syncthreads();
       for (int b = 0; b < cnt; ++b) {
         const int j = (lo + 1 + 2 * (i0 + b)) << a.shift;
-        slot_store<T, NMAX>(Linv + (size_t)(j - 1) * nn, sl.base + b * SZ, n);
+        slot_store_packed<T, NMAX>(Linv + (size_t)(j - 1) * nn, sl.base + b * SZ, n);
       }
       __syncthreads();
     }
@@ -492,7 +507,7 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
     slot_load<T, NMAX>(Cx, a.C + (size_t)s * nn, n, false);
     __syncthreads();
     factor_diag<T, NMAX>(Ax, chain_row0 + (unsigned long long)a.permpos[N - 1] * n, n, a.info);
-    slot_store<T, NMAX>(Linv + (size_t)(N - 1) * nn, Ax, n);
+    slot_store_packed<T, NMAX>(Linv + (size_t)(N - 1) * nn, Ax, n);
     // F = C L_X^{-T}
     typename Mfma<T>::acc_t f = mfma_tile_nt<T, NMAX, false>(Cx, Ax);
     __syncthreads();

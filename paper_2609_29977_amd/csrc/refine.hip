@@ -183,49 +183,66 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
   }
 }
 
+// Maximum that propagates NaN (so a NaN residual or correction fails the stop test).
+__device__ inline double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
+
 __device__ inline double block_max(double v, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off));
   const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) sh[wv] = v;
   __syncthreads();
   double m = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, sh[i]);
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = nan_max(m, sh[i]);
   __syncthreads();
   return m;
 }
 
-// partial[t][q][blk] = max over this block's slice of |v_t[q][.]| (t = 0: v, 1: v2)
+// partial[t][q][blk] = max over this block's slice of |v_t[q][.]| (t = 0: v, 1: v2).
+// Each thread keeps four independent loads in flight per iteration.
 __global__ void __launch_bounds__(256) maxabs_partial_kernel(const double* v, const double* v2,
                                                              int nrhs, size_t len,
                                                              double* partial, const int* done) {
   if (done && *done) return;
   __shared__ double sh[4];
   const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int t = 0; t < (v2 ? 2 : 1); ++t) {
     const double* src = t == 0 ? v : v2;
     for (int q = 0; q < nrhs; ++q) {
-      double mx = 0.0;
-      for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
-        mx = fmax(mx, fabs(src[(size_t)q * len + i]));
-      mx = block_max(mx, sh);
+      const double* p = src + (size_t)q * len;
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+      size_t i = t0;
+      for (; i + 3 * stride < len; i += 4 * stride) {
+        const double a0 = p[i], a1 = p[i + stride], a2 = p[i + 2 * stride], a3 = p[i + 3 * stride];
+        m0 = nan_max(fabs(a0), m0);
+        m1 = nan_max(fabs(a1), m1);
+        m2 = nan_max(fabs(a2), m2);
+        m3 = nan_max(fabs(a3), m3);
+      }
+      for (; i < len; i += stride) m0 = nan_max(fabs(p[i]), m0);
+      double mx = block_max(nan_max(nan_max(m0, m1), nan_max(m2, m3)), sh);
       if (threadIdx.x == 0) partial[((size_t)t * nrhs + q) * gridDim.x + blockIdx.x] = mx;
     }
   }
 }
 
+// max over the block partials of one vector and right-hand side, on one wave
+__device__ inline double wave_reduce_partials(const double* part, int blocks) {
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < blocks; i += 64) mx = nan_max(part[i], mx);
+  for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
+  return mx;
+}
+
 __global__ void __launch_bounds__(64) maxabs_final_kernel(const double* partial, int blocks,
-                                                          int nrhs, int two, double* out,
-                                                          double* out2, const int* done) {
+                                                          int nrhs, double* out,
+                                                          const int* done) {
   if (done && *done) return;
-  for (int t = 0; t < two; ++t)
-    for (int q = 0; q < nrhs; ++q) {
-      double mx = 0.0;
-      for (int i = threadIdx.x; i < blocks; i += 64)
-        mx = fmax(mx, partial[((size_t)t * nrhs + q) * blocks + i]);
-      for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-      if (threadIdx.x == 0) (t == 0 ? out : out2)[q] = mx;
-    }
+  for (int q = 0; q < nrhs; ++q) {
+    const double mx = wave_reduce_partials(partial + (size_t)q * blocks, blocks);
+    if (threadIdx.x == 0) out[q] = mx;
+  }
 }
 
 // flags[0] = done, flags[1] = corrections applied
@@ -236,19 +253,31 @@ __global__ void refine_reset_kernel(int* flags) {
   }
 }
 
-__global__ void refine_check_kernel(const double* dnorm, const double* xnorm, int nrhs,
-                                    double tol, int* flags, double* relcorr) {
-  if (threadIdx.x != 0 || flags[0]) return;
-  flags[1] += 1;
+// |d|_inf and |x|_inf from the block partials, then the stop test
+// |d_q|_inf <= tol |x_q|_inf for every right-hand side.
+__global__ void __launch_bounds__(64) refine_check_kernel(const double* partial, int blocks,
+                                                          int nrhs, double tol, int* flags,
+                                                          double* relcorr, double* dnorm,
+                                                          double* xnorm) {
+  if (flags[0]) return;
   bool ok = true;
   double worst = 0.0;
   for (int q = 0; q < nrhs; ++q) {
-    const double rel = xnorm[q] > 0.0 ? dnorm[q] / xnorm[q] : dnorm[q];
-    worst = fmax(worst, rel);
-    if (!(dnorm[q] <= tol * xnorm[q])) ok = false;
+    const double d = wave_reduce_partials(partial + (size_t)q * blocks, blocks);
+    const double xv = wave_reduce_partials(partial + ((size_t)nrhs + q) * blocks, blocks);
+    const double rel = xv > 0.0 ? d / xv : d;
+    worst = nan_max(worst, rel);
+    if (!(d <= tol * xv)) ok = false;
+    if (threadIdx.x == 0) {
+      dnorm[q] = d;
+      xnorm[q] = xv;
+    }
   }
-  *relcorr = worst;
-  if (ok) flags[0] = 1;
+  if (threadIdx.x == 0) {
+    flags[1] += 1;
+    *relcorr = worst;
+    if (ok) flags[0] = 1;
+  }
 }
 
 }  // namespace
@@ -268,22 +297,25 @@ void launch_residual_root(const ResidualArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(residual_root_kernel, dim3(1), dim3(1024), 0, st, a);
 }
 
-void launch_maxabs(const double* v, const double* v2, int nrhs, size_t len, double* partial,
-                   double* out, double* out2, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(maxabs_partial_kernel, dim3(kNormBlocks), dim3(256), 0, st, v, v2, nrhs,
-                     len, partial, done);
+void launch_maxabs(const double* v, int nrhs, size_t len, double* partial, double* out,
+                   const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(maxabs_partial_kernel, dim3(kNormBlocks), dim3(256), 0, st, v,
+                     (const double*)nullptr, nrhs, len, partial, done);
   hipLaunchKernelGGL(maxabs_final_kernel, dim3(1), dim3(64), 0, st, partial, kNormBlocks, nrhs,
-                     v2 ? 2 : 1, out, out2, done);
+                     out, done);
 }
 
 void launch_refine_reset(int* flags, hipStream_t st) {
   hipLaunchKernelGGL(refine_reset_kernel, dim3(1), dim3(64), 0, st, flags);
 }
 
-void launch_refine_check(const double* dnorm, const double* xnorm, int nrhs, double tol,
-                         int* flags, double* relcorr, hipStream_t st) {
-  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(64), 0, st, dnorm, xnorm, nrhs, tol,
-                     flags, relcorr);
+void launch_refine_check(const double* d, const double* x, int nrhs, size_t len,
+                         double* partial, double tol, int* flags, double* relcorr,
+                         double* dnorm, double* xnorm, hipStream_t st) {
+  hipLaunchKernelGGL(maxabs_partial_kernel, dim3(kNormBlocks), dim3(256), 0, st, d, x, nrhs, len,
+                     partial, (const int*)flags);
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(64), 0, st, (const double*)partial,
+                     kNormBlocks, nrhs, tol, flags, relcorr, dnorm, xnorm);
 }
 
 }  // namespace bmpc

@@ -98,6 +98,24 @@ struct RegBlock {
     }
   }
 
+  // Lower-triangular block stored packed by rows (element (r, c), c <= r, at
+  // r (r + 1) / 2 + c); entries above the diagonal and padding read as zero.
+  template <bool TRANS>
+  __device__ void load_packed(const T* __restrict__ g, int n) {
+    const int o = out_index(), b = base();
+    const auto rs = block_rsrc(g, (unsigned)(n * (n + 1) / 2) * sizeof(T));
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int r = TRANS ? b + e : o, c = TRANS ? o : b + e;
+      const bool ok = c <= r && r < n;
+      const unsigned off = ok ? (unsigned)(r * (r + 1) / 2 + c) * sizeof(T) : kOutOfRange;
+      if constexpr (sizeof(T) == 8)
+        v[e] = buf_load_f64(rs, off);
+      else
+        v[e] = buf_load_f32(rs, off);
+    }
+  }
+
   // partial sum of this lane's elements against vec[base .. base+EPL) (LDS, padded)
   __device__ T dot(const T* vec) const {
     const int b = base();

@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
   }
 
   RB lin;
-  if (wv == 0) lin.template load_fixed<!FWD, FULL>(Linv + (size_t)(j - 1) * nn, n);
+  if (wv == 0) lin.template load_packed<!FWD>(Linv + (size_t)(j - 1) * nn, n);
   for (int base = 0; base == 0 || base < npull; base += W * P) {
     RB blk[P];
     WaveVec<T, NMAX> vs[P];
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
 
   RB lin, fb;
-  lin.template load<false>(Linv + (size_t)(N - 1) * nn, n);
+  lin.template load_packed<false>(Linv + (size_t)(N - 1) * nn, n);
   fb.template load<false>(reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n);
   gather_rhs<T, NMAX>(a, sm.rhs, ((size_t)s * N + 0) * n);
   T part[kMaxRhs];
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* yx = reinterpret_cast<T*>(a.y) + ((size_t)s * N + (N - 1)) * nrhs * n;
   RB lin, fb;
-  lin.template load<true>(Linv + (size_t)(N - 1) * nn, n);
+  lin.template load_packed<true>(Linv + (size_t)(N - 1) * nn, n);
   fb.template load<true>(reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n);
   for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
     const int q = idx / NMAX, i = idx % NMAX;
