@@ -73,6 +73,66 @@ def measured_traffic(kernel_class, digest):
     return ent.get("bytes_per_launch")
 
 
+def bench_gradients(args):
+    """Gradient workload: 64 independent FP64 systems (S=128, N=64, n=16), loss
+    0.5 ||x||^2; one step = forward (factor + solve) and backward (adjoint solve +
+    block gradients) of every system through the autograd Function."""
+    import numpy as np
+    import torch
+
+    from paper_2609_29977_amd.autograd import batched_branch_solve
+    from synth.branch_system import make_system
+
+    B, S, N, n = 64, 128, 64, 16
+    t0 = time.perf_counter()
+    systems = [make_system(S, N, n, 1, 1e-2, 100 + i) for i in range(B)]
+    log(f"generated {B} systems in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    st = lambda name: torch.from_numpy(np.stack([getattr(s, name) for s in systems])).to(dev)
+    D, E, C, R, b = st("D"), st("E"), st("C"), st("R"), st("b")
+    params = [D, E, C, R, b]
+    for p_ in params:
+        p_.requires_grad_()
+
+    def step():
+        for p_ in params:
+            p_.grad = None
+        x = batched_branch_solve(D, E, C, R, b, "fp64")
+        (0.5 * (x * x).sum()).backward()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - w0) * 1e3)
+    err = None
+    if not args.no_cpu:
+        from oracle import gradients
+        worst = 0.0
+        for i in (0, B - 1):
+            s = systems[i]
+            _, _, (db, dD, dE, dC, dR) = gradients.loss_gradients(s.D, s.E, s.C, s.R, s.b)
+            for got, ref in ((b.grad[i], db), (D.grad[i], dD), (E.grad[i], dE),
+                             (C.grad[i], dC), (R.grad[i], dR)):
+                worst = max(worst, float(np.max(np.abs(got.cpu().numpy() - ref)) /
+                                         np.max(np.abs(ref))))
+        err = worst
+    ms = statistics.median(times)
+    out = {"metric": "gradient workload: forward+backward of 64 systems (S=128 N=64 n=16, FP64)",
+           "value": round(B / (ms * 1e-3), 1), "unit": "systems/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "p99_ms": round(sorted(times)[max(0, int(0.99 * len(times)) - 1)], 4),
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "c5", "systems": B, "S": S, "N": N, "n": n},
+           "max_rel_err_vs_oracle_grad": err}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -97,6 +157,9 @@ def main():
 
     from paper_2609_29977_amd import bmpc
     from synth.branch_system import CONFIGS, make_config
+
+    if args.config == "c5":
+        return bench_gradients(args)
 
     S, N, n, nrhs, delta = CONFIGS[args.config]
     t0 = time.perf_counter()

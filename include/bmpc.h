@@ -134,6 +134,25 @@ bmpc_status bmpc_refine(bmpc_plan plan, const double* D, const double* E,
                         const double* C, const double* R, const double* b, double* x,
                         double tol, int32_t max_iters);
 
+/* Gradients of a loss through x = K^{-1} b (not one of the paper's algorithms; the
+ * derivative of its linear solve).  Differentiating K x = b for a loss l with
+ * g = dl/dx gives the adjoint lam = K^{-1} g (K is symmetric: call bmpc_solve on g
+ * with the same factor), dl/db = lam and the dense gradient dl/dK = -lam x^T summed
+ * over the right-hand sides.  This call writes what each block array receives from
+ * the entries of K it fills (eq. (root_coupled_matrix), eq. (tail_block_tridiagonal)):
+ *   dD[s][k] = -sym(sum_q lam_{s,k} x_{s,k}^T)     (both triangles written)
+ *   dE[s][k] = -sum_q (lam_{s,k+1} x_{s,k}^T + x_{s,k+1} lam_{s,k}^T)
+ *   dC[s]    = -sum_q (lam_0 x_{s,0}^T + x_0 lam_{s,0}^T)
+ *   dR       = -sym(sum_q lam_0 x_0^T)
+ * with sym(A) = (A + A^T)/2 (symmetric arguments get symmetric gradients), x_{s,k}
+ * the stage-k part of tail s and x_0 the root part.  x, lam: device arrays
+ * [nrhs][(S*N+1)*n] in the layout of b.  dD [S][N][n][n], dE [S][N-1][n][n],
+ * dC [S][n][n], dR [n][n]: device arrays, overwritten; any may be NULL to skip it
+ * (dE is ignored when N == 1).  Needs no factor.  Asynchronous on the plan's stream.
+ * BMPC_ERR_INVALID for a NULL plan, x or lam. */
+bmpc_status bmpc_grad_blocks(bmpc_plan plan, const double* x, const double* lam, double* dD,
+                             double* dE, double* dC, double* dR);
+
 /* Synchronizes the plan's stream.  *info = 0 after a successful factor; otherwise
  * the 1-based natural row index (tails first, root last, as in b) of the first
  * non-positive pivot in the elimination order Pi, and the call returns

@@ -1,0 +1,92 @@
+"""torch.autograd support: x = K^{-1} b differentiable in D, E, C, R and b.
+
+Forward: factor and solve through the C ABI (FP64, or FP32 with iterative
+refinement).  Backward: the adjoint lam = K^{-1} g is one more solve with the same
+factor (K is symmetric; refined like the forward solve in FP32 plans), db = lam, and the block gradients come from
+bmpc_grad_blocks (dD and dR symmetric, see include/bmpc.h).  All arithmetic runs in
+the HIP library; this module only moves tensors.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import bmpc
+
+# Plans are reused across calls of the same shape: a forward takes a plan from the
+# pool (its factor must survive until the backward), the backward returns it.
+_POOL: dict = {}
+
+
+def _acquire(S, N, n, nrhs, precision):
+    key = (S, N, n, nrhs, bmpc._prec(precision), torch.cuda.current_device())
+    free = _POOL.get(key)
+    if free:
+        return key, free.pop()
+    return key, bmpc.Plan(S, N, n, nrhs, precision)
+
+
+def _release(key, plan):
+    _POOL.setdefault(key, []).append(plan)
+
+
+def clear_plan_pool():
+    """Destroy the pooled plans (frees their device workspaces)."""
+    for plans in _POOL.values():
+        for p in plans:
+            p.close()
+    _POOL.clear()
+
+
+class BranchSolve(torch.autograd.Function):
+    """x = K(D, E, C, R)^{-1} b for one system; tensors in the layout of include/bmpc.h
+    with b of shape [nrhs, (S*N+1)*n]."""
+
+    @staticmethod
+    def forward(ctx, D, E, C, R, b, precision="fp64", refine_tol=1e-12, refine_iters=10):
+        S, N, n = D.shape[0], D.shape[1], D.shape[2]
+        nrhs = b.shape[0]
+        key, plan = _acquire(S, N, n, nrhs, precision)
+        D, C, R, b = D.contiguous(), C.contiguous(), R.contiguous(), b.contiguous()
+        E = E.contiguous() if N > 1 else None
+        plan.factor(D, E, C, R)
+        if plan.precision == bmpc.FP64:
+            x = plan.solve(b)
+        else:
+            x = plan.refine(D, E, C, R, b, tol=refine_tol, max_iters=refine_iters)
+        ctx.plan = plan
+        ctx.key = key
+        ctx.refine = (refine_tol, refine_iters)
+        if plan.precision == bmpc.FP64:
+            ctx.save_for_backward(x)
+        else:
+            ctx.save_for_backward(x, D, E if N > 1 else torch.empty(0, device=D.device), C, R)
+        ctx.N = N
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        plan = ctx.plan
+        if plan.precision == bmpc.FP64:
+            (x,) = ctx.saved_tensors
+            lam = plan.solve(gx.contiguous())
+        else:
+            # the adjoint is refined like the forward solve (FP64 residuals)
+            x, D, E, C, R = ctx.saved_tensors
+            tol, iters = ctx.refine
+            lam = plan.refine(D, E if ctx.N > 1 else None, C, R, gx.contiguous(), tol=tol,
+                              max_iters=iters)
+        dD, dE, dC, dR = plan.grad_blocks(x, lam)
+        ctx.plan = None
+        _release(ctx.key, plan)
+        return dD, (dE if ctx.N > 1 else None), dC, dR, lam, None, None, None
+
+
+def branch_solve(D, E, C, R, b, precision="fp64"):
+    """Differentiable solve of one root-coupled branch system."""
+    return BranchSolve.apply(D, E, C, R, b, precision)
+
+
+def batched_branch_solve(D, E, C, R, b, precision="fp64"):
+    """Independent systems stacked on a leading batch dimension, solved one by one."""
+    return torch.stack([BranchSolve.apply(D[i], E[i], C[i], R[i], b[i], precision)
+                        for i in range(D.shape[0])])

@@ -24,7 +24,7 @@ EXPORTED = [
     "bmpc_export_root_factor", "bmpc_set_profiling", "bmpc_get_kernel_times",
     "bmpc_reset_kernel_times", "bmpc_kernel_class_name", "bmpc_kernel_class_count",
     "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
-    "bmpc_cost_model",
+    "bmpc_cost_model", "bmpc_grad_blocks",
 ]
 
 
@@ -99,6 +99,7 @@ def lib():
         "bmpc_ordering": [i32, P(i32)],
         "bmpc_structure": [i32, P(i32), P(i32), i64, P(i64)],
         "bmpc_cost_model": [P(_Dims), i32, P(_Options), P(_Cost)],
+        "bmpc_grad_blocks": [vp, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -254,6 +255,25 @@ class Plan:
         _check(lib().bmpc_refine(self._h, *blocks, pb, px, float(tol), int(max_iters)),
                "bmpc_refine")
         return x
+
+    def grad_blocks(self, x, lam):
+        """(dD, dE, dC, dR) of a loss through x = K^{-1} b, from the solution x and the
+        adjoint lam = K^{-1} dloss/dx (see bmpc_grad_blocks)."""
+        import torch
+        S, N, n = self.S, self.N, self.n
+        f64 = torch.float64
+        px = _ptr(x, "x", f64, self.nrhs * self.length)
+        pl = _ptr(lam, "lam", f64, self.nrhs * self.length)
+        dev = x.device
+        dD = torch.empty((S, N, n, n), dtype=f64, device=dev)
+        dE = torch.empty((S, max(N - 1, 0), n, n), dtype=f64, device=dev)
+        dC = torch.empty((S, n, n), dtype=f64, device=dev)
+        dR = torch.empty((n, n), dtype=f64, device=dev)
+        _check(lib().bmpc_grad_blocks(self._h, px, pl, ctypes.c_void_p(dD.data_ptr()),
+                                      ctypes.c_void_p(dE.data_ptr()) if N > 1 else None,
+                                      ctypes.c_void_p(dC.data_ptr()),
+                                      ctypes.c_void_p(dR.data_ptr())), "bmpc_grad_blocks")
+        return dD, dE, dC, dR
 
     def info(self) -> int:
         v = ctypes.c_int64(0)

@@ -585,6 +585,24 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
   return last_error_status();
 }
 
+bmpc_status bmpc_grad_blocks(bmpc_plan p, const double* x, const double* lam, double* dD,
+                             double* dE, double* dC, double* dR) {
+  if (!p || !x || !lam) return BMPC_ERR_INVALID;
+  GradArgs g{};
+  g.S = p->d.S;
+  g.N = p->d.N;
+  g.n = p->d.n;
+  g.nrhs = p->d.nrhs;
+  g.x = x;
+  g.lam = lam;
+  g.dD = dD;
+  g.dE = p->d.N > 1 ? dE : nullptr;
+  g.dC = dC;
+  g.dR = dR;
+  timed(p, KC_GRAD_BLOCKS, [&] { launch_grad_blocks(g, p->stream); });
+  return last_error_status();
+}
+
 bmpc_status bmpc_get_info(bmpc_plan p, int64_t* info) {
   if (!p || !info) return BMPC_ERR_INVALID;
   unsigned long long v = 0;
@@ -741,7 +759,7 @@ const char* bmpc_kernel_class_name(int32_t cls) {
       "factor_init",  "factor_first_pass", "factor_mid_pass", "factor_final_pass",
       "root_reduce",  "root_potrf",        "solve_fwd",       "solve_x_fwd",
       "solve_root",   "solve_x_bwd",       "solve_bwd",       "residual",
-      "residual_root", "refine_misc"};
+      "residual_root", "refine_misc",     "grad_blocks"};
   if (cls < 0 || cls >= KC_COUNT) return "";
   return names[cls];
 }

@@ -46,6 +46,7 @@ enum KernelClass : int {
   KC_RESIDUAL,       // FP64 tail residual b - K x
   KC_RESIDUAL_ROOT,  // FP64 root residual
   KC_REFINE_MISC,    // refinement bookkeeping (norm reset, stop test)
+  KC_GRAD_BLOCKS,    // block gradients through the solve
   KC_COUNT
 };
 
@@ -109,6 +110,16 @@ struct ResidualArgs {
   const int* done;
 };
 
+struct GradArgs {
+  int S, N, n, nrhs;
+  const double* x;       // [nrhs][len] solution
+  const double* lam;     // [nrhs][len] adjoint K^{-1} g
+  double* dD;            // [S][N][n][n] or null
+  double* dE;            // [S][N-1][n][n] or null
+  double* dC;            // [S][n][n] or null
+  double* dR;            // [n][n] or null
+};
+
 // launchers (defined next to their kernels)
 template <typename T>
 void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st);
@@ -130,6 +141,7 @@ template <typename T>
 void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st);
 
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st);
+void launch_grad_blocks(const GradArgs& a, hipStream_t st);
 void launch_residual_root(const ResidualArgs& a, hipStream_t st);
 void launch_refine_reset(int* flags, hipStream_t st);
 // Infinity norms by a two-stage maximum (kNormBlocks block partials, then one wave),

@@ -1,0 +1,82 @@
+// Block gradients of a loss through the solve x = K^{-1} b (gfx950).
+//
+// Differentiating K x = b: with lam = K^{-1} g (g = dloss/dx, one more solve with the
+// same factor) the dense gradient is dK = -lam x^T, summed over the right-hand sides.
+// Each block array collects the entries of K it fills (eq. (root_coupled_matrix),
+// eq. (tail_block_tridiagonal)): D and R symmetrically (sym(A) = (A + A^T) / 2),
+// E[s][k] at (k+1, k) and transposed at (k, k+1), C[s] at (root, stage 0) and
+// transposed at (stage 0, root).  One workgroup per tail stage writes dD and dE of
+// that stage (and dC for stage 0); one more workgroup writes dR.  The vectors are
+// staged in LDS; every output element is written once, coalesced.  HBM-bound on the
+// writes: 8 n^2 bytes per D, E and C block.
+#include "bmpc_internal.h"
+
+namespace bmpc {
+
+namespace {
+
+constexpr int GT = 256;
+
+__global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a) {
+  __shared__ double xs[kMaxRhs][3][32];  // x of stage k, stage k+1, root
+  __shared__ double ls[kMaxRhs][3][32];  // lam of the same
+  const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
+  const size_t nn = (size_t)n * n;
+  const size_t len = ((size_t)S * N + 1) * n;
+  const size_t root = (size_t)S * N * n;
+  const bool is_root = blockIdx.x == (unsigned)(S * N);
+  const int s = is_root ? 0 : blockIdx.x / N;
+  const int k = is_root ? 0 : blockIdx.x - s * N;
+  for (int idx = threadIdx.x; idx < nrhs * 3 * n; idx += GT) {
+    const int q = idx / (3 * n), rem = idx - q * 3 * n, w = rem / n, i = rem - w * n;
+    size_t off;
+    bool ok = true;
+    if (w == 2) {
+      off = root + i;
+    } else {
+      const int st = k + w;
+      ok = !is_root && st < N;
+      off = ((size_t)s * N + (ok ? st : 0)) * n + i;
+    }
+    xs[q][w][i] = ok ? a.x[(size_t)q * len + off] : 0.0;
+    ls[q][w][i] = ok ? a.lam[(size_t)q * len + off] : 0.0;
+  }
+  __syncthreads();
+  if (is_root) {
+    if (!a.dR) return;
+    for (int e = threadIdx.x; e < n * n; e += GT) {
+      const int r = e / n, c = e - r * n;
+      double acc = 0.0;
+      for (int q = 0; q < nrhs; ++q) acc += ls[q][2][r] * xs[q][2][c] + ls[q][2][c] * xs[q][2][r];
+      a.dR[e] = -0.5 * acc;
+    }
+    return;
+  }
+  const size_t blk = (size_t)s * N + k;
+  for (int e = threadIdx.x; e < n * n; e += GT) {
+    const int r = e / n, c = e - r * n;
+    if (a.dD) {
+      double acc = 0.0;
+      for (int q = 0; q < nrhs; ++q) acc += ls[q][0][r] * xs[q][0][c] + ls[q][0][c] * xs[q][0][r];
+      a.dD[blk * nn + e] = -0.5 * acc;
+    }
+    if (a.dE && k + 1 < N) {
+      double acc = 0.0;
+      for (int q = 0; q < nrhs; ++q) acc += ls[q][1][r] * xs[q][0][c] + xs[q][1][r] * ls[q][0][c];
+      a.dE[((size_t)s * (N - 1) + k) * nn + e] = -acc;
+    }
+    if (a.dC && k == 0) {
+      double acc = 0.0;
+      for (int q = 0; q < nrhs; ++q) acc += ls[q][2][r] * xs[q][0][c] + xs[q][2][r] * ls[q][0][c];
+      a.dC[(size_t)s * nn + e] = -acc;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_grad_blocks(const GradArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(grad_blocks_kernel, dim3((unsigned)(a.S * a.N + 1)), dim3(GT), 0, st, a);
+}
+
+}  // namespace bmpc
