@@ -26,6 +26,13 @@
  *                       order, the root block last.
  * The library never keeps a caller pointer after a call returns.
  *
+ * Batches.  A plan may hold B = num_systems (bmpc_options) independent systems of the
+ * same dims, factored and solved together in the same launches.  Their arrays are
+ * stacked along the leading dimension: D [B*S][N][n][n], E [B*S][N-1][n][n],
+ * C [B*S][n][n] (system i owns scenarios i*S .. i*S+S-1), R [B][n][n] and
+ * b, x [B][nrhs][(S*N+1)*n].  Everything below holds per system; with B = 1 these
+ * are the single-system layouts above.
+ *
  * Streams and ordering.  Every device operation is enqueued on the plan's stream
  * (hipStream_t passed as void*; NULL = the legacy default stream) and is
  * asynchronous unless stated.  The library allocates device memory only in
@@ -71,7 +78,9 @@ typedef struct {
 typedef struct {
   int32_t window_depth; /* 0 = automatic; else levels eliminated per factor pass
                            (1..6), bounded by the shared-memory budget */
-  int32_t reserved[7];
+  int32_t num_systems;  /* 0 or 1: one system; B > 1: a batch of B independent
+                           systems of the same dims (layouts: see "Batches") */
+  int32_t reserved[6];
 } bmpc_options;
 
 typedef struct {
@@ -154,13 +163,14 @@ bmpc_status bmpc_grad_blocks(bmpc_plan plan, const double* x, const double* lam,
                              double* dE, double* dC, double* dR);
 
 /* Synchronizes the plan's stream.  *info = 0 after a successful factor; otherwise
- * the 1-based natural row index (tails first, root last, as in b) of the first
- * non-positive pivot in the elimination order Pi, and the call returns
- * BMPC_ERR_NOT_SPD. */
+ * the 1-based natural row index (tails first, root last, as in b; in a batch the
+ * systems follow each other, (S*N+1)*n rows each) of the first non-positive pivot in
+ * the elimination order Pi, and the call returns BMPC_ERR_NOT_SPD. */
 bmpc_status bmpc_get_info(bmpc_plan plan, int64_t* info);
 
 /* Synchronizes.  Corrections applied by the last bmpc_refine and the final
- * max_q |d_q|_inf / |x_q|_inf.  Returns BMPC_ERR_NOT_CONVERGED if the stop test
+ * max |d_q|_inf / |x_q|_inf over the right-hand sides (and systems of a batch; the
+ * stop test holds for each of them).  Returns BMPC_ERR_NOT_CONVERGED if the stop test
  * was not met within max_iters. */
 bmpc_status bmpc_get_stats(bmpc_plan plan, int32_t* iters, double* rel_correction);
 
@@ -179,12 +189,13 @@ bmpc_status bmpc_query_cost(bmpc_plan plan, bmpc_cost* cost);
 bmpc_status bmpc_query_kernel_cost(bmpc_plan plan, int32_t cls, double* bytes,
                                    double* flops, int32_t* launches);
 
-/* Copy the factor of tail s to host memory (synchronizes): L [N*n][N*n] row-major
+/* Copy the factor of tail s (0 <= s < B*S; tail s of the batch is scenario s % S of
+ * system s / S) to host memory (synchronizes): L [N*n][N*n] row-major
  * in permuted order (lower block structure of L_i; the DIAGONAL blocks are given as
  * their inverses L_jj^{-1}, which is what the plan stores), F [n][n] = F_{s,1}.
  * Values are widened to FP64.  For tests of small systems. */
 bmpc_status bmpc_export_tail_factor(bmpc_plan plan, int32_t s, double* L, double* F);
-/* Copy L_R [n][n] (FP64, lower) to host memory (synchronizes). */
+/* Copy L_R [B][n][n] (FP64, lower; one per system) to host memory (synchronizes). */
 bmpc_status bmpc_export_root_factor(bmpc_plan plan, double* LR);
 
 /* Per-kernel timing with HIP events on the plan's stream.  While enabled, every

@@ -86,7 +86,53 @@ def branch_solve(D, E, C, R, b, precision="fp64"):
     return BranchSolve.apply(D, E, C, R, b, precision)
 
 
+class BatchedBranchSolve(torch.autograd.Function):
+    """Independent systems of one shape stacked on a leading batch dimension
+    (D [B][S][N][n][n], E [B][S][N-1][n][n], C [B][S][n][n], R [B][n][n],
+    b [B][nrhs][(S*N+1)*n]), factored and solved together in one batch plan."""
+
+    @staticmethod
+    def forward(ctx, D, E, C, R, b, precision="fp64", refine_tol=1e-12, refine_iters=10):
+        B, S, N, n = D.shape[0], D.shape[1], D.shape[2], D.shape[3]
+        nrhs = b.shape[1]
+        key = (B, S, N, n, nrhs, bmpc._prec(precision), torch.cuda.current_device(), "batch")
+        free = _POOL.get(key)
+        plan = free.pop() if free else bmpc.Plan(S, N, n, nrhs, precision, num_systems=B)
+        D, C, R, b = D.contiguous(), C.contiguous(), R.contiguous(), b.contiguous()
+        E = E.contiguous() if N > 1 else None
+        plan.factor(D, E, C, R)
+        if plan.precision == bmpc.FP64:
+            x = plan.solve(b)
+            ctx.save_for_backward(x)
+        else:
+            x = plan.refine(D, E, C, R, b, tol=refine_tol, max_iters=refine_iters)
+            ctx.save_for_backward(x, D, E if N > 1 else torch.empty(0, device=D.device), C, R)
+        ctx.plan, ctx.key, ctx.N = plan, key, N
+        ctx.refine = (refine_tol, refine_iters)
+        ctx.shapes = (B, S, N, n)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        plan = ctx.plan
+        if plan.precision == bmpc.FP64:
+            (x,) = ctx.saved_tensors
+            lam = plan.solve(gx.contiguous())
+        else:
+            x, D, E, C, R = ctx.saved_tensors
+            tol, iters = ctx.refine
+            lam = plan.refine(D, E if ctx.N > 1 else None, C, R, gx.contiguous(), tol=tol,
+                              max_iters=iters)
+        dD, dE, dC, dR = plan.grad_blocks(x, lam)
+        B, S, N, n = ctx.shapes
+        ctx.plan = None
+        _release(ctx.key, plan)
+        dE = dE.view(B, S, N - 1, n, n) if N > 1 else None
+        return (dD.view(B, S, N, n, n), dE, dC.view(B, S, n, n), dR.view(B, n, n), lam,
+                None, None, None)
+
+
 def batched_branch_solve(D, E, C, R, b, precision="fp64"):
-    """Independent systems stacked on a leading batch dimension, solved one by one."""
-    return torch.stack([BranchSolve.apply(D[i], E[i], C[i], R[i], b[i], precision)
-                        for i in range(D.shape[0])])
+    """Independent systems of one shape stacked on a leading batch dimension, solved in
+    one batch plan (one factor and one solve for all of them)."""
+    return BatchedBranchSolve.apply(D, E, C, R, b, precision)

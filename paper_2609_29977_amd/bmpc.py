@@ -40,7 +40,8 @@ class _Dims(ctypes.Structure):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("window_depth", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("window_depth", ctypes.c_int32), ("num_systems", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class _Cost(ctypes.Structure):
@@ -155,9 +156,9 @@ def structure(N: int) -> list:
 
 
 def cost_model(S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
-               window_depth: int = 0) -> Cost:
+               window_depth: int = 0, num_systems: int = 1) -> Cost:
     d = _Dims(S, N, n, nrhs)
-    o = _Options(window_depth)
+    o = _Options(window_depth, num_systems)
     c = _Cost()
     _check(lib().bmpc_cost_model(ctypes.byref(d), _prec(precision), ctypes.byref(o),
                                  ctypes.byref(c)), "bmpc_cost_model")
@@ -187,21 +188,24 @@ def _ptr(t, what, dtype=None, numel=None):
 
 
 class Plan:
-    """A bmpc plan: analysis + persistent device workspaces for one (S, N, n, nrhs)."""
+    """A bmpc plan: analysis + persistent device workspaces for one (S, N, n, nrhs),
+    or for a batch of num_systems independent systems of that shape (arrays stacked
+    along the leading dimension, see include/bmpc.h)."""
 
     def __init__(self, S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
-                 window_depth: int = 0, stream=None):
+                 window_depth: int = 0, stream=None, num_systems: int = 1):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("bmpc needs a HIP device (torch.cuda.is_available() is False)")
         self.S, self.N, self.n, self.nrhs = int(S), int(N), int(n), int(nrhs)
+        self.B = int(num_systems)
         self.precision = _prec(precision)
         self._h = ctypes.c_void_p()
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream
         d = _Dims(self.S, self.N, self.n, self.nrhs)
-        o = _Options(int(window_depth))
+        o = _Options(int(window_depth), self.B)
         _check(lib().bmpc_analyze_ex(ctypes.byref(d), self.precision,
                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
                                      ctypes.byref(self._h)), "bmpc_analyze")
@@ -228,11 +232,11 @@ class Plan:
 
     def _blocks(self, D, E, C, R):
         import torch
-        S, N, n = self.S, self.N, self.n
+        S, N, n, B = self.S, self.N, self.n, self.B
         f64 = torch.float64
-        return (_ptr(D, "D", f64, S * N * n * n),
-                _ptr(E, "E", f64, S * (N - 1) * n * n) if N > 1 else None,
-                _ptr(C, "C", f64, S * n * n), _ptr(R, "R", f64, n * n))
+        return (_ptr(D, "D", f64, B * S * N * n * n),
+                _ptr(E, "E", f64, B * S * (N - 1) * n * n) if N > 1 else None,
+                _ptr(C, "C", f64, B * S * n * n), _ptr(R, "R", f64, B * n * n))
 
     def factor(self, D, E, C, R):
         _check(lib().bmpc_factor(self._h, *self._blocks(D, E, C, R)), "bmpc_factor")
@@ -241,8 +245,8 @@ class Plan:
         import torch
         if x is None:
             x = torch.empty_like(b)
-        return (_ptr(b, "b", torch.float64, self.nrhs * self.length),
-                _ptr(x, "x", torch.float64, self.nrhs * self.length), x)
+        return (_ptr(b, "b", torch.float64, self.B * self.nrhs * self.length),
+                _ptr(x, "x", torch.float64, self.B * self.nrhs * self.length), x)
 
     def solve(self, b, x=None):
         pb, px, x = self._rhs(b, x)
@@ -260,15 +264,15 @@ class Plan:
         """(dD, dE, dC, dR) of a loss through x = K^{-1} b, from the solution x and the
         adjoint lam = K^{-1} dloss/dx (see bmpc_grad_blocks)."""
         import torch
-        S, N, n = self.S, self.N, self.n
+        S, N, n, B = self.S, self.N, self.n, self.B
         f64 = torch.float64
-        px = _ptr(x, "x", f64, self.nrhs * self.length)
-        pl = _ptr(lam, "lam", f64, self.nrhs * self.length)
+        px = _ptr(x, "x", f64, B * self.nrhs * self.length)
+        pl = _ptr(lam, "lam", f64, B * self.nrhs * self.length)
         dev = x.device
-        dD = torch.empty((S, N, n, n), dtype=f64, device=dev)
-        dE = torch.empty((S, max(N - 1, 0), n, n), dtype=f64, device=dev)
-        dC = torch.empty((S, n, n), dtype=f64, device=dev)
-        dR = torch.empty((n, n), dtype=f64, device=dev)
+        dD = torch.empty((B * S, N, n, n), dtype=f64, device=dev)
+        dE = torch.empty((B * S, max(N - 1, 0), n, n), dtype=f64, device=dev)
+        dC = torch.empty((B * S, n, n), dtype=f64, device=dev)
+        dR = torch.empty((B, n, n) if B > 1 else (n, n), dtype=f64, device=dev)
         _check(lib().bmpc_grad_blocks(self._h, px, pl, ctypes.c_void_p(dD.data_ptr()),
                                       ctypes.c_void_p(dE.data_ptr()) if N > 1 else None,
                                       ctypes.c_void_p(dC.data_ptr()),
@@ -319,11 +323,11 @@ class Plan:
 
     def export_root_factor(self):
         import numpy as np
-        LR = np.zeros((self.n, self.n))
+        LR = np.zeros((self.B, self.n, self.n))
         _check(lib().bmpc_export_root_factor(
             self._h, LR.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
             "bmpc_export_root_factor")
-        return LR
+        return LR[0] if self.B == 1 else LR
 
     def set_profiling(self, enable: bool):
         _check(lib().bmpc_set_profiling(self._h, int(bool(enable))), "bmpc_set_profiling")

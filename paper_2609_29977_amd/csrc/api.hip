@@ -74,7 +74,7 @@ struct Costs {
   int levels = 0, Tw = 0;
 };
 
-Costs make_costs(const bmpc_dims& d, bool fp64, int Tw) {
+Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B) {
   Costs c;
   c.Tw = Tw;
   const int S = d.S, N = d.N, n = d.n, m = N - 1;
@@ -150,6 +150,21 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw) {
   for (int k = 0; k < KC_COUNT; ++k) c.launches[k] = 1;
   c.launches[KC_SOLVE_FWD] = L;
   c.launches[KC_SOLVE_BWD] = L;
+  // a batch of B systems does B times the work in the same launches
+  for (PassPlan& pp : c.passes) {
+    pp.flops *= B;
+    pp.bytes *= B;
+  }
+  for (int k = 0; k < KC_COUNT; ++k) {
+    c.pass_flops[k] *= B;
+    c.pass_bytes[k] *= B;
+  }
+  c.factor_flops *= B;
+  c.solve_flops *= B;
+  c.factor_bytes *= B;
+  c.solve_bytes *= B;
+  c.residual_bytes *= B;
+  c.L_bytes *= B;
   return c;
 }
 
@@ -160,6 +175,7 @@ struct bmpc_plan_s {
   bmpc_precision prec = BMPC_FP64;
   bool fp64 = true;
   int m = 0, nmax = 8, Tw = 1, groups = 1;
+  int B = 1;  // systems in the batch
   hipStream_t stream = nullptr;
   Costs costs;
   std::vector<int> perm, permpos;
@@ -238,10 +254,13 @@ void collect_timings(bmpc_plan p) {
   p->timings.clear();
 }
 
-bool dims_ok(const bmpc_dims* d) {
+bool dims_ok(const bmpc_dims* d, int B = 1) {
   return d && d->S >= 1 && d->N >= 1 && d->n >= 1 && d->n <= 32 && d->nrhs >= 1 &&
-         d->nrhs <= kMaxRhs && (double)d->S * d->N * d->n < 2.0e9;
+         d->nrhs <= kMaxRhs && B >= 1 && (double)B * d->S * d->N * d->n < 2.0e9 &&
+         (double)B * d->S * d->N < 2.0e9 / 64;
 }
+
+int systems_of(const bmpc_options* o) { return (o && o->num_systems > 0) ? o->num_systems : 1; }
 
 void free_plan_memory(bmpc_plan p) {
   for (void* a : p->allocs) (void)hipFree(a);
@@ -283,7 +302,8 @@ void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double*
   for (int k = 0; k < npass; ++k) {
     const PassPlan& pp = p->costs.passes[k];
     FactorPassArgs a{};
-    a.S = d.S;
+    a.S = p->B * d.S;
+    a.Ssys = d.S;
     a.N = d.N;
     a.n = d.n;
     a.m = p->m;
@@ -317,16 +337,19 @@ void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double*
     timed(p, cls, [&] { launch_factor_pass<T>(a, p->nmax, st); });
   }
   timed(p, KC_ROOT_REDUCE,
-        [&] { launch_root_reduce(p->U, p->Upart, d.S, d.n, p->groups, st); });
+        [&] { launch_root_reduce(p->U, p->Upart, p->B, d.S, d.n, p->groups, st); });
   const int64_t root_row = (int64_t)d.S * d.N * d.n;
+  const int64_t sys_rows = root_row + d.n;
   timed(p, KC_ROOT_POTRF, [&] {
-    launch_root_potrf(R, p->Upart, p->groups, d.n, p->LR, root_row, p->d_info, st);
+    launch_root_potrf(R, p->Upart, p->B, p->groups, d.n, p->LR, sys_rows, root_row, p->d_info,
+                      st);
   });
 }
 
 SolveArgs solve_args(bmpc_plan p, const double* b, double* x) {
   SolveArgs a{};
   a.S = p->d.S;
+  a.B = p->B;
   a.N = p->d.N;
   a.n = p->d.n;
   a.m = p->m;
@@ -411,11 +434,12 @@ bmpc_status bmpc_structure(int32_t N, int32_t* rows, int32_t* cols, int64_t cap,
 
 bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
                             const bmpc_options* opts, bmpc_cost* cost) {
-  if (!dims_ok(dims) || !cost || (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
+  if (!dims_ok(dims, systems_of(opts)) || !cost ||
+      (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
     return BMPC_ERR_INVALID;
   const bool fp64 = prec == BMPC_FP64;
   const int Tw = pick_window_depth(fp64, nmax_for(dims->n), opts);
-  Costs c = make_costs(*dims, fp64, Tw);
+  Costs c = make_costs(*dims, fp64, Tw, systems_of(opts));
   std::memset(cost, 0, sizeof(*cost));
   cost->factor_flops = c.factor_flops;
   cost->solve_flops = c.solve_flops;
@@ -432,7 +456,7 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
                             const bmpc_options* opts, bmpc_plan* out) {
   if (!out) return BMPC_ERR_INVALID;
   *out = nullptr;
-  if (!dims_ok(dims) || (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
+  if (!dims_ok(dims, systems_of(opts)) || (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
     return BMPC_ERR_INVALID;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BMPC_ERR_DEVICE;
@@ -444,39 +468,42 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
   p->m = dims->N - 1;
   p->nmax = nmax_for(dims->n);
   p->Tw = pick_window_depth(p->fp64, p->nmax, opts);
+  p->B = systems_of(opts);
   p->stream = reinterpret_cast<hipStream_t>(stream);
-  p->costs = make_costs(*dims, p->fp64, p->Tw);
+  p->costs = make_costs(*dims, p->fp64, p->Tw, p->B);
   p->perm = make_perm(dims->N);
   p->permpos = make_permpos(dims->N);
   p->groups = std::min(dims->S, 32);
-  const int S = dims->S, N = dims->N, n = dims->n, nrhs = dims->nrhs;
+  const int B = p->B, N = dims->N, n = dims->n, nrhs = dims->nrhs;
+  const size_t S = (size_t)B * dims->S;  // chains of the batch
   const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
-  const size_t len = ((size_t)S * N + 1) * n;
+  const size_t len = ((size_t)dims->S * N + 1) * n;
+  const size_t segs = (size_t)B * nrhs;  // (system, right-hand side) vectors
   const int npass = (int)p->costs.passes.size();
   p->stride = (npass > 1 ? p->costs.passes[0].windows : 1) + 1;
   const size_t gblocks = (size_t)(N > 1 ? N - 1 : 1);
-  bool ok = dalloc(p, &p->Linv, (size_t)S * N * nn * tb) &&
-            dalloc(p, &p->Gl, (size_t)S * gblocks * nn * tb) &&
-            dalloc(p, &p->Gr, (size_t)S * gblocks * nn * tb) &&
-            dalloc(p, &p->F, (size_t)S * nn * tb) &&
-            dalloc(p, (void**)&p->U, (size_t)S * nn * 8) &&
-            dalloc(p, (void**)&p->Upart, (size_t)p->groups * nn * 8) &&
-            dalloc(p, (void**)&p->LR, nn * 8) &&
-            dalloc(p, &p->accX, (size_t)S * npass * nn * tb) &&
+  bool ok = dalloc(p, &p->Linv, S * N * nn * tb) &&
+            dalloc(p, &p->Gl, S * gblocks * nn * tb) &&
+            dalloc(p, &p->Gr, S * gblocks * nn * tb) &&
+            dalloc(p, &p->F, S * nn * tb) &&
+            dalloc(p, (void**)&p->U, S * nn * 8) &&
+            dalloc(p, (void**)&p->Upart, (size_t)B * p->groups * nn * 8) &&
+            dalloc(p, (void**)&p->LR, (size_t)B * nn * 8) &&
+            dalloc(p, &p->accX, S * npass * nn * tb) &&
             dalloc(p, (void**)&p->d_permpos, (size_t)N * sizeof(int)) &&
             dalloc(p, (void**)&p->d_info, sizeof(unsigned long long)) &&
-            dalloc(p, &p->y, (size_t)S * N * nrhs * n * tb) &&
-            dalloc(p, (void**)&p->w, (size_t)S * nrhs * n * 8) &&
-            dalloc(p, (void**)&p->x0, (size_t)nrhs * n * 8) &&
-            dalloc(p, (void**)&p->rbuf, (size_t)nrhs * len * 8) &&
-            dalloc(p, (void**)&p->norms, (size_t)3 * nrhs * 8) &&
-            dalloc(p, (void**)&p->npart, (size_t)2 * nrhs * kNormBlocks * 8) &&
+            dalloc(p, &p->y, S * N * nrhs * n * tb) &&
+            dalloc(p, (void**)&p->w, S * nrhs * n * 8) &&
+            dalloc(p, (void**)&p->x0, segs * n * 8) &&
+            dalloc(p, (void**)&p->rbuf, segs * len * 8) &&
+            dalloc(p, (void**)&p->norms, 3 * segs * 8) &&
+            dalloc(p, (void**)&p->npart, 2 * segs * kNormBlocks * 8) &&
             dalloc(p, (void**)&p->flags, 2 * sizeof(int)) &&
             dalloc(p, (void**)&p->relcorr, sizeof(double));
   if (ok && npass > 1) {
     for (int set = 0; set < 2 && ok; ++set)
       for (int b = 0; b < 3 && ok; ++b)
-        ok = dalloc(p, &p->acc[set][b], (size_t)S * p->stride * nn * tb);
+        ok = dalloc(p, &p->acc[set][b], S * p->stride * nn * tb);
   }
   if (!ok) {
     free_plan_memory(p);
@@ -535,10 +562,11 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
   if (!p->factored) return BMPC_ERR_STATE;
   hipStream_t st = p->stream;
   const int nrhs = p->d.nrhs;
+  const int segs = p->B * nrhs;  // norms per (system, right-hand side)
   const size_t len = ((size_t)p->d.S * p->d.N + 1) * p->d.n;
   double* rnorm = p->norms;
-  double* dnorm = p->norms + nrhs;
-  double* xnorm = p->norms + 2 * nrhs;
+  double* dnorm = p->norms + segs;
+  double* xnorm = p->norms + 2 * segs;
   timed(p, KC_REFINE_MISC, [&] { launch_refine_reset(p->flags, st); });
   SolveArgs a = solve_args(p, b, x);
   if (p->fp64)
@@ -547,6 +575,7 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
     enqueue_solve<float>(p, a);
   ResidualArgs ra{};
   ra.S = p->d.S;
+  ra.B = p->B;
   ra.N = p->d.N;
   ra.n = p->d.n;
   ra.nrhs = nrhs;
@@ -570,14 +599,14 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
     timed(p, KC_RESIDUAL, [&] { launch_residual(ra, p->nmax, st); });
     timed(p, KC_RESIDUAL_ROOT, [&] { launch_residual_root(ra, st); });
     timed(p, KC_REFINE_MISC, [&] {
-      launch_maxabs(p->rbuf, nrhs, len, p->npart, rnorm, p->flags, st);
+      launch_maxabs(p->rbuf, segs, len, p->npart, rnorm, p->flags, st);
     });
     if (p->fp64)
       enqueue_solve<double>(p, c);
     else
       enqueue_solve<float>(p, c);
     timed(p, KC_REFINE_MISC, [&] {
-      launch_refine_check(p->rbuf, x, nrhs, len, p->npart, tol, p->flags, p->relcorr, dnorm,
+      launch_refine_check(p->rbuf, x, segs, len, p->npart, tol, p->flags, p->relcorr, dnorm,
                           xnorm, st);
     });
   }
@@ -590,6 +619,7 @@ bmpc_status bmpc_grad_blocks(bmpc_plan p, const double* x, const double* lam, do
   if (!p || !x || !lam) return BMPC_ERR_INVALID;
   GradArgs g{};
   g.S = p->d.S;
+  g.B = p->B;
   g.N = p->d.N;
   g.n = p->d.n;
   g.nrhs = p->d.nrhs;
@@ -613,11 +643,15 @@ bmpc_status bmpc_get_info(bmpc_plan p, int64_t* info) {
     *info = 0;
     return BMPC_OK;
   }
+  // recorded: system base + tail base + permuted position * n + row (1-based);
+  // reported: the same row in natural stage order
   const int64_t Nn = (int64_t)p->d.N * p->d.n, n = p->d.n;
+  const int64_t sys_rows = (int64_t)p->d.S * Nn + n;
   const int64_t p0 = (int64_t)v - 1;
-  if (p0 < (int64_t)p->d.S * Nn) {
-    const int64_t s = p0 / Nn, rem = p0 % Nn, pos = rem / n, i = rem % n;
-    *info = s * Nn + (int64_t)p->perm[pos] * n + i + 1;
+  const int64_t sys = p0 / sys_rows, r0 = p0 % sys_rows;
+  if (r0 < (int64_t)p->d.S * Nn) {
+    const int64_t s = r0 / Nn, rem = r0 % Nn, pos = rem / n, i = rem % n;
+    *info = sys * sys_rows + s * Nn + (int64_t)p->perm[pos] * n + i + 1;
   } else {
     *info = (int64_t)v;
   }
@@ -669,7 +703,7 @@ bmpc_status bmpc_query_kernel_cost(bmpc_plan p, int32_t cls, double* bytes, doub
 }
 
 bmpc_status bmpc_export_tail_factor(bmpc_plan p, int32_t s, double* L, double* F) {
-  if (!p || !L || !F || s < 0 || s >= p->d.S) return BMPC_ERR_INVALID;
+  if (!p || !L || !F || s < 0 || s >= p->B * p->d.S) return BMPC_ERR_INVALID;
   if (!p->factored) return BMPC_ERR_STATE;
   const int N = p->d.N, n = p->d.n, m = p->m;
   const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
@@ -718,7 +752,8 @@ bmpc_status bmpc_export_root_factor(bmpc_plan p, double* LR) {
   if (!p || !LR) return BMPC_ERR_INVALID;
   if (!p->factored) return BMPC_ERR_STATE;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
-  if (hipMemcpy(LR, p->LR, (size_t)p->d.n * p->d.n * 8, hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(LR, p->LR, (size_t)p->B * p->d.n * p->d.n * 8, hipMemcpyDeviceToHost) !=
+      hipSuccess)
     return BMPC_ERR_DEVICE;
   return BMPC_OK;
 }

@@ -50,8 +50,13 @@ enum KernelClass : int {
   KC_COUNT
 };
 
+// Batches: B independent systems of one shape are factored and solved together.
+// The tail kernels run over the B*S chains (chain g is scenario g % S of system
+// g / S); the root steps run once per system.  Vectors b, x, r are [B][nrhs][len]
+// with len = (S*N+1)*n.
 struct FactorPassArgs {
-  int S, N, n, m;       // m = N - 1
+  int S, N, n, m;       // S = chains of the batch (B * scenarios); m = N - 1
+  int Ssys;             // scenarios per system (for natural row numbers)
   int Tw;               // window depth (levels per pass)
   int pass, npass;      // index of this pass and total passes
   int mk, shift;        // reduced chain length, position stride log2
@@ -79,7 +84,8 @@ struct FactorPassArgs {
 };
 
 struct SolveArgs {
-  int S, N, n, m, nrhs;
+  int S, N, n, m, nrhs;  // S = scenarios per system
+  int B;                 // systems in the batch
   const void* Linv;
   const void* Gl;
   const void* Gr;
@@ -97,21 +103,23 @@ struct SolveArgs {
 };
 
 struct ResidualArgs {
-  int S, N, n, nrhs;
+  int S, N, n, nrhs;     // S = scenarios per system
+  int B;                 // systems in the batch
   int chunk;             // stages per work item of the tail residual
   const double* D;
   const double* E;
   const double* C;
-  const double* R;
+  const double* R;       // [B][n][n]
   const double* b;
   const double* x;
-  double* r;             // [nrhs][len]
+  double* r;             // [B][nrhs][len]
   double* w;             // [S][nrhs][n] products C_s x_{s,0}
   const int* done;
 };
 
 struct GradArgs {
-  int S, N, n, nrhs;
+  int S, N, n, nrhs;     // S = scenarios per system
+  int B;                 // systems in the batch
   const double* x;       // [nrhs][len] solution
   const double* lam;     // [nrhs][len] adjoint K^{-1} g
   double* dD;            // [S][N][n][n] or null
@@ -124,11 +132,14 @@ struct GradArgs {
 template <typename T>
 void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st);
 void launch_factor_init(unsigned long long* info, hipStream_t st);
-void launch_root_reduce(const double* U, double* part, int S, int n, int groups,
+// part[sys][g] = sum of U over the scenarios of group g of system sys (B systems of S)
+void launch_root_reduce(const double* U, double* part, int B, int S, int n, int groups,
                         hipStream_t st);
-void launch_root_potrf(const double* R, const double* part, int groups, int n,
-                       double* LR, int64_t row_base, unsigned long long* info,
-                       hipStream_t st);
+// LR[sys] = chol(R[sys] - sum_g part[sys][g]) for every system; row numbers of system
+// sys start at sys * sys_rows, its root rows at root_row within it
+void launch_root_potrf(const double* R, const double* part, int B, int groups, int n,
+                       double* LR, int64_t sys_rows, int64_t root_row,
+                       unsigned long long* info, hipStream_t st);
 
 template <typename T>
 void launch_solve_fwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st);

@@ -286,7 +286,11 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
   T* Linv = reinterpret_cast<T*>(a.Linv) + (size_t)s * N * nn;
   T* Gl = reinterpret_cast<T*>(a.Gl) + (size_t)s * (N > 1 ? N - 1 : 1) * nn;
   T* Gr = reinterpret_cast<T*>(a.Gr) + (size_t)s * (N > 1 ? N - 1 : 1) * nn;
-  const unsigned long long chain_row0 = (unsigned long long)s * N * n;
+  // natural row of the chain's first entry: systems in order, tails before the root
+  const int sys = s / a.Ssys;
+  const unsigned long long chain_row0 =
+      (unsigned long long)sys * ((unsigned long long)a.Ssys * N + 1) * n +
+      (unsigned long long)(s - sys * a.Ssys) * N * n;
 
   // Prologue: the pass-local level-1 positions (odd q) see no update from inside the
   // window, so their diagonal blocks (D plus updates carried from earlier passes) are
@@ -530,17 +534,20 @@ __global__ void factor_init_kernel(unsigned long long* info) {
   if (threadIdx.x == 0) *info = ~0ull;
 }
 
-// part[g][e] = sum of U[s][e] over the scenarios of group g, in scenario order.
+// part[sys][g][e] = sum of U[s][e] over the scenarios of group g of system sys, in
+// scenario order (one workgroup per (system, group)).
 __global__ void __launch_bounds__(256) root_reduce_kernel(const double* __restrict__ U,
                                                           double* part, int S, int nn,
                                                           int groups) {
-  const int g = blockIdx.x;
+  const int sys = blockIdx.x / groups;
+  const int g = blockIdx.x - sys * groups;
   const int per = (S + groups - 1) / groups;
   const int s0 = g * per, s1 = min(S, s0 + per);
+  const double* Us = U + (size_t)sys * S * nn;
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
     double acc = 0.0;
-    for (int s = s0; s < s1; ++s) acc += U[(size_t)s * nn + e];
-    part[(size_t)g * nn + e] = acc;
+    for (int s = s0; s < s1; ++s) acc += Us[(size_t)s * nn + e];
+    part[((size_t)sys * groups + g) * nn + e] = acc;
   }
 }
 
@@ -549,9 +556,16 @@ __global__ void __launch_bounds__(256) root_reduce_kernel(const double* __restri
 __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restrict__ R,
                                                           const double* __restrict__ part,
                                                           int groups, int n, double* LR,
-                                                          unsigned long long row_base,
+                                                          unsigned long long sys_rows,
+                                                          unsigned long long root_row,
                                                           unsigned long long* info) {
   __shared__ double A[32 * 33];
+  // one workgroup per system of the batch
+  const int sys = blockIdx.x;
+  R += (size_t)sys * n * n;
+  part += (size_t)sys * groups * n * n;
+  LR += (size_t)sys * n * n;
+  const unsigned long long row_base = sys * sys_rows + root_row;
   constexpr int LD = 33;
   const int e = threadIdx.x;
   const int r = e / 32, c = e % 32;
@@ -642,16 +656,17 @@ void launch_factor_init(unsigned long long* info, hipStream_t st) {
   hipLaunchKernelGGL(factor_init_kernel, dim3(1), dim3(64), 0, st, info);
 }
 
-void launch_root_reduce(const double* U, double* part, int S, int n, int groups,
+void launch_root_reduce(const double* U, double* part, int B, int S, int n, int groups,
                         hipStream_t st) {
-  hipLaunchKernelGGL(root_reduce_kernel, dim3(groups), dim3(256), 0, st, U, part, S, n * n,
+  hipLaunchKernelGGL(root_reduce_kernel, dim3(B * groups), dim3(256), 0, st, U, part, S, n * n,
                      groups);
 }
 
-void launch_root_potrf(const double* R, const double* part, int groups, int n, double* LR,
-                       int64_t row_base, unsigned long long* info, hipStream_t st) {
-  hipLaunchKernelGGL(root_potrf_kernel, dim3(1), dim3(1024), 0, st, R, part, groups, n, LR,
-                     (unsigned long long)row_base, info);
+void launch_root_potrf(const double* R, const double* part, int B, int groups, int n,
+                       double* LR, int64_t sys_rows, int64_t root_row,
+                       unsigned long long* info, hipStream_t st) {
+  hipLaunchKernelGGL(root_potrf_kernel, dim3(B), dim3(1024), 0, st, R, part, groups, n, LR,
+                     (unsigned long long)sys_rows, (unsigned long long)root_row, info);
 }
 
 }  // namespace bmpc

@@ -6,7 +6,7 @@
 // eq. (tail_block_tridiagonal)): D and R symmetrically (sym(A) = (A + A^T) / 2),
 // E[s][k] at (k+1, k) and transposed at (k, k+1), C[s] at (root, stage 0) and
 // transposed at (stage 0, root).  One workgroup per tail stage writes dD and dE of
-// that stage (and dC for stage 0); one more workgroup writes dR.  The vectors are
+// that stage (and dC for stage 0); one more workgroup per system writes its dR.  The vectors are
 // staged in LDS; every output element is written once, coalesced.  HBM-bound on the
 // writes: 8 n^2 bytes per D, E and C block.
 #include "bmpc_internal.h"
@@ -23,10 +23,15 @@ __global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a) {
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
   const size_t nn = (size_t)n * n;
   const size_t len = ((size_t)S * N + 1) * n;
-  const size_t root = (size_t)S * N * n;
-  const bool is_root = blockIdx.x == (unsigned)(S * N);
+  const int chains = a.B * S;
+  // workgroups [0, chains*N): stage k of chain s; then one per system for dR
+  const bool is_root = blockIdx.x >= (unsigned)(chains * N);
   const int s = is_root ? 0 : blockIdx.x / N;
   const int k = is_root ? 0 : blockIdx.x - s * N;
+  const int sys = is_root ? (int)blockIdx.x - chains * N : s / S;
+  const int sl = s - (s / S) * S;
+  const size_t vbase = (size_t)sys * nrhs * len;
+  const size_t root = vbase + (size_t)S * N * n;
   for (int idx = threadIdx.x; idx < nrhs * 3 * n; idx += GT) {
     const int q = idx / (3 * n), rem = idx - q * 3 * n, w = rem / n, i = rem - w * n;
     size_t off;
@@ -36,7 +41,7 @@ __global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a) {
     } else {
       const int st = k + w;
       ok = !is_root && st < N;
-      off = ((size_t)s * N + (ok ? st : 0)) * n + i;
+      off = vbase + ((size_t)sl * N + (ok ? st : 0)) * n + i;
     }
     xs[q][w][i] = ok ? a.x[(size_t)q * len + off] : 0.0;
     ls[q][w][i] = ok ? a.lam[(size_t)q * len + off] : 0.0;
@@ -48,7 +53,7 @@ __global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a) {
       const int r = e / n, c = e - r * n;
       double acc = 0.0;
       for (int q = 0; q < nrhs; ++q) acc += ls[q][2][r] * xs[q][2][c] + ls[q][2][c] * xs[q][2][r];
-      a.dR[e] = -0.5 * acc;
+      a.dR[(size_t)sys * nn + e] = -0.5 * acc;
     }
     return;
   }
@@ -76,7 +81,8 @@ __global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a) {
 }  // namespace
 
 void launch_grad_blocks(const GradArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(grad_blocks_kernel, dim3((unsigned)(a.S * a.N + 1)), dim3(GT), 0, st, a);
+  hipLaunchKernelGGL(grad_blocks_kernel, dim3((unsigned)(a.B * a.S * a.N + a.B)), dim3(GT), 0,
+                     st, a);
 }
 
 }  // namespace bmpc

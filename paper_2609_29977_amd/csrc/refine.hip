@@ -71,16 +71,19 @@ __global__ void __launch_bounds__(ResCfg<NMAX>::NT) residual_kernel(ResidualArgs
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
   const size_t nn = (size_t)n * n;
   const size_t len = ((size_t)S * N + 1) * n;
-  const int s = blockIdx.x / chunks;
+  const int s = blockIdx.x / chunks;  // chain of the batch
   const int ch = blockIdx.x - s * chunks;
+  const int sys = s / S, sl = s - sys * S;
+  const size_t vbase = (size_t)sys * nrhs * len;  // this system's vectors
   const int k0 = ch * a.chunk, k1 = min(N, k0 + a.chunk);
   const int o = RB::out_index(), b = RB::base();
 
   auto load_x = [&](double (*dst)[NMAX], int k) {
     for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
       const int q = idx / NMAX, i = idx % NMAX;
-      dst[q][i] = (k >= 0 && k < N && i < n) ? a.x[(size_t)q * len + ((size_t)s * N + k) * n + i]
-                                             : 0.0;
+      dst[q][i] = (k >= 0 && k < N && i < n)
+                      ? a.x[vbase + (size_t)q * len + ((size_t)sl * N + k) * n + i]
+                      : 0.0;
     }
   };
   int ip = 0, ic = 1, in = 2;  // rotating indices of x_{k-1}, x_k, x_{k+1}
@@ -89,7 +92,7 @@ __global__ void __launch_bounds__(ResCfg<NMAX>::NT) residual_kernel(ResidualArgs
   if (k0 == 0)
     for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
       const int q = idx / NMAX, i = idx % NMAX;
-      x0s[q][i] = i < n ? a.x[(size_t)q * len + (size_t)S * N * n + i] : 0.0;
+      x0s[q][i] = i < n ? a.x[vbase + (size_t)q * len + (size_t)S * N * n + i] : 0.0;
     }
   // carry: this lane's partial of E_{k0-1} x_{k0-1} for row k0, one slot per
   // right-hand side (LDS, so the loop over right-hand sides need not be unrolled)
@@ -109,7 +112,7 @@ __global__ void __launch_bounds__(ResCfg<NMAX>::NT) residual_kernel(ResidualArgs
     StageBlocks<NMAX> nxt;
     if (k + 1 < k1) nxt.load(a, s, k + 1);
     __syncthreads();
-    const size_t off = ((size_t)s * N + k) * n;
+    const size_t off = vbase + ((size_t)sl * N + k) * n;
 #pragma unroll 1
     for (int q = 0; q < nrhs; ++q) {
       double p = cur.d.dot(xs[ic][q]) + my[q * NT];
@@ -148,8 +151,11 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
   if (a.done && *a.done) return;
   __shared__ double part[32][33];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
+  const int sys = blockIdx.x;  // one workgroup per system
   const size_t len = ((size_t)S * N + 1) * n;
-  const size_t root = (size_t)S * N * n;
+  const size_t root = (size_t)sys * nrhs * len + (size_t)S * N * n;
+  const double* w = a.w + (size_t)sys * S * nrhs * n;
+  const double* R = a.R + (size_t)sys * n * n;
   const int t = threadIdx.x, i = t & 31, g = t >> 5;
   for (int q = 0; q < nrhs; ++q) {
     double acc = 0.0;
@@ -160,7 +166,7 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
 #pragma unroll
         for (int u = 0; u < B; ++u) {
           const int sc = s0 + 32 * u;
-          v[u] = sc < S ? a.w[((size_t)sc * nrhs + q) * n + i] : 0.0;
+          v[u] = sc < S ? w[((size_t)sc * nrhs + q) * n + i] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < B; ++u) acc += v[u];
@@ -174,7 +180,7 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
       for (int gg = 0; gg < 32; ++gg) sum += part[gg][row];
       double rx = 0.0;
       for (int c = 0; c < n; ++c) {
-        const double rv = (row >= c) ? a.R[row * n + c] : a.R[c * n + row];
+        const double rv = (row >= c) ? R[row * n + c] : R[c * n + row];
         rx += rv * a.x[(size_t)q * len + root + c];
       }
       a.r[(size_t)q * len + root + row] = a.b[(size_t)q * len + root + row] - rx - sum;
@@ -284,7 +290,7 @@ __global__ void __launch_bounds__(64) refine_check_kernel(const double* partial,
 
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
   const int chunks = (a.N + a.chunk - 1) / a.chunk;
-  const dim3 grid((unsigned)a.S * (unsigned)chunks);
+  const dim3 grid((unsigned)(a.B * a.S) * (unsigned)chunks);
   if (nmax <= 8)
     hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(ResCfg<8>::NT), 0, st, a, chunks);
   else if (nmax <= 16)
@@ -294,7 +300,7 @@ void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
 }
 
 void launch_residual_root(const ResidualArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(residual_root_kernel, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(residual_root_kernel, dim3(a.B), dim3(1024), 0, st, a);
 }
 
 void launch_maxabs(const double* v, int nrhs, size_t len, double* partial, double* out,

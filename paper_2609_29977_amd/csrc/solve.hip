@@ -26,18 +26,29 @@ namespace {
 
 constexpr int NT = kSolveThreads;
 
-// Gathered right-hand side of a position: dst[q][i] = scale_q * b[q][off + i], zero
-// padded to NMAX.
+// Vectors b, x, r are [B][nrhs][len], len = (S*N+1)*n: system sys, right-hand side q
+// starts at (sys*nrhs + q)*len, its tails in stage order, its root last.  Chain g of
+// the batch (0 <= g < B*S) is scenario g % S of system g / S.  vec_off gives the
+// offset of (chain g, q = 0, stage); seg_of the first norm index (sys*nrhs) of g.
+__device__ inline size_t vec_len(const SolveArgs& a) { return ((size_t)a.S * a.N + 1) * a.n; }
+__device__ inline size_t vec_off(const SolveArgs& a, int g, int stage) {
+  const int sys = g / a.S, sl = g - sys * a.S;
+  return (size_t)sys * a.nrhs * vec_len(a) + ((size_t)sl * a.N + stage) * a.n;
+}
+__device__ inline int seg_of(const SolveArgs& a, int g) { return (g / a.S) * a.nrhs; }
+
+// Gathered right-hand side of a position: dst[q][i] = b[off + q*len + i] / rnorm, zero
+// padded to NMAX (seg0 = norm index of q = 0).
 template <typename T, int NMAX>
-__device__ inline void gather_rhs(const SolveArgs& a, T (*dst)[NMAX], size_t off) {
-  const size_t len = ((size_t)a.S * a.N + 1) * a.n;
+__device__ inline void gather_rhs(const SolveArgs& a, T (*dst)[NMAX], size_t off, int seg0) {
+  const size_t len = vec_len(a);
   for (int idx = threadIdx.x; idx < a.nrhs * NMAX; idx += NT) {
     const int q = idx / NMAX, i = idx % NMAX;
     T v = T(0);
     if (i < a.n) {
       double bv = a.b[(size_t)q * len + off + i];
       if (a.rnorm) {
-        const double rn = a.rnorm[q];
+        const double rn = a.rnorm[seg0 + q];
         bv = rn > 0.0 ? bv / rn : 0.0;
       }
       v = static_cast<T>(bv);
@@ -130,12 +141,11 @@ struct SolveSmem {
   T rhs[kMaxRhs][NMAX];
 };
 
-// x[q][off + o] = d  or  x += rnorm_q * d with rnorm_q * d kept in dstore.
-__device__ inline void scatter_value(const SolveArgs& a, int q, size_t off, double d) {
-  const size_t len = ((size_t)a.S * a.N + 1) * a.n;
-  const size_t idx = (size_t)q * len + off;
+// x[off + q*len] = d  or  x += rnorm * d with rnorm * d kept in dstore.
+__device__ inline void scatter_value(const SolveArgs& a, int q, size_t off, int seg0, double d) {
+  const size_t idx = (size_t)q * vec_len(a) + off;
   if (a.accumulate) {
-    const double dd = a.rnorm[q] * d;
+    const double dd = a.rnorm[seg0 + q] * d;
     a.x[idx] += dd;
     a.dstore[idx] = dd;
   } else {
@@ -237,15 +247,16 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
   // right-hand side of the position: the gathered b (forward) or its dy (backward)
   if (wv == 0) {
     if constexpr (FWD) {
-      const size_t len = ((size_t)a.S * N + 1) * n;
-      const size_t off = ((size_t)s * N + (N - j)) * n;
+      const size_t len = vec_len(a);
+      const size_t off = vec_off(a, s, N - j);
+      const int seg0 = seg_of(a, s);
       for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += 64) {
         const int q = idx / NMAX, ii = idx % NMAX;
         T v = T(0);
         if (ii < n) {
           double bv = a.b[(size_t)q * len + off + ii];
           if (a.rnorm) {
-            const double rn = a.rnorm[q];
+            const double rn = a.rnorm[seg0 + q];
             bv = rn > 0.0 ? bv / rn : 0.0;
           }
           v = static_cast<T>(bv);
@@ -305,13 +316,15 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
     rhs[q][ii] -= acc;
   }
   wave_lds_fence();
-  const size_t off = ((size_t)s * N + (N - j)) * n;
+  const size_t off = vec_off(a, s, N - j);
+  const int seg0 = seg_of(a, s);
 #pragma unroll 1
   for (int q = 0; q < nrhs; ++q) {
     const T v = lane_group_sum<RB::LPR>(lin.dot(rhs[q]));
     if (RB::base() == 0 && RB::out_index() < n) {
       yj[q * n + RB::out_index()] = v;
-      if constexpr (!FWD) scatter_value(a, q, off + RB::out_index(), static_cast<double>(v));
+      if constexpr (!FWD)
+        scatter_value(a, q, off + RB::out_index(), seg0, static_cast<double>(v));
     }
   }
 }
@@ -332,7 +345,7 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   RB lin, fb;
   lin.template load_packed<false>(Linv + (size_t)(N - 1) * nn, n);
   fb.template load<false>(reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n);
-  gather_rhs<T, NMAX>(a, sm.rhs, ((size_t)s * N + 0) * n);
+  gather_rhs<T, NMAX>(a, sm.rhs, vec_off(a, s, 0), seg_of(a, s));
   T part[kMaxRhs];
 #pragma unroll
   for (int q = 0; q < kMaxRhs; ++q) part[q] = T(0);
@@ -375,7 +388,8 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   }
 }
 
-// Root step in FP64 (Algorithm 2, lines 5-7).  One workgroup of 1024 threads:
+// Root step in FP64 (Algorithm 2, lines 5-7).  One workgroup of 1024 threads per
+// system of the batch:
 // r~_0 = r_0 - sum_s w_s with thread (g, i) summing the scenarios s = g mod 32 of
 // element i and the 32 group partials combined in order; then the two triangular
 // solves with L_R in LDS, one wave per right-hand side, lane i owning row i.
@@ -385,12 +399,15 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
   __shared__ double L[32 * 33];
   __shared__ double r0[kMaxRhs][32];
   const int n = a.n, S = a.S, nrhs = a.nrhs;
-  const size_t len = ((size_t)S * a.N + 1) * n;
-  const size_t root_off = (size_t)S * a.N * n;
+  const int sys = blockIdx.x;
+  const size_t len = vec_len(a);
+  const size_t root_off = (size_t)sys * nrhs * len + (size_t)S * a.N * n;
+  const int seg0 = sys * nrhs;
+  const double* w = a.w + (size_t)sys * S * nrhs * n;  // this system's chains
   const int t = threadIdx.x, i = t & 31, g = t >> 5;
   {
     const int r = t / 32, c = t % 32;
-    L[r * 33 + c] = (r < n && c < n) ? a.LR[r * n + c] : 0.0;
+    L[r * 33 + c] = (r < n && c < n) ? a.LR[(size_t)sys * n * n + r * n + c] : 0.0;
   }
   for (int q = 0; q < nrhs; ++q) {
     double acc = 0.0;
@@ -401,7 +418,7 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
 #pragma unroll
         for (int u = 0; u < B; ++u) {
           const int sc = s0 + 32 * u;
-          v[u] = sc < S ? a.w[((size_t)sc * nrhs + q) * n + i] : 0.0;
+          v[u] = sc < S ? w[((size_t)sc * nrhs + q) * n + i] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < B; ++u) acc += v[u];
@@ -414,7 +431,7 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
       for (int gg = 0; gg < 32; ++gg) sum += part[gg][t];
       double bv = a.b[(size_t)q * len + root_off + t];
       if (a.rnorm) {
-        const double rn = a.rnorm[q];
+        const double rn = a.rnorm[seg0 + q];
         bv = rn > 0.0 ? bv / rn : 0.0;
       }
       r0[q][t] = bv - sum;
@@ -440,8 +457,8 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
   __syncthreads();
   for (int idx = t; idx < n * nrhs; idx += 1024) {
     const int q = idx / n, ii = idx - (idx / n) * n;
-    a.x0[idx] = r0[q][ii];
-    scatter_value(a, q, root_off + ii, r0[q][ii]);
+    a.x0[(size_t)sys * nrhs * n + idx] = r0[q][ii];
+    scatter_value(a, q, root_off + ii, seg0, r0[q][ii]);
   }
 }
 
@@ -461,7 +478,7 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
   fb.template load<true>(reinterpret_cast<const T*>(a.F) + (size_t)s * nn, n);
   for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
     const int q = idx / NMAX, i = idx % NMAX;
-    x0s[q][i] = i < n ? a.x0[q * n + i] : 0.0;
+    x0s[q][i] = i < n ? a.x0[((size_t)(s / a.S) * nrhs + q) * n + i] : 0.0;
     sm.rhs[q][i] = i < n ? yx[q * n + i] : T(0);
   }
   __syncthreads();
@@ -478,14 +495,15 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
     }
   }
   __syncthreads();
-  const size_t off = ((size_t)s * N + 0) * n;
+  const size_t off = vec_off(a, s, 0);
+  const int seg0 = seg_of(a, s);
 #pragma unroll
   for (int q = 0; q < kMaxRhs; ++q) {
     if (q < nrhs) {
       const T v = lane_group_sum<RB::LPR>(lin.dot(sm.rhs[q]));
       if (b == 0 && o < n) {
         yx[q * n + o] = v;
-        scatter_value(a, q, off + o, static_cast<double>(v));
+        scatter_value(a, q, off + o, seg0, static_cast<double>(v));
       }
     }
   }
@@ -510,10 +528,10 @@ void fwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
       std::max(1, std::min(kLevelMaxWaves, (pulls + kPullsPerWave - 1) / kPullsPerWave));
   const size_t sh = level_smem_bytes<T, NMAX>(waves, a.nrhs);
   if (a.n == NMAX)
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, true>), dim3(a.S * count),
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, true>), dim3(a.B * a.S * count),
                        dim3(64 * waves), sh, st, a, level, count);
   else
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, false>), dim3(a.S * count),
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, false>), dim3(a.B * a.S * count),
                        dim3(64 * waves), sh, st, a, level, count);
 }
 template <typename T, int NMAX>
@@ -522,19 +540,19 @@ void bwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
   if (count <= 0) return;
   const size_t sh = level_smem_bytes<T, NMAX>(1, a.nrhs);
   if (a.n == NMAX)
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, true>), dim3(a.S * count), dim3(64),
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, true>), dim3(a.B * a.S * count), dim3(64),
                        sh, st, a, level, count);
   else
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, false>), dim3(a.S * count), dim3(64),
+    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, false>), dim3(a.B * a.S * count), dim3(64),
                        sh, st, a, level, count);
 }
 template <typename T, int NMAX>
 void x_fwd_t(const SolveArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((solve_x_fwd_kernel<T, NMAX>), dim3(a.S), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL((solve_x_fwd_kernel<T, NMAX>), dim3(a.B * a.S), dim3(NT), 0, st, a);
 }
 template <typename T, int NMAX>
 void x_bwd_t(const SolveArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((solve_x_bwd_kernel<T, NMAX>), dim3(a.S), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL((solve_x_bwd_kernel<T, NMAX>), dim3(a.B * a.S), dim3(NT), 0, st, a);
 }
 
 }  // namespace
@@ -556,7 +574,7 @@ void launch_solve_x_bwd(const SolveArgs& a, int nmax, hipStream_t st) {
   BMPC_DISPATCH_NMAX(nmax, x_bwd_t, a, st);
 }
 void launch_solve_root(const SolveArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(solve_root_kernel, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(solve_root_kernel, dim3(a.B), dim3(1024), 0, st, a);
 }
 
 template void launch_solve_fwd_level<double>(const SolveArgs&, int, int, hipStream_t);
