@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--window-depth", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (accuracy + CPU baseline)")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--systems", type=int, default=512,
+                    help="batching workload (--config c4): number of systems")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="batching workload: launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration "
                          "for the HBM traffic figures) and exit")
@@ -71,6 +75,91 @@ def measured_traffic(kernel_class, digest):
     if not ent or ent.get("source_digest") != digest:
         return None
     return ent.get("bytes_per_launch")
+
+
+def bench_hetero(args):
+    """Batching workload: independent systems with S ~ U[8, 256], N ~ U[16, 256],
+    n ~ {8, 16, 32}, delta log-uniform in [1e-4, 1], one right-hand side, FP32 +
+    one refinement correction, grouped into padded uniform batches.  One step solves
+    every system once (factor + refine of every bucket)."""
+    import numpy as np
+    import torch
+
+    from paper_2609_29977_amd import bmpc
+    from paper_2609_29977_amd.batch import HeteroBatch
+    from synth.branch_system_gpu import make_system_gpu
+
+    K = args.systems
+    rng = np.random.default_rng(args.seed)
+    shapes, deltas = [], []
+    for _ in range(K):
+        S = int(rng.integers(8, 257))
+        N = int(rng.integers(16, 257))
+        n = int(rng.choice([8, 16, 32]))
+        shapes.append((S, N, n, 1))
+        deltas.append(float(10 ** rng.uniform(-4, 0)))
+    t0 = time.perf_counter()
+    hb = HeteroBatch(shapes, "fp32")
+    for i, (S, N, n, _) in enumerate(shapes):
+        hb.put(i, *make_system_gpu(S, N, n, 1, deltas[i], 1000 + i))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"{K} systems in {len(hb.groups)} buckets (padded work x{hb.padded_work:.2f}), "
+        f"set up in {time.perf_counter() - t0:.1f}s, "
+        f"{torch.cuda.memory_allocated() / 2**30:.1f} GiB allocated by torch")
+    flops = 0.0
+    for S, N, n, nrhs in shapes:
+        c = bmpc.cost_model(S, N, n, nrhs, "fp32")
+        flops += c.factor_flops + c.solve_flops
+
+    if args.no_graph:
+        def step():
+            hb.solve(refine_tol=0.0, refine_iters=1)
+    else:
+        tc = time.perf_counter()
+        hb.capture(refine_tol=0.0, refine_iters=1)
+        log(f"captured the batch solve in {time.perf_counter() - tc:.2f}s")
+
+        def step():
+            hb.replay()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - w0) * 1e3)
+    bad = hb.info()
+    err = None
+    if not args.no_cpu:
+        from oracle import oracle
+        worst = 0.0
+        for i in (0, K // 2, K - 1):
+            S, N, n, _ = shapes[i]
+            D, E, C, R, b = (t.cpu().numpy() for t in make_system_gpu(S, N, n, 1, deltas[i], 1000 + i))
+            ref, info = oracle.solve(D, E, C, R, b, nthreads=16)
+            x = hb.solution(i).cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(x - ref)) / np.max(np.abs(ref))))
+        err = worst
+    ts = sorted(times)
+    p50 = statistics.median(ts)
+    p99 = ts[min(len(ts) - 1, int(round(0.99 * (len(ts) - 1))))]
+    out = {"metric": "batched independent systems, FP32 + 1 refinement correction",
+           "value": round(K / (p50 * 1e-3), 1), "unit": "systems/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(p50, 3),
+           "p50_ms": round(p50, 3), "p99_ms": round(p99, 3), "higher_is_better": True,
+           "dtype": "f32+f64", "data": "synthetic (device generator)",
+           "config": {"workload": "c4", "systems": K, "S": "U[8,256]", "N": "U[16,256]",
+                      "n": "{8,16,32}", "delta": "log-U[1e-4,1]", "buckets": len(hb.groups),
+                      "padded_work": round(hb.padded_work, 3), "graph": not args.no_graph},
+           "gflops_real_work": round(flops / (p50 * 1e-3) / 1e9, 1),
+           "failed_buckets": bad, "max_rel_err_vs_oracle_sampled": err}
+    print(json.dumps(out))
+    hb.close()
 
 
 def bench_gradients(args):
@@ -160,6 +249,8 @@ def main():
 
     if args.config == "c5":
         return bench_gradients(args)
+    if args.config == "c4":
+        return bench_hetero(args)
 
     S, N, n, nrhs, delta = CONFIGS[args.config]
     t0 = time.perf_counter()
