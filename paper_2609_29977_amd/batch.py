@@ -36,6 +36,7 @@ class _Group:
     nrhs: int
     members: list = field(default_factory=list)  # indices of systems
     plan: object = None
+    stream: object = None
     D: object = None
     E: object = None
     C: object = None
@@ -47,7 +48,7 @@ class _Group:
 class HeteroBatch:
     """Bucketed storage and plans for systems of shapes shapes[i] = (S, N, n, nrhs)."""
 
-    def __init__(self, shapes, precision="fp32", device="cuda"):
+    def __init__(self, shapes, precision="fp32", device="cuda", streams: int = 4):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.precision = precision
         self.device = torch.device(device)
@@ -59,6 +60,15 @@ class HeteroBatch:
             self.slot.append((key, len(g.members)))
             g.members.append(i)
         self.groups = groups
+        # Buckets are independent: they run on `streams` streams (default priority),
+        # longest first onto the least loaded stream, so that small buckets fill the
+        # device together.
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max(1, streams))]
+        load = [0.0] * len(self.streams)
+        for g in sorted(groups.values(), key=lambda g: -len(g.members) * g.S * g.N * g.n ** 3):
+            k = min(range(len(load)), key=load.__getitem__)
+            g.stream = self.streams[k]
+            load[k] += len(g.members) * g.S * g.N * g.n ** 3
         f64 = torch.float64
         for g in groups.values():
             B, S, N, n = len(g.members), g.S, g.N, g.n
@@ -69,7 +79,7 @@ class HeteroBatch:
             g.R = eye.expand(B, n, n).contiguous()
             g.b = torch.zeros((B, g.nrhs, (S * N + 1) * n), dtype=f64, device=self.device)
             g.x = torch.zeros_like(g.b)
-            g.plan = bmpc.Plan(S, N, n, g.nrhs, precision, num_systems=B)
+            g.plan = bmpc.Plan(S, N, n, g.nrhs, precision, num_systems=B, stream=g.stream)
 
     @property
     def padded_work(self) -> float:
@@ -105,7 +115,12 @@ class HeteroBatch:
         return torch.cat([xt, g.x[k, :, g.S * g.N * n:]], dim=1)
 
     def solve(self, refine_tol=0.0, refine_iters=1):
-        """Factor and solve every bucket (FP32 plans: refined; FP64: plain solve)."""
+        """Factor and solve every bucket (FP32 plans: refined; FP64: plain solve).
+        Ordered after the current stream's earlier work; the current stream waits for
+        all buckets."""
+        cur = torch.cuda.current_stream(self.device)
+        for st in self.streams:
+            st.wait_stream(cur)
         for g in self.groups.values():
             E = g.E if g.N > 1 else None
             g.plan.factor(g.D, E, g.C, g.R)
@@ -114,17 +129,17 @@ class HeteroBatch:
             else:
                 g.plan.refine(g.D, E, g.C, g.R, g.b, g.x, tol=refine_tol,
                               max_iters=refine_iters)
+        for st in self.streams:
+            cur.wait_stream(st)
 
     def capture(self, refine_tol=0.0, refine_iters=1):
         """Record solve() once into a HIP graph (torch.cuda.CUDAGraph): the library
         allocates nothing and records no memset in factor/refine, so the launches of
-        every bucket replay as one graph.  The plans run on a side stream from then on."""
+        every bucket, forked over the bucket streams and joined, replay as one graph."""
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            for g in self.groups.values():
-                g.plan.set_stream(side)
-            self.solve(refine_tol, refine_iters)  # warm-up on the capture stream
+            self.solve(refine_tol, refine_iters)  # warm-up
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
