@@ -212,6 +212,34 @@ int32_t bmpc_kernel_class_count(void);
 bmpc_status bmpc_destroy(bmpc_plan plan);
 const char* bmpc_status_string(bmpc_status st);
 
+/* ---- IPM front end ---------------------------------------------------------- */
+
+typedef struct {
+  int32_t S, N;  /* scenarios, stages per tail */
+  int32_t n;     /* block size, 1..32 */
+  int32_t me;    /* equality rows per link, 0..64 */
+  int32_t mi;    /* inequality rows per link, 0..128 */
+} bmpc_qp_dims;
+
+/* Reduced IPM system of a branch-MPC QP (the appendix on the linear systems of IPM and
+ * ADMM): the regularized primal-dual KKT matrix [[P + tau I, A^T, G^T], [A, -delta I,
+ * 0], [G, 0, -(W + delta I)]] reduced to K = P + tau I + delta^{-1} A^T A +
+ * G^T (W + delta I)^{-1} G, written as the D, E, C, R blocks bmpc_factor takes.
+ * The QP terms are given per link of the variable chain: link 0 of scenario s couples
+ * (u, v) = (x_0, x_{s,0}), link k (1 <= k < N) couples (x_{s,k-1}, x_{s,k}), link N is
+ * the terminal term on u = x_{s,N-1} (its v columns must be zero).  Device arrays:
+ *   Q [S][N+1][2n][2n]   link cost Hessians (P = sum of links), variables (u, v)
+ *   A [S][N+1][me][2n]   equality rows,  G [S][N+1][mi][2n] inequality rows
+ *   w [S][N+1][mi]       diagonal of W (positive)
+ * Outputs (device, overwritten): D [S][N][n][n] (both triangles), E [S][N-1][n][n],
+ * C [S][n][n], R [n][n]; work: device scratch of S*n*n doubles.  tau >= 0, delta > 0.
+ * Asynchronous on stream (NULL = legacy default); allocates nothing.  The root block
+ * is summed over the scenarios in scenario order (deterministic). */
+bmpc_status bmpc_assemble_qp(const bmpc_qp_dims* dims, const double* Q, const double* A,
+                             const double* G, const double* w, double tau, double delta,
+                             double* D, double* E, double* C, double* R, double* work,
+                             void* stream);
+
 /* ---- host-only helpers (no device needed) ---------------------------------- */
 
 /* Pi_i for N stages (same content as bmpc_query_perm). */

@@ -24,7 +24,7 @@ EXPORTED = [
     "bmpc_export_root_factor", "bmpc_set_profiling", "bmpc_get_kernel_times",
     "bmpc_reset_kernel_times", "bmpc_kernel_class_name", "bmpc_kernel_class_count",
     "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
-    "bmpc_cost_model", "bmpc_grad_blocks",
+    "bmpc_cost_model", "bmpc_grad_blocks", "bmpc_assemble_qp",
 ]
 
 
@@ -37,6 +37,11 @@ class BmpcError(RuntimeError):
 class _Dims(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int32), ("N", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("nrhs", ctypes.c_int32)]
+
+
+class _QpDims(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("N", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("me", ctypes.c_int32), ("mi", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -101,6 +106,7 @@ def lib():
         "bmpc_structure": [i32, P(i32), P(i32), i64, P(i64)],
         "bmpc_cost_model": [P(_Dims), i32, P(_Options), P(_Cost)],
         "bmpc_grad_blocks": [vp, vp, vp, vp, vp, vp, vp],
+        "bmpc_assemble_qp": [P(_QpDims), vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -185,6 +191,36 @@ def _ptr(t, what, dtype=None, numel=None):
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{what} has {t.numel()} elements, expected {numel}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def assemble_qp(Q, A, G, w, tau: float, delta: float, stream=None):
+    """Reduced IPM system K = P + tau I + A^T A / delta + G^T (W + delta I)^{-1} G of a
+    branch-MPC QP given per link (see bmpc_assemble_qp): returns D, E, C, R (device
+    tensors, FP64) ready for Plan.factor."""
+    import torch
+    S, L, n2, _ = Q.shape
+    N, n = L - 1, n2 // 2
+    me, mi = A.shape[2], G.shape[2]
+    f64 = torch.float64
+    dev = Q.device
+    d = _QpDims(S, N, n, me, mi)
+    D = torch.empty((S, N, n, n), dtype=f64, device=dev)
+    E = torch.empty((S, max(N - 1, 0), n, n), dtype=f64, device=dev)
+    C = torch.empty((S, n, n), dtype=f64, device=dev)
+    R = torch.empty((n, n), dtype=f64, device=dev)
+    work = torch.empty((S, n, n), dtype=f64, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    args = [_ptr(Q, "Q", f64, S * L * n2 * n2), _ptr(A, "A", f64, S * L * me * n2) if me else None,
+            _ptr(G, "G", f64, S * L * mi * n2) if mi else None,
+            _ptr(w, "w", f64, S * L * mi) if mi else None]
+    _check(lib().bmpc_assemble_qp(ctypes.byref(d), *args, float(tau), float(delta),
+                                  ctypes.c_void_p(D.data_ptr()),
+                                  ctypes.c_void_p(E.data_ptr()) if N > 1 else None,
+                                  ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(R.data_ptr()),
+                                  ctypes.c_void_p(work.data_ptr()),
+                                  ctypes.c_void_p(stream.cuda_stream)), "bmpc_assemble_qp")
+    return D, E, C, R
 
 
 class Plan:
