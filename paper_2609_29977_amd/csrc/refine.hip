@@ -16,134 +16,162 @@ namespace bmpc {
 
 namespace {
 
-// Waves per tail work item: the rows of each block are split over WAVES waves so that
-// the three blocks of a stage and their prefetched successors take at most 12 doubles
-// per lane each (about 128 VGPRs at n = 32, four waves per SIMD for this HBM-bound
-// kernel).
-template <int NMAX>
-struct ResCfg {
-  static constexpr int WAVES = NMAX == 32 ? 4 : (NMAX == 16 ? 2 : 1);
-  static constexpr int NT = 64 * WAVES;
-  typedef RegBlock<double, NMAX, WAVES> RB;
-};
+// One 256-thread workgroup walks a chunk of consecutive stages of one tail.  The
+// blocks of a stage (the lower triangle of D, all of E) are read with coalesced 8-byte
+// loads into registers one stage ahead, then staged in double-buffered LDS, where the
+// symmetric product with D and the product with E^T read them transposed; so each E
+// block leaves HBM once and serves both rows it touches.  Row o of the stage's result
+// is summed by RT = min(256 / NMAX, NMAX) threads, each over NMAX / RT columns (at
+// NMAX = 8 only the first 64 threads have a row).  Two stages are in flight: step k
+// computes stage k from LDS while stages k+1 and k+2 arrive in registers.
+constexpr int RES_T = 256;
 
-// Register block of a symmetric matrix stored by its lower triangle, normal mapping:
-// lane holds row o, columns base..base+EPL of sym(D).
+// LDS of a residual workgroup: Ds[2][NMAX][NMAX+1] (D of stage k in Ds[k & 1]),
+// Es[2][NMAX][NMAX+1] (E of stage k in Es[k & 1]; C in Es[1] at stage 0), then
+// xs[3][nrhs][NMAX] and x0s[nrhs][NMAX] (dynamic, sized by nrhs).
 template <int NMAX>
-__device__ inline void load_sym(typename ResCfg<NMAX>::RB& rb, const double* __restrict__ g,
-                                int n) {
-  typedef typename ResCfg<NMAX>::RB RB;
-  const int o = RB::out_index(), b = RB::base();
-  const auto rs = block_rsrc(g, (unsigned)(n * n) * sizeof(double));
-  // element (o, c) is read from whichever triangle holds it; padding reads as zero
-#pragma unroll
-  for (int e = 0; e < RB::EPL; ++e) {
-    const int c = b + e;
-    const int idx = c <= o ? o * n + c : c * n + o;
-    const unsigned off = (o < n && c < n) ? (unsigned)idx * sizeof(double) : kOutOfRange;
-    rb.v[e] = buf_load_f64(rs, off);
-  }
+inline size_t residual_lds_bytes(int nrhs) {
+  return (size_t)(4 * NMAX * (NMAX + 1) + 4 * nrhs * NMAX) * sizeof(double);
 }
 
+// One block of a stage over the NMAX x NMAX grid (padding and, with LOWER, the part
+// above the diagonal read as zero, so the LDS copy never holds stale values).
 template <int NMAX>
-struct StageBlocks {
-  typename ResCfg<NMAX>::RB d, en, et;  // D_k (sym), E_k (normal), E_k (transposed)
-  __device__ void load(const ResidualArgs& a, int s, int k) {
-    const int n = a.n, N = a.N;
-    const size_t nn = (size_t)n * n;
-    load_sym<NMAX>(d, a.D + ((size_t)s * N + k) * nn, n);
-    if (k + 1 < N) {
-      const auto rs = block_rsrc(a.E + ((size_t)s * (N - 1) + k) * nn,
-                                 (unsigned)nn * sizeof(double));
-      en.template load_buf<false>(rs, n);
-      et.template load_buf<true>(rs, n);
+struct BlockFetch {
+  static constexpr int PER = (NMAX * NMAX + RES_T - 1) / RES_T;
+  double v[PER];
+  template <bool LOWER>
+  __device__ void issue(const double* __restrict__ g, int n) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * RES_T;
+      const int r = e / NMAX, c = e % NMAX;
+      const bool ok = e < NMAX * NMAX && r < n && c < n && (!LOWER || c <= r);
+      v[u] = ok ? g[r * n + c] : 0.0;
+    }
+  }
+  __device__ void commit(double* dst) const {
+    constexpr int LD = NMAX + 1;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * RES_T;
+      if (e < NMAX * NMAX) dst[(e / NMAX) * LD + e % NMAX] = v[u];
     }
   }
 };
 
 template <int NMAX>
-__global__ void __launch_bounds__(ResCfg<NMAX>::NT) residual_kernel(ResidualArgs a, int chunks) {
+__global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chunks) {
   if (a.done && *a.done) return;
-  typedef typename ResCfg<NMAX>::RB RB;
-  constexpr int NT = ResCfg<NMAX>::NT;
-  __shared__ double xs[3][kMaxRhs][NMAX];  // x_{k-1}, x_k, x_{k+1} (rotating)
-  __shared__ double x0s[kMaxRhs][NMAX];
+  constexpr int LD = NMAX + 1;
+  constexpr int BS = NMAX * LD;
+  constexpr int RT = RES_T / NMAX < NMAX ? RES_T / NMAX : NMAX;  // threads per row
+  constexpr int CPT = NMAX / RT;                                 // columns per thread
+  static_assert(CPT >= 1 && RT * CPT == NMAX, "row split");
+  extern __shared__ __align__(16) double res_lds[];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
+  double* Ds = res_lds;                // [2][BS]
+  double* Es = res_lds + 2 * BS;       // [2][BS]
+  double* xs = res_lds + 4 * BS;       // [3][nrhs][NMAX]
+  double* x0s = xs + 3 * nrhs * NMAX;  // [nrhs][NMAX]
   const size_t nn = (size_t)n * n;
   const size_t len = ((size_t)S * N + 1) * n;
   const int s = blockIdx.x / chunks;  // chain of the batch
   const int ch = blockIdx.x - s * chunks;
   const int sys = s / S, sl = s - sys * S;
-  const size_t vbase = (size_t)sys * nrhs * len;  // this system's vectors
+  const size_t vbase = (size_t)sys * nrhs * len;
   const int k0 = ch * a.chunk, k1 = min(N, k0 + a.chunk);
-  const int o = RB::out_index(), b = RB::base();
+  const double* Dc = a.D + (size_t)s * N * nn;
+  const double* Ec = a.E + (size_t)s * (N > 1 ? N - 1 : 0) * nn;
+  const int t = threadIdx.x, orow = t / RT, p = t - orow * RT;
+  const int o = orow < NMAX ? orow : 0;  // rows past NMAX (NMAX = 8) compute row 0, unused
 
-  auto load_x = [&](double (*dst)[NMAX], int k) {
-    for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
+  auto load_x = [&](int slot, int k) {
+    for (int idx = t; idx < nrhs * NMAX; idx += RES_T) {
       const int q = idx / NMAX, i = idx % NMAX;
-      dst[q][i] = (k >= 0 && k < N && i < n)
-                      ? a.x[vbase + (size_t)q * len + ((size_t)sl * N + k) * n + i]
-                      : 0.0;
+      xs[(slot * nrhs + q) * NMAX + i] =
+          (k >= 0 && k < N && i < n) ? a.x[vbase + (size_t)q * len + ((size_t)sl * N + k) * n + i]
+                                     : 0.0;
     }
   };
-  int ip = 0, ic = 1, in = 2;  // rotating indices of x_{k-1}, x_k, x_{k+1}
-  load_x(xs[ip], k0 - 1);
-  load_x(xs[ic], k0);
-  if (k0 == 0)
-    for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += NT) {
-      const int q = idx / NMAX, i = idx % NMAX;
-      x0s[q][i] = i < n ? a.x[vbase + (size_t)q * len + (size_t)S * N * n + i] : 0.0;
-    }
-  // carry: this lane's partial of E_{k0-1} x_{k0-1} for row k0, one slot per
-  // right-hand side (LDS, so the loop over right-hand sides need not be unrolled)
-  __shared__ double carry[kMaxRhs][NT];
-  double* my = &carry[0][threadIdx.x];
-  for (int q = 0; q < nrhs; ++q) my[q * NT] = 0.0;
-  StageBlocks<NMAX> cur;
-  cur.load(a, s, k0);
-  if (k0 > 0) {
-    RB ep;
-    ep.template load<false>(a.E + ((size_t)s * (N - 1) + (k0 - 1)) * nn, n);
-    __syncthreads();
-    for (int q = 0; q < nrhs; ++q) my[q * NT] = ep.dot(xs[ip][q]);
+  // stage k0 (and E of k0 - 1) straight into LDS, x of k0 - 1 and k0
+  {
+    BlockFetch<NMAX> fd, fe, fp;
+    fd.template issue<true>(Dc + (size_t)k0 * nn, n);
+    if (k0 + 1 < N) fe.template issue<false>(Ec + (size_t)k0 * nn, n);
+    if (k0 > 0) fp.template issue<false>(Ec + (size_t)(k0 - 1) * nn, n);
+    fd.commit(Ds + (k0 & 1) * BS);
+    if (k0 + 1 < N) fe.commit(Es + (k0 & 1) * BS);
+    if (k0 > 0) fp.commit(Es + ((k0 - 1) & 1) * BS);
+    load_x((k0 + 2) % 3, k0 - 1);
+    load_x(k0 % 3, k0);
+    if (k0 == 0)
+      for (int idx = t; idx < nrhs * NMAX; idx += RES_T) {
+        const int q = idx / NMAX, i = idx % NMAX;
+        x0s[q * NMAX + i] = i < n ? a.x[vbase + (size_t)q * len + (size_t)S * N * n + i] : 0.0;
+      }
   }
-  for (int k = k0; k < k1; ++k) {
-    load_x(xs[in], k + 1);
-    StageBlocks<NMAX> nxt;
-    if (k + 1 < k1) nxt.load(a, s, k + 1);
+  // two stages in flight: fa holds stage k+1, fb stage k+2 when step k starts
+  BlockFetch<NMAX> fa_d, fa_e, fb_d, fb_e;
+  auto issue = [&](BlockFetch<NMAX>& fd, BlockFetch<NMAX>& fe, int k) {
+    if (k < k1) {
+      fd.template issue<true>(Dc + (size_t)k * nn, n);
+      if (k + 1 < N) fe.template issue<false>(Ec + (size_t)k * nn, n);
+    }
+  };
+  issue(fa_d, fa_e, k0 + 1);
+  issue(fb_d, fb_e, k0 + 2);
+  auto step = [&](int k, BlockFetch<NMAX>& fd, BlockFetch<NMAX>& fe) {
+    load_x((k + 1) % 3, k + 1);
+    if (k == 0) {  // C_s into the free E buffer of stage -1
+      BlockFetch<NMAX> fc;
+      fc.template issue<false>(a.C + (size_t)s * nn, n);
+      fc.commit(Es + BS);
+    }
     __syncthreads();
+    const double* D = Ds + (k & 1) * BS;
+    const double* Ek = Es + (k & 1) * BS;
+    const double* Ep = Es + ((k + 1) & 1) * BS;  // E of stage k-1 (or C at k = 0)
+    const double* xm = xs + ((k + 2) % 3) * nrhs * NMAX;
+    const double* xk = xs + (k % 3) * nrhs * NMAX;
+    const double* xp = xs + ((k + 1) % 3) * nrhs * NMAX;
+    const bool has_prev = k > 0, has_next = k + 1 < N;
     const size_t off = vbase + ((size_t)sl * N + k) * n;
 #pragma unroll 1
     for (int q = 0; q < nrhs; ++q) {
-      double p = cur.d.dot(xs[ic][q]) + my[q * NT];
-      if (k + 1 < N) {
-        p += cur.et.dot(xs[in][q]);
-        my[q * NT] = cur.en.dot(xs[ic][q]);
-      }
-      p = lane_group_sum<RB::LPR>(p);
-      if (b == 0 && o < n) a.r[(size_t)q * len + off + o] = a.b[(size_t)q * len + off + o] - p;
-    }
-    if (k == 0) {
-      // C_s^T x_0 enters row 0; w_s = C_s x_{s,0} feeds the root row
-      RB ct, cn;
-      ct.template load<true>(a.C + (size_t)s * nn, n);
-      cn.template load<false>(a.C + (size_t)s * nn, n);
-#pragma unroll 1
-      for (int q = 0; q < nrhs; ++q) {
-        const double pc = lane_group_sum<RB::LPR>(ct.dot(x0s[q]));
-        const double pw = lane_group_sum<RB::LPR>(cn.dot(xs[ic][q]));
-        if (b == 0 && o < n) {
-          a.r[(size_t)q * len + off + o] -= pc;
-          a.w[((size_t)s * nrhs + q) * n + o] = pw;
+      double acc = 0.0, accw = 0.0;
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int c = p * CPT + u;
+        const double dv = c <= o ? D[o * LD + c] : D[c * LD + o];
+        acc += dv * xk[q * NMAX + c];
+        if (has_prev) acc += Ep[o * LD + c] * xm[q * NMAX + c];  // E_{k-1} x_{k-1}
+        if (has_next) acc += Ek[c * LD + o] * xp[q * NMAX + c];  // E_k^T x_{k+1}
+        if (!has_prev) {                                        // k = 0: C^T x_0, C x_{s,0}
+          acc += Ep[c * LD + o] * x0s[q * NMAX + c];
+          accw += Ep[o * LD + c] * xk[q * NMAX + c];
         }
+      }
+#pragma unroll
+      for (int w = 1; w < RT; w <<= 1) {
+        acc += __shfl_xor(acc, w);
+        accw += __shfl_xor(accw, w);
+      }
+      if (p == 0 && orow < n) {
+        a.r[(size_t)q * len + off + o] = a.b[(size_t)q * len + off + o] - acc;
+        if (!has_prev) a.w[((size_t)s * nrhs + q) * n + o] = accw;
       }
     }
     __syncthreads();
-    cur = nxt;
-    const int t = ip;
-    ip = ic;
-    ic = in;
-    in = t;
+    if (k + 1 < k1) {
+      fd.commit(Ds + ((k + 1) & 1) * BS);
+      if (k + 2 < N) fe.commit(Es + ((k + 1) & 1) * BS);
+      issue(fd, fe, k + 3);
+    }
+  };
+  for (int k = k0; k < k1; k += 2) {
+    step(k, fa_d, fa_e);
+    if (k + 1 < k1) step(k + 1, fb_d, fb_e);
   }
 }
 
@@ -292,11 +320,14 @@ void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
   const int chunks = (a.N + a.chunk - 1) / a.chunk;
   const dim3 grid((unsigned)(a.B * a.S) * (unsigned)chunks);
   if (nmax <= 8)
-    hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(ResCfg<8>::NT), 0, st, a, chunks);
+    hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(RES_T), residual_lds_bytes<8>(a.nrhs), st,
+                       a, chunks);
   else if (nmax <= 16)
-    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(ResCfg<16>::NT), 0, st, a, chunks);
+    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(RES_T), residual_lds_bytes<16>(a.nrhs),
+                       st, a, chunks);
   else
-    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(ResCfg<32>::NT), 0, st, a, chunks);
+    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(RES_T), residual_lds_bytes<32>(a.nrhs),
+                       st, a, chunks);
 }
 
 void launch_residual_root(const ResidualArgs& a, hipStream_t st) {
