@@ -192,6 +192,58 @@ struct FetchEven {
   }
 };
 
+// The window's left boundary node: its accumulated updates from earlier passes (AL)
+// and its coupling to its successor (CL: E^T in the first pass, the carried fill after).
+// Fetched into registers before the prologue, placed in LDS after it.
+template <typename T, int NMAX, bool FIRST>
+struct BoundaryFetch {
+  static constexpr int EL = Share<NMAX>::ELEMS;
+  typedef typename std::conditional<FIRST, double, T>::type CT;
+  CT cl[EL];
+  T al[EL];
+
+  __device__ void issue(const FactorPassArgs& a, int s, int lo) {
+    const int n = a.n, N = a.N;
+    const size_t nn = (size_t)n * n;
+    const CT* src;
+    const T* accR = nullptr;
+    const T* accL = nullptr;
+    if constexpr (FIRST) {
+      src = a.E + ((size_t)s * (N - 1) + (N - 1 - lo)) * nn;
+    } else {
+      const size_t o = ((size_t)s * a.stride + lo) * nn;
+      src = reinterpret_cast<const T*>(a.fill_in) + o;
+      accR = reinterpret_cast<const T*>(a.accR_in) + o;
+      accL = reinterpret_cast<const T*>(a.accL_in) + o;
+    }
+#pragma unroll
+    for (int j = 0; j < EL; ++j) {
+      const int e = Share<NMAX>::elem(j);
+      const int r = e / NMAX, c = e % NMAX;
+      const bool in = e < NMAX * NMAX && r < n && c < n;
+      cl[j] = in ? src[r * n + c] : CT(0);
+      if constexpr (!FIRST) al[j] = in ? accR[r * n + c] + accL[r * n + c] : T(0);
+    }
+  }
+
+  __device__ void commit(T* AL, T* CL) const {
+    constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+    for (int j = 0; j < EL; ++j) {
+      const int e = Share<NMAX>::elem(j);
+      if (e >= NMAX * NMAX) continue;
+      const int r = e / NMAX, c = e % NMAX;
+      if constexpr (FIRST) {
+        CL[c * LD + r] = static_cast<T>(cl[j]);  // K[lo+1, lo] = E^T
+        AL[r * LD + c] = T(0);
+      } else {
+        CL[r * LD + c] = cl[j];
+        AL[r * LD + c] = al[j];
+      }
+    }
+  }
+};
+
 template <typename T, int NMAX>
 __device__ inline void slot_store(T* __restrict__ dst, const T* src, int n) {
   constexpr int LD = Lay<NMAX>::LD;
@@ -292,6 +344,9 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
       (unsigned long long)sys * ((unsigned long long)a.Ssys * N + 1) * n +
       (unsigned long long)(s - sys * a.Ssys) * N * n;
 
+  BoundaryFetch<T, NMAX, FIRST> bf;
+  if (has_left) bf.issue(a, s, lo);
+
   // Prologue: the pass-local level-1 positions (odd q) see no update from inside the
   // window, so their diagonal blocks (D plus updates carried from earlier passes) are
   // factored and inverted up front.  Up to kBatch blocks at a time are loaded by the
@@ -388,33 +443,9 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
   if (lo + 1 <= hi) fo.issue(a, s, lo + 1);
   if (lo + 2 <= hi) fe.issue(a, s, lo + 2);
 
-  if (has_left) {
-    // The left boundary node keeps the updates it received while it was a window
-    // boundary in earlier passes; they travel with it in its left accumulator.
-    if constexpr (!FIRST) {
-      const size_t base = (size_t)s * a.stride + lo;
-      slot_load<T, NMAX>(sl.AL(), reinterpret_cast<const T*>(a.accR_in) + base * nn, n, false);
-      slot_load<T, NMAX>(sl.AL(), reinterpret_cast<const T*>(a.accL_in) + base * nn, n, true);
-    } else {
-      slot_zero<T, NMAX>(sl.AL());
-    }
-    // coupling of the left boundary to its successor
-    if constexpr (FIRST) {
-      constexpr int LD = Lay<NMAX>::LD;
-      const double* E = a.E + ((size_t)s * (N - 1) + (N - 1 - lo)) * nn;
-#pragma unroll
-      for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
-        const int e = Share<NMAX>::elem(j);
-        if (e < NMAX * NMAX) {
-          const int r = e / NMAX, c = e % NMAX;
-          sl.CL()[c * LD + r] = (r < n && c < n) ? static_cast<T>(E[r * n + c]) : T(0);
-        }
-      }
-    } else {
-      slot_load<T, NMAX>(sl.CL(), reinterpret_cast<const T*>(a.fill_in) +
-                                      ((size_t)s * a.stride + lo) * nn, n, false);
-    }
-  }
+  // The left boundary node keeps the updates it received while it was a window
+  // boundary in earlier passes; they travel with it in its left accumulator.
+  if (has_left) bf.commit(sl.AL(), sl.CL());
   slot_zero<T, NMAX>(sl.AR());
   __syncthreads();
 

@@ -116,6 +116,37 @@ struct RegBlock {
     }
   }
 
+  // load_packed for n == NMAX without control flow, in two steps so that the loads can
+  // be in flight while other loads are issued: load_packed_raw reads every element at
+  // its packed offset (above the diagonal: an in-range offset of another element), and
+  // mask_packed zeroes the entries above the diagonal.  In the transposed mapping the
+  // offset of row b+e is (b(b+1)/2 + o) + e*b + e(e+1)/2: one lane-varying add and an
+  // immediate per element.
+  template <bool TRANS>
+  __device__ void load_packed_raw(const T* __restrict__ g) {
+    constexpr unsigned SZ = sizeof(T);
+    const int o = out_index(), b = base();
+    const auto rs = block_rsrc(g, (unsigned)(NMAX * (NMAX + 1) / 2) * SZ);
+    const unsigned v0 = TRANS ? (unsigned)(b * (b + 1) / 2 + o) * SZ
+                              : (unsigned)(o * (o + 1) / 2 + b) * SZ;
+    const unsigned st = TRANS ? (unsigned)b * SZ : SZ;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const unsigned off = v0 + e * st + (TRANS ? (unsigned)(e * (e + 1) / 2) * SZ : 0u);
+      if constexpr (sizeof(T) == 8)
+        v[e] = buf_load_f64(rs, off);
+      else
+        v[e] = buf_load_f32(rs, off);
+    }
+  }
+  template <bool TRANS>
+  __device__ void mask_packed() {
+    const int o = out_index(), b = base();
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      if (!(TRANS ? b + e >= o : b + e <= o)) v[e] = T(0);
+  }
+
   // partial sum of this lane's elements against vec[base .. base+EPL) (LDS, padded)
   __device__ T dot(const T* vec) const {
     const int b = base();
@@ -131,6 +162,29 @@ template <int LPR, typename T>
 __device__ inline T lane_group_sum(T p) {
 #pragma unroll
   for (int off = 1; off < LPR; off <<= 1) p += __shfl_xor(p, off);
+  return p;
+}
+
+// The same sum through DPP lane permutations within quads (xor 1, xor 2); wider groups
+// fall back to a shuffle.  Additions are commutative, so all lanes of a group end up
+// with bit-identical sums.
+template <int CTRL>
+__device__ inline float dpp_perm(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_perm(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int LPR, typename T>
+__device__ inline T lane_group_sum_dpp(T p) {
+  if constexpr (LPR >= 2) p += dpp_perm<0xB1>(p);  // quad_perm [1,0,3,2]: lane ^ 1
+  if constexpr (LPR >= 4) p += dpp_perm<0x4E>(p);  // quad_perm [2,3,0,1]: lane ^ 2
+#pragma unroll
+  for (int off = 4; off < LPR; off <<= 1) p += __shfl_xor(p, off);
   return p;
 }
 

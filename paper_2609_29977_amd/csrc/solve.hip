@@ -186,6 +186,29 @@ struct WaveVec {
       v[k] = (q < nrhs && i < n) ? src[q * n + i] : T(0);
     }
   }
+  // n == NMAX: the nrhs x n values are contiguous; a buffer resource over them reads
+  // the padding past nrhs as zero, and rounds past it are skipped wave-uniformly.
+  __device__ void load_full(const T* __restrict__ src, int nrhs) {
+    const int lane = threadIdx.x & 63;
+    const auto rs = block_rsrc(src, (unsigned)(nrhs * NMAX) * sizeof(T));
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (k * 64 < nrhs * NMAX) {
+        const unsigned off = (unsigned)(lane + k * 64) * sizeof(T);
+        if constexpr (sizeof(T) == 8)
+          v[k] = buf_load_f64(rs, off);
+        else
+          v[k] = buf_load_f32(rs, off);
+      }
+    }
+  }
+  __device__ void store_full(T (*dst)[NMAX], int nrhs) const {
+    const int lane = threadIdx.x & 63;
+    T* d = &dst[0][0];
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (k * 64 < nrhs * NMAX && lane + k * 64 < nrhs * NMAX) d[lane + k * 64] = v[k];
+  }
   __device__ void store(T (*dst)[NMAX], int nrhs) const {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -196,6 +219,59 @@ struct WaveVec {
     }
   }
 };
+
+// Right-hand side of a position, held in registers by wave 0 until the pull loads are
+// in flight: the gathered b scaled by 1/rnorm (forward) or the position's y (backward).
+template <typename T, int NMAX, bool FWD>
+struct RhsRegs {
+  static constexpr int PER = (kMaxRhs * NMAX + 63) / 64;
+  typedef typename std::conditional<FWD, double, T>::type RT;
+  RT v[PER];
+  double rn[FWD ? PER : 1];
+  // Lanes past the data read a clamped in-range element; store() drops them, so no
+  // loaded value is used before the factor loads are issued.
+  __device__ void load(const SolveArgs& a, size_t off, int seg0, const T* yj) {
+    const int lane = threadIdx.x & 63;
+    const size_t len = vec_len(a);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (k * 64 >= a.nrhs * NMAX) continue;  // wave-uniform
+      const int idx = lane + k * 64;
+      const int q = min(idx / NMAX, a.nrhs - 1), ii = min(idx % NMAX, a.n - 1);
+      if constexpr (FWD) {
+        v[k] = a.b[(size_t)q * len + off + ii];
+        if (a.rnorm) rn[k] = a.rnorm[seg0 + q];
+      } else {
+        v[k] = yj[q * a.n + ii];
+      }
+    }
+  }
+  __device__ void store(const SolveArgs& a, T (*dst)[NMAX]) const {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (k * 64 >= a.nrhs * NMAX) continue;  // wave-uniform
+      const int idx = lane + k * 64;
+      const int q = idx / NMAX, ii = idx % NMAX;
+      if (q < a.nrhs) {
+        T t = T(0);
+        if (ii < a.n) {
+          if constexpr (FWD) {
+            const double r = a.rnorm ? rn[k] : 1.0;
+            t = static_cast<T>(r > 0.0 ? v[k] / r : 0.0);
+          } else {
+            t = v[k];
+          }
+        }
+        dst[q][ii] = t;
+      }
+    }
+  }
+};
+
+// Right-hand sides whose refinement update (x += rnorm * d) has x and rnorm fetched
+// together with the factor blocks; further ones are read when they are written.
+constexpr int kUpdatePrefetch = 2;
 
 template <typename T, int NMAX, bool FWD, bool FULL>
 __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveArgs a, int level,
@@ -222,6 +298,11 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
   T* yj = y + (size_t)(j - 1) * nrhs * n;
   const int half = 1 << (level - 1);
   const int npull = FWD ? 2 * (level - 1) : 2;
+  const size_t off = vec_off(a, s, N - j);
+  const int seg0 = seg_of(a, s);
+  const size_t len = vec_len(a);
+  const int o = RB::out_index();
+  const bool writer = RB::base() == 0 && o < n;
 
   auto pull = [&](int p, const T*& blk, const T*& vec) -> bool {
     if constexpr (FWD) {
@@ -244,36 +325,34 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
     return true;
   };
 
-  // right-hand side of the position: the gathered b (forward) or its dy (backward)
+  // Every global load of the first round goes out before the first wait: wave 0 takes
+  // L_jj^{-1}, the right-hand side and (backward refinement update) x and rnorm; each
+  // wave its pulls.
+  RB lin;
+  RhsRegs<T, NMAX, FWD> rr;
+  double xold[kUpdatePrefetch] = {}, rnq[kUpdatePrefetch] = {};
   if (wv == 0) {
-    if constexpr (FWD) {
-      const size_t len = vec_len(a);
-      const size_t off = vec_off(a, s, N - j);
-      const int seg0 = seg_of(a, s);
-      for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += 64) {
-        const int q = idx / NMAX, ii = idx % NMAX;
-        T v = T(0);
-        if (ii < n) {
-          double bv = a.b[(size_t)q * len + off + ii];
-          if (a.rnorm) {
-            const double rn = a.rnorm[seg0 + q];
-            bv = rn > 0.0 ? bv / rn : 0.0;
+    if constexpr (FULL)
+      lin.template load_packed_raw<!FWD>(Linv + (size_t)(j - 1) * nn);
+    else
+      lin.template load_packed<!FWD>(Linv + (size_t)(j - 1) * nn, n);
+    rr.load(a, off, seg0, yj);
+    if constexpr (!FWD) {
+      if (a.accumulate) {  // wave-uniform; the writer lanes use the values
+        const int oc = min(o, n - 1);
+#pragma unroll
+        for (int q = 0; q < kUpdatePrefetch; ++q) {
+          if (q < nrhs) {
+            xold[q] = a.x[(size_t)q * len + off + oc];
+            rnq[q] = a.rnorm[seg0 + q];
           }
-          v = static_cast<T>(bv);
         }
-        rhs[q][ii] = v;
-      }
-    } else {
-      for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += 64) {
-        const int q = idx / NMAX, ii = idx % NMAX;
-        rhs[q][ii] = ii < n ? yj[q * n + ii] : T(0);
       }
     }
   }
-
-  RB lin;
-  if (wv == 0) lin.template load_packed<!FWD>(Linv + (size_t)(j - 1) * nn, n);
-  for (int base = 0; base == 0 || base < npull; base += W * P) {
+  // One round: this wave's pulls base + wv*P + u.  The first round is peeled so that
+  // wave 0 stores the right-hand side right after that round's loads are issued.
+  auto round = [&](int base, bool first) {
     RB blk[P];
     WaveVec<T, NMAX> vs[P];
     bool has[P];
@@ -285,12 +364,22 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
       has[u] = p < npull && pull(p, bp, vp);
       if (has[u]) {
         blk[u].template load_fixed<!FWD, FULL>(bp, n);
-        vs[u].load(vp, n, nrhs);
+        if constexpr (FULL)
+          vs[u].load_full(vp, nrhs);
+        else
+          vs[u].load(vp, n, nrhs);
       }
     }
+    if (first && wv == 0) rr.store(a, rhs);
 #pragma unroll
-    for (int u = 0; u < P; ++u)
-      if (has[u]) vs[u].store(vbuf + (size_t)(wv * P + u) * nrhs, nrhs);
+    for (int u = 0; u < P; ++u) {
+      if (has[u]) {
+        if constexpr (FULL)
+          vs[u].store_full(vbuf + (size_t)(wv * P + u) * nrhs, nrhs);
+        else
+          vs[u].store(vbuf + (size_t)(wv * P + u) * nrhs, nrhs);
+      }
+    }
     wave_lds_fence();
     // this wave's partial sums, accumulated over the rounds in its LDS row
 #pragma unroll 1
@@ -301,14 +390,17 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
         if (has[u]) acc += blk[u].dot(vbuf[(size_t)(wv * P + u) * nrhs + q]);
       acc = lane_group_sum<RB::LPR>(acc);
       if (RB::base() == 0) {
-        T* dst = &partial[wv * nrhs + q][RB::out_index()];
-        *dst = base == 0 ? acc : *dst + acc;
+        T* dst = &partial[wv * nrhs + q][o];
+        *dst = first ? acc : *dst + acc;
       }
     }
     wave_lds_fence();
-  }
+  };
+  round(0, true);
+  for (int base = W * P; base < npull; base += W * P) round(base, false);
   __syncthreads();
   if (wv != 0) return;
+  if constexpr (FULL) lin.template mask_packed<!FWD>();
   for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += 64) {
     const int q = idx / NMAX, ii = idx % NMAX;
     T acc = partial[q][ii];
@@ -316,15 +408,175 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
     rhs[q][ii] -= acc;
   }
   wave_lds_fence();
-  const size_t off = vec_off(a, s, N - j);
-  const int seg0 = seg_of(a, s);
-#pragma unroll 1
-  for (int q = 0; q < nrhs; ++q) {
+  // x[off + q*len] = d, or x += rnorm * d with rnorm * d kept in dstore
+  auto finish = [&](int q, double xo, double rn) {
     const T v = lane_group_sum<RB::LPR>(lin.dot(rhs[q]));
-    if (RB::base() == 0 && RB::out_index() < n) {
-      yj[q * n + RB::out_index()] = v;
-      if constexpr (!FWD)
-        scatter_value(a, q, off + RB::out_index(), seg0, static_cast<double>(v));
+    if (writer) {
+      yj[q * n + o] = v;
+      if constexpr (!FWD) {
+        const size_t idx = (size_t)q * len + off + o;
+        const double d = static_cast<double>(v);
+        if (a.accumulate) {
+          const double dd = rn * d;
+          a.x[idx] = xo + dd;
+          a.dstore[idx] = dd;
+        } else {
+          a.x[idx] = d;
+        }
+      }
+    }
+  };
+  if constexpr (FWD) {
+#pragma unroll 1
+    for (int q = 0; q < nrhs; ++q) finish(q, 0.0, 0.0);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kUpdatePrefetch; ++q)
+      if (q < nrhs) finish(q, xold[q], rnq[q]);
+#pragma unroll 1
+    for (int q = kUpdatePrefetch; q < nrhs; ++q) {
+      const size_t idx = (size_t)q * len + off + o;
+      const bool ok = a.accumulate && writer;
+      finish(q, ok ? a.x[idx] : 0.0, ok ? a.rnorm[seg0 + q] : 0.0);
+    }
+  }
+}
+
+// Level kernel for one right-hand side and n == NMAX (the common case): the same
+// products and summation order as solve_level_kernel with the per-element staging of
+// several right-hand sides taken out.  Lane l holds element l % NMAX of each vector it
+// stages; the chain comes from the grid (position index, scenario, system), and each
+// wave keeps its partial sums in a register across rounds.
+template <typename T, int NMAX, bool FWD>
+__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_kernel(SolveArgs a,
+                                                                             int level) {
+  if (a.done && *a.done) return;
+  typedef RegBlock<T, NMAX> RB;
+  constexpr int P = kPullsPerWave;
+  constexpr int n = NMAX;
+  constexpr size_t nn = (size_t)NMAX * NMAX;
+  const int N = a.N, m = a.m;
+  const int W = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  extern __shared__ __align__(16) unsigned char level_smem[];
+  typedef T Vec[NMAX];
+  Vec* vbuf = reinterpret_cast<Vec*>(level_smem);  // [w * P + u]
+  Vec* partial = vbuf + W * P;                     // [w]
+  T* t = partial[W];                               // right-hand side, then residual
+  const int i = blockIdx.x, sl = blockIdx.y, sys = blockIdx.z;
+  const size_t s = (size_t)sys * a.S + sl;
+  const int j = (2 * i + 1) << (level - 1);
+  const size_t gstride = (size_t)(N > 1 ? N - 1 : 1);
+  const T* Gl = reinterpret_cast<const T*>(a.Gl) + s * gstride * nn;
+  const T* Gr = reinterpret_cast<const T*>(a.Gr) + s * gstride * nn;
+  const T* Linv = reinterpret_cast<const T*>(a.Linv) + s * N * nn;
+  T* y = reinterpret_cast<T*>(a.y) + s * N * n;
+  T* yj = y + (size_t)(j - 1) * n;
+  const int half = 1 << (level - 1);
+  const int npull = FWD ? 2 * (level - 1) : 2;
+  const size_t len = ((size_t)a.S * N + 1) * n;
+  const size_t off = (size_t)sys * len + ((size_t)sl * N + (N - j)) * n;
+  const int o = RB::out_index();
+  const bool writer = RB::base() == 0;
+  const int vl = lane & (NMAX - 1);
+
+  auto pull = [&](int p, const T*& blk, const T*& vec) -> bool {
+    if constexpr (FWD) {
+      const int tt = p >> 1;
+      const int c = (p & 1) ? j + (1 << tt) : j - (1 << tt);
+      if (c > m) return false;
+      blk = ((p & 1) ? Gl : Gr) + (size_t)(c - 1) * nn;
+      vec = y + (size_t)(c - 1) * n;
+    } else {
+      if (p == 0) {
+        if (j - half < 1) return false;
+        blk = Gl + (size_t)(j - 1) * nn;
+        vec = y + (size_t)(j - half - 1) * n;
+      } else {
+        const int ir = j + half <= m ? j + half - 1 : N - 1;
+        blk = Gr + (size_t)(j - 1) * nn;
+        vec = y + (size_t)ir * n;
+      }
+    }
+    return true;
+  };
+
+  // All loads of the first round are issued before the first wait.
+  RB lin;
+  T rv = T(0);
+  double rb = 0.0, xo = 0.0;
+  if (wv == 0) {
+    lin.template load_packed_raw<!FWD>(Linv + (size_t)(j - 1) * nn);
+    if constexpr (FWD)
+      rb = a.b[off + vl];
+    else
+      rv = yj[vl];
+    if (!FWD && a.accumulate) xo = a.x[off + o];
+  }
+  T tot = T(0);
+  auto round = [&](int base, bool first) {
+    RB blk[P];
+    T vv[P];
+    bool has[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int p = base + wv * P + u;
+      const T* bp = nullptr;
+      const T* vp = nullptr;
+      has[u] = p < npull && pull(p, bp, vp);
+      if (has[u]) {
+        blk[u].template load_fixed<!FWD, true>(bp, n);
+        vv[u] = vp[vl];
+      }
+    }
+    if (first && wv == 0 && lane < NMAX) {
+      if constexpr (FWD) {
+        const double rn = a.rnorm ? a.rnorm[sys] : 1.0;
+        t[lane] = static_cast<T>(rn > 0.0 ? rb / rn : 0.0);
+      } else {
+        t[lane] = rv;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u)
+      if (has[u] && lane < NMAX) vbuf[wv * P + u][lane] = vv[u];
+    wave_lds_fence();
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < P; ++u)
+      if (has[u]) acc += blk[u].dot(vbuf[wv * P + u]);
+    acc = lane_group_sum_dpp<RB::LPR>(acc);
+    tot = first ? acc : tot + acc;
+    wave_lds_fence();
+  };
+  round(0, true);
+  for (int base = W * P; base < npull; base += W * P) round(base, false);
+  if (W > 1) {
+    if (writer) partial[wv][o] = tot;
+    __syncthreads();
+    if (wv != 0) return;
+    T sum = partial[0][o];
+    for (int w = 1; w < W; ++w) sum += partial[w][o];
+    tot = sum;
+  }
+  // residual of the position, then L_jj^{-1} (forward) or L_jj^{-T} (backward) on it
+  const T r = t[o] - tot;
+  wave_lds_fence();
+  if (writer) t[o] = r;
+  wave_lds_fence();
+  lin.template mask_packed<!FWD>();
+  const T v = lane_group_sum_dpp<RB::LPR>(lin.dot(t));
+  if (writer) {
+    yj[o] = v;
+    if constexpr (!FWD) {
+      const size_t idx = off + o;
+      const double d = static_cast<double>(v);
+      if (a.accumulate) {
+        const double dd = a.rnorm[sys] * d;
+        a.x[idx] = xo + dd;
+        a.dstore[idx] = dd;
+      } else {
+        a.x[idx] = d;
+      }
     }
   }
 }
@@ -519,6 +771,13 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
       FN<T, 32>(__VA_ARGS__);             \
   } while (0)
 
+// One right-hand side, full blocks, and a grid of (positions, scenarios, systems)
+// within the launch limits of the y and z dimensions.
+template <int NMAX>
+inline bool one_rhs_full(const SolveArgs& a) {
+  return a.nrhs == 1 && a.n == NMAX && a.S <= 65535 && a.B <= 65535;
+}
+
 template <typename T, int NMAX>
 void fwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
   const int count = level_count(a.m, level);
@@ -527,7 +786,10 @@ void fwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
   const int waves =
       std::max(1, std::min(kLevelMaxWaves, (pulls + kPullsPerWave - 1) / kPullsPerWave));
   const size_t sh = level_smem_bytes<T, NMAX>(waves, a.nrhs);
-  if (a.n == NMAX)
+  if (one_rhs_full<NMAX>(a))
+    hipLaunchKernelGGL((solve_level_one_kernel<T, NMAX, true>), dim3(count, a.S, a.B),
+                       dim3(64 * waves), sh, st, a, level);
+  else if (a.n == NMAX)
     hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, true>), dim3(a.B * a.S * count),
                        dim3(64 * waves), sh, st, a, level, count);
   else
@@ -539,7 +801,10 @@ void bwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
   const int count = level_count(a.m, level);
   if (count <= 0) return;
   const size_t sh = level_smem_bytes<T, NMAX>(1, a.nrhs);
-  if (a.n == NMAX)
+  if (one_rhs_full<NMAX>(a))
+    hipLaunchKernelGGL((solve_level_one_kernel<T, NMAX, false>), dim3(count, a.S, a.B), dim3(64),
+                       sh, st, a, level);
+  else if (a.n == NMAX)
     hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, true>), dim3(a.B * a.S * count), dim3(64),
                        sh, st, a, level, count);
   else
