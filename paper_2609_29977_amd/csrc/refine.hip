@@ -18,49 +18,100 @@ namespace {
 
 // One 256-thread workgroup walks a chunk of consecutive stages of one tail.  The
 // blocks of a stage (the lower triangle of D, all of E) are read with coalesced 8-byte
-// loads into registers one stage ahead, then staged in double-buffered LDS, where the
-// symmetric product with D and the product with E^T read them transposed; so each E
-// block leaves HBM once and serves both rows it touches.  Row o of the stage's result
-// is summed by RT = min(256 / NMAX, NMAX) threads, each over NMAX / RT columns (at
-// NMAX = 8 only the first 64 threads have a row).  Two stages are in flight: step k
-// computes stage k from LDS while stages k+1 and k+2 arrive in registers.
+// loads into registers two stages ahead, together with the x of the next stage and the
+// b of the stage, then staged in double-buffered LDS, where the symmetric product with
+// D and the product with E^T read them transposed; so each E block leaves HBM once and
+// serves both rows it touches.  Nothing fetched ahead is used before the step that
+// needs it, so the loads of two stages stay in flight while a stage is applied.  Row o
+// of the stage's result is summed by RT = min(256 / NMAX, NMAX) threads, each over
+// NMAX / RT columns (at NMAX = 8 only the first 64 threads have a row).
 constexpr int RES_T = 256;
 
 // LDS of a residual workgroup: Ds[2][NMAX][NMAX+1] (D of stage k in Ds[k & 1]),
 // Es[2][NMAX][NMAX+1] (E of stage k in Es[k & 1]; C in Es[1] at stage 0), then
-// xs[3][nrhs][NMAX] and x0s[nrhs][NMAX] (dynamic, sized by nrhs).
+// xs[3][nrhs][NMAX], x0s[nrhs][NMAX], bs[2][nrhs][NMAX], rs[nrhs][NMAX] and
+// ws[nrhs][NMAX] (dynamic, sized by nrhs).
 template <int NMAX>
 inline size_t residual_lds_bytes(int nrhs) {
-  return (size_t)(4 * NMAX * (NMAX + 1) + 4 * nrhs * NMAX) * sizeof(double);
+  return (size_t)(4 * NMAX * (NMAX + 1) + 8 * nrhs * NMAX) * sizeof(double);
 }
 
-// One block of a stage over the NMAX x NMAX grid (padding and, with LOWER, the part
-// above the diagonal read as zero, so the LDS copy never holds stale values).
-template <int NMAX>
-struct BlockFetch {
+// The blocks and vectors of one stage k, in registers: D_k (lower triangle), E_k (if
+// k + 1 < N), x_{k+1} and b_k.  With FULL (n == NMAX) the blocks are read through a
+// buffer resource (entries above the diagonal of D at an out-of-range offset, so they
+// read as zero and are not fetched); vector lanes past the data read a clamped
+// in-range element.  commit() writes the stage into LDS, zero padded, so the LDS copy
+// never holds stale values.
+template <int NMAX, bool FULL>
+struct StageFetch {
   static constexpr int PER = (NMAX * NMAX + RES_T - 1) / RES_T;
-  double v[PER];
+  static constexpr int VPER = (kMaxRhs * NMAX + RES_T - 1) / RES_T;
+  double d[PER], e[PER], xv[VPER], bv[VPER];
+
+  // A block that does not exist (exists = false) is read as zero without a memory
+  // access, so every fetch issues the same loads.
   template <bool LOWER>
-  __device__ void issue(const double* __restrict__ g, int n) {
+  __device__ static void block(double (&v)[PER], const double* __restrict__ g, int n,
+                               bool exists) {
+    if constexpr (FULL) {
+      const auto rs = block_rsrc(g, exists ? (unsigned)(NMAX * NMAX) * 8u : 0u);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * RES_T;
-      const int r = e / NMAX, c = e % NMAX;
-      const bool ok = e < NMAX * NMAX && r < n && c < n && (!LOWER || c <= r);
-      v[u] = ok ? g[r * n + c] : 0.0;
+      for (int u = 0; u < PER; ++u) {
+        const int el = threadIdx.x + u * RES_T;
+        const int r = el / NMAX, c = el % NMAX;
+        const bool ok = el < NMAX * NMAX && (!LOWER || c <= r);
+        v[u] = buf_load_f64(rs, ok ? (unsigned)el * 8u : kOutOfRange);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int el = threadIdx.x + u * RES_T;
+        const int r = el / NMAX, c = el % NMAX;
+        const bool ok = exists && el < NMAX * NMAX && r < n && c < n && (!LOWER || c <= r);
+        v[u] = ok ? g[r * n + c] : 0.0;
+      }
     }
   }
-  __device__ void commit(double* dst) const {
+  __device__ static void put(double* dst, const double (&v)[PER]) {
     constexpr int LD = NMAX + 1;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * RES_T;
-      if (e < NMAX * NMAX) dst[(e / NMAX) * LD + e % NMAX] = v[u];
+      const int el = threadIdx.x + u * RES_T;
+      if (el < NMAX * NMAX) dst[(el / NMAX) * LD + el % NMAX] = v[u];
+    }
+  }
+  // xk = offset of stage 0 of the chain's vectors (right-hand side 0).  Stages at or
+  // past k1 (the end of the chunk) fetch nothing from the blocks and clamped vectors.
+  __device__ void issue(const ResidualArgs& a, const double* Dc, const double* Ec, size_t xk,
+                        size_t len, int k, int k1) {
+    static_assert(VPER == 1, "one vector element per thread");
+    const int n = a.n, N = a.N, nrhs = a.nrhs;
+    const size_t nn = (size_t)n * n;
+    const int kc = min(k, N - 1);
+    block<true>(d, Dc + (size_t)kc * nn, n, k < k1);
+    block<false>(e, Ec + (size_t)min(kc, N - 2 < 0 ? 0 : N - 2) * nn, n, k < k1 && k + 1 < N);
+    const int idx = threadIdx.x;
+    const int q = min(idx / NMAX, nrhs - 1), i = min(idx % NMAX, n - 1);
+    const size_t base = xk + (size_t)q * len + i;
+    xv[0] = a.x[base + (size_t)min(k + 1, N - 1) * n];
+    bv[0] = a.b[base + (size_t)kc * n];
+  }
+  // stage k into D/E slots, x_{k+1} into xslot, b_k into bslot
+  __device__ void commit(const ResidualArgs& a, int k, double* Dsl, double* Esl, double* xslot,
+                         double* bslot) const {
+    const int n = a.n, N = a.N, nrhs = a.nrhs;
+    put(Dsl, d);
+    if (k + 1 < N) put(Esl, e);
+    const int idx = threadIdx.x;
+    if (idx < nrhs * NMAX) {
+      const bool ok = idx % NMAX < n;
+      xslot[idx] = ok && k + 1 < N ? xv[0] : 0.0;
+      bslot[idx] = ok ? bv[0] : 0.0;
     }
   }
 };
 
-template <int NMAX>
+template <int NMAX, bool FULL>
 __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chunks) {
   if (a.done && *a.done) return;
   constexpr int LD = NMAX + 1;
@@ -68,110 +119,107 @@ __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chu
   constexpr int RT = RES_T / NMAX < NMAX ? RES_T / NMAX : NMAX;  // threads per row
   constexpr int CPT = NMAX / RT;                                 // columns per thread
   static_assert(CPT >= 1 && RT * CPT == NMAX, "row split");
+  typedef StageFetch<NMAX, FULL> SF;
   extern __shared__ __align__(16) double res_lds[];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
+  const int VS = nrhs * NMAX;          // one vector slot
   double* Ds = res_lds;                // [2][BS]
   double* Es = res_lds + 2 * BS;       // [2][BS]
   double* xs = res_lds + 4 * BS;       // [3][nrhs][NMAX]
-  double* x0s = xs + 3 * nrhs * NMAX;  // [nrhs][NMAX]
+  double* x0s = xs + 3 * VS;           // [nrhs][NMAX]
+  double* bs = x0s + VS;               // [2][nrhs][NMAX]
+  double* rs = bs + 2 * VS;            // [nrhs][NMAX] residual of the current stage
+  double* ws = rs + VS;                // [nrhs][NMAX] C_s x_{s,0} (stage 0)
   const size_t nn = (size_t)n * n;
   const size_t len = ((size_t)S * N + 1) * n;
   const int s = blockIdx.x / chunks;  // chain of the batch
   const int ch = blockIdx.x - s * chunks;
   const int sys = s / S, sl = s - sys * S;
   const size_t vbase = (size_t)sys * nrhs * len;
+  const size_t xk = vbase + (size_t)sl * N * n;  // stage 0 of this chain, q = 0
   const int k0 = ch * a.chunk, k1 = min(N, k0 + a.chunk);
   const double* Dc = a.D + (size_t)s * N * nn;
   const double* Ec = a.E + (size_t)s * (N > 1 ? N - 1 : 0) * nn;
   const int t = threadIdx.x, orow = t / RT, p = t - orow * RT;
   const int o = orow < NMAX ? orow : 0;  // rows past NMAX (NMAX = 8) compute row 0, unused
 
-  auto load_x = [&](int slot, int k) {
-    for (int idx = t; idx < nrhs * NMAX; idx += RES_T) {
-      const int q = idx / NMAX, i = idx % NMAX;
-      xs[(slot * nrhs + q) * NMAX + i] =
-          (k >= 0 && k < N && i < n) ? a.x[vbase + (size_t)q * len + ((size_t)sl * N + k) * n + i]
-                                     : 0.0;
-    }
-  };
-  // stage k0 (and E of k0 - 1) straight into LDS, x of k0 - 1 and k0
+  // Prologue: stage k0 with x_{k0+1} and b_{k0}, E_{k0-1} (or C_s at k0 = 0), x_{k0-1},
+  // x_{k0} and (k0 = 0) the root x, all straight into LDS.
   {
-    BlockFetch<NMAX> fd, fe, fp;
-    fd.template issue<true>(Dc + (size_t)k0 * nn, n);
-    if (k0 + 1 < N) fe.template issue<false>(Ec + (size_t)k0 * nn, n);
-    if (k0 > 0) fp.template issue<false>(Ec + (size_t)(k0 - 1) * nn, n);
-    fd.commit(Ds + (k0 & 1) * BS);
-    if (k0 + 1 < N) fe.commit(Es + (k0 & 1) * BS);
-    if (k0 > 0) fp.commit(Es + ((k0 - 1) & 1) * BS);
-    load_x((k0 + 2) % 3, k0 - 1);
-    load_x(k0 % 3, k0);
-    if (k0 == 0)
-      for (int idx = t; idx < nrhs * NMAX; idx += RES_T) {
-        const int q = idx / NMAX, i = idx % NMAX;
-        x0s[q * NMAX + i] = i < n ? a.x[vbase + (size_t)q * len + (size_t)S * N * n + i] : 0.0;
-      }
+    SF f0;
+    double pv[SF::PER];
+    f0.issue(a, Dc, Ec, xk, len, k0, k1);
+    if (k0 > 0)
+      SF::template block<false>(pv, Ec + (size_t)(k0 - 1) * nn, n, true);
+    else
+      SF::template block<false>(pv, a.C + (size_t)s * nn, n, true);
+    for (int idx = t; idx < VS; idx += RES_T) {
+      const int q = idx / NMAX, i = idx % NMAX;
+      const size_t b0 = xk + (size_t)q * len + i;
+      xs[((k0 + 2) % 3) * VS + idx] = (k0 > 0 && i < n) ? a.x[b0 + (size_t)(k0 - 1) * n] : 0.0;
+      xs[(k0 % 3) * VS + idx] = i < n ? a.x[b0 + (size_t)k0 * n] : 0.0;
+      if (k0 == 0)
+        x0s[idx] = i < n ? a.x[vbase + (size_t)q * len + (size_t)S * N * n + i] : 0.0;
+    }
+    f0.commit(a, k0, Ds + (k0 & 1) * BS, Es + (k0 & 1) * BS, xs + ((k0 + 1) % 3) * VS,
+              bs + (k0 & 1) * VS);
+    SF::put(Es + ((k0 + 1) & 1) * BS, pv);
   }
-  // two stages in flight: fa holds stage k+1, fb stage k+2 when step k starts
-  BlockFetch<NMAX> fa_d, fa_e, fb_d, fb_e;
-  auto issue = [&](BlockFetch<NMAX>& fd, BlockFetch<NMAX>& fe, int k) {
-    if (k < k1) {
-      fd.template issue<true>(Dc + (size_t)k * nn, n);
-      if (k + 1 < N) fe.template issue<false>(Ec + (size_t)k * nn, n);
-    }
-  };
-  issue(fa_d, fa_e, k0 + 1);
-  issue(fb_d, fb_e, k0 + 2);
-  auto step = [&](int k, BlockFetch<NMAX>& fd, BlockFetch<NMAX>& fe) {
-    load_x((k + 1) % 3, k + 1);
-    if (k == 0) {  // C_s into the free E buffer of stage -1
-      BlockFetch<NMAX> fc;
-      fc.template issue<false>(a.C + (size_t)s * nn, n);
-      fc.commit(Es + BS);
-    }
+  // Two stages in flight: fa holds stage k+1 and fb stage k+2 when step k starts.  Every
+  // step issues the same loads (past the chunk they fetch nothing) and stores its
+  // residual after the next fetch is issued, so the wait for a stage covers only the
+  // loads issued before it.
+  SF fa, fb;
+  fa.issue(a, Dc, Ec, xk, len, k0 + 1, k1);
+  __builtin_amdgcn_sched_barrier(0);  // keep stage k0+1 ahead of k0+2 in the load queue
+  fb.issue(a, Dc, Ec, xk, len, k0 + 2, k1);
+  auto step = [&](int k, SF& f) {
     __syncthreads();
-    const double* D = Ds + (k & 1) * BS;
-    const double* Ek = Es + (k & 1) * BS;
-    const double* Ep = Es + ((k + 1) & 1) * BS;  // E of stage k-1 (or C at k = 0)
-    const double* xm = xs + ((k + 2) % 3) * nrhs * NMAX;
-    const double* xk = xs + (k % 3) * nrhs * NMAX;
-    const double* xp = xs + ((k + 1) % 3) * nrhs * NMAX;
-    const bool has_prev = k > 0, has_next = k + 1 < N;
-    const size_t off = vbase + ((size_t)sl * N + k) * n;
+    if (k < k1) {
+      const double* D = Ds + (k & 1) * BS;
+      const double* Ek = Es + (k & 1) * BS;
+      const double* Ep = Es + ((k + 1) & 1) * BS;  // E of stage k-1 (or C at k = 0)
+      const double* xm = xs + ((k + 2) % 3) * VS;
+      const double* xkk = xs + (k % 3) * VS;
+      const double* xp = xs + ((k + 1) % 3) * VS;
+      const double* bk = bs + (k & 1) * VS;
+      const bool has_prev = k > 0, has_next = k + 1 < N;
 #pragma unroll 1
-    for (int q = 0; q < nrhs; ++q) {
-      double acc = 0.0, accw = 0.0;
+      for (int q = 0; q < nrhs; ++q) {
+        double acc = 0.0, accw = 0.0;
 #pragma unroll
-      for (int u = 0; u < CPT; ++u) {
-        const int c = p * CPT + u;
-        const double dv = c <= o ? D[o * LD + c] : D[c * LD + o];
-        acc += dv * xk[q * NMAX + c];
-        if (has_prev) acc += Ep[o * LD + c] * xm[q * NMAX + c];  // E_{k-1} x_{k-1}
-        if (has_next) acc += Ek[c * LD + o] * xp[q * NMAX + c];  // E_k^T x_{k+1}
-        if (!has_prev) {                                        // k = 0: C^T x_0, C x_{s,0}
-          acc += Ep[c * LD + o] * x0s[q * NMAX + c];
-          accw += Ep[o * LD + c] * xk[q * NMAX + c];
+        for (int u = 0; u < CPT; ++u) {
+          const int c = p * CPT + u;
+          const double dv = c <= o ? D[o * LD + c] : D[c * LD + o];
+          acc += dv * xkk[q * NMAX + c];
+          if (has_prev) acc += Ep[o * LD + c] * xm[q * NMAX + c];  // E_{k-1} x_{k-1}
+          if (has_next) acc += Ek[c * LD + o] * xp[q * NMAX + c];  // E_k^T x_{k+1}
+          if (!has_prev) {                                        // k = 0: C^T x_0, C x_{s,0}
+            acc += Ep[c * LD + o] * x0s[q * NMAX + c];
+            accw += Ep[o * LD + c] * xkk[q * NMAX + c];
+          }
+        }
+        acc = lane_group_sum_dpp<RT>(acc);
+        if (p == 0 && orow < NMAX) rs[q * NMAX + o] = bk[q * NMAX + o] - acc;
+        if (!has_prev) {
+          accw = lane_group_sum_dpp<RT>(accw);
+          if (p == 0 && orow < NMAX) ws[q * NMAX + o] = accw;
         }
       }
-#pragma unroll
-      for (int w = 1; w < RT; w <<= 1) {
-        acc += __shfl_xor(acc, w);
-        accw += __shfl_xor(accw, w);
-      }
-      if (p == 0 && orow < n) {
-        a.r[(size_t)q * len + off + o] = a.b[(size_t)q * len + off + o] - acc;
-        if (!has_prev) a.w[((size_t)s * nrhs + q) * n + o] = accw;
-      }
     }
     __syncthreads();
-    if (k + 1 < k1) {
-      fd.commit(Ds + ((k + 1) & 1) * BS);
-      if (k + 2 < N) fe.commit(Es + ((k + 1) & 1) * BS);
-      issue(fd, fe, k + 3);
+    f.commit(a, k + 1, Ds + ((k + 1) & 1) * BS, Es + ((k + 1) & 1) * BS,
+             xs + ((k + 2) % 3) * VS, bs + ((k + 1) & 1) * VS);
+    f.issue(a, Dc, Ec, xk, len, k + 3, k1);
+    if (k < k1 && t < VS && t % NMAX < n) {
+      const int q = t / NMAX, i = t % NMAX;
+      a.r[xk + (size_t)q * len + (size_t)k * n + i] = rs[t];
+      if (k == 0) a.w[((size_t)s * nrhs + q) * n + i] = ws[t];
     }
   };
   for (int k = k0; k < k1; k += 2) {
-    step(k, fa_d, fa_e);
-    if (k + 1 < k1) step(k + 1, fb_d, fb_e);
+    step(k, fa);
+    step(k + 1, fb);
   }
 }
 
@@ -316,18 +364,25 @@ __global__ void __launch_bounds__(64) refine_check_kernel(const double* partial,
 
 }  // namespace
 
+template <int NMAX>
+static void launch_residual_t(const ResidualArgs& a, dim3 grid, int chunks, hipStream_t st) {
+  if (a.n == NMAX)
+    hipLaunchKernelGGL((residual_kernel<NMAX, true>), grid, dim3(RES_T),
+                       residual_lds_bytes<NMAX>(a.nrhs), st, a, chunks);
+  else
+    hipLaunchKernelGGL((residual_kernel<NMAX, false>), grid, dim3(RES_T),
+                       residual_lds_bytes<NMAX>(a.nrhs), st, a, chunks);
+}
+
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
   const int chunks = (a.N + a.chunk - 1) / a.chunk;
   const dim3 grid((unsigned)(a.B * a.S) * (unsigned)chunks);
   if (nmax <= 8)
-    hipLaunchKernelGGL(residual_kernel<8>, grid, dim3(RES_T), residual_lds_bytes<8>(a.nrhs), st,
-                       a, chunks);
+    launch_residual_t<8>(a, grid, chunks, st);
   else if (nmax <= 16)
-    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(RES_T), residual_lds_bytes<16>(a.nrhs),
-                       st, a, chunks);
+    launch_residual_t<16>(a, grid, chunks, st);
   else
-    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(RES_T), residual_lds_bytes<32>(a.nrhs),
-                       st, a, chunks);
+    launch_residual_t<32>(a, grid, chunks, st);
 }
 
 void launch_residual_root(const ResidualArgs& a, hipStream_t st) {

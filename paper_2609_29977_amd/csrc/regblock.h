@@ -165,9 +165,10 @@ __device__ inline T lane_group_sum(T p) {
   return p;
 }
 
-// The same sum through DPP lane permutations within quads (xor 1, xor 2); wider groups
-// fall back to a shuffle.  Additions are commutative, so all lanes of a group end up
-// with bit-identical sums.
+// The same sum through DPP lane permutations (xor 1 and xor 2 within quads, then the
+// mirrored quad and the mirrored half row, which pair each partial sum with one that
+// does not overlap it).  Additions are commutative, so all lanes of a group end up with
+// bit-identical sums, in the same pairwise order as lane_group_sum.
 template <int CTRL>
 __device__ inline float dpp_perm(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
@@ -181,10 +182,11 @@ __device__ inline double dpp_perm(double x) {
 }
 template <int LPR, typename T>
 __device__ inline T lane_group_sum_dpp(T p) {
-  if constexpr (LPR >= 2) p += dpp_perm<0xB1>(p);  // quad_perm [1,0,3,2]: lane ^ 1
-  if constexpr (LPR >= 4) p += dpp_perm<0x4E>(p);  // quad_perm [2,3,0,1]: lane ^ 2
-#pragma unroll
-  for (int off = 4; off < LPR; off <<= 1) p += __shfl_xor(p, off);
+  static_assert(LPR >= 1 && LPR <= 16, "groups within a DPP row");
+  if constexpr (LPR >= 2) p += dpp_perm<0xB1>(p);   // quad_perm [1,0,3,2]: lane ^ 1
+  if constexpr (LPR >= 4) p += dpp_perm<0x4E>(p);   // quad_perm [2,3,0,1]: lane ^ 2
+  if constexpr (LPR >= 8) p += dpp_perm<0x141>(p);  // row_half_mirror: the other quad
+  if constexpr (LPR >= 16) p += dpp_perm<0x140>(p); // row_mirror: the other half row
   return p;
 }
 
