@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--ir-steps", type=int, default=1)
     ap.add_argument("--window-depth", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (accuracy + CPU baseline)")
+    ap.add_argument("--separate", action="store_true",
+                    help="time separate factor and solve calls (default: the forward "
+                         "substitution of the first solve runs inside the factorization)")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--systems", type=int, default=512,
                     help="batching workload (--config c4): number of systems")
@@ -346,13 +349,25 @@ def main():
     x32 = torch.empty_like(b)
     x64 = torch.empty_like(b)
 
-    def step32():
+    # The timed step: factor + solve with the first solve's forward substitution inside
+    # the factorization (bmpc_factor_refine / bmpc_factor_solve); --separate times the
+    # separate factor and solve calls instead.  Both are reported.
+    def step32_fused():
+        p32.factor_refine(D, E, C, R, b, x32, tol=0.0, max_iters=args.ir_steps)
+
+    def step64_fused():
+        p64.factor_solve(D, E, C, R, b, x64)
+
+    def step32_sep():
         p32.factor(D, E, C, R)
         p32.refine(D, E, C, R, b, x32, tol=0.0, max_iters=args.ir_steps)
 
-    def step64():
+    def step64_sep():
         p64.factor(D, E, C, R)
         p64.solve(b, x64)
+
+    step32, step64 = (step32_sep, step64_sep) if args.separate else (step32_fused, step64_fused)
+    alt32, alt64 = (step32_fused, step64_fused) if args.separate else (step32_sep, step64_sep)
 
     def timed(step, k):
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
@@ -375,6 +390,13 @@ def main():
     ms32, per32 = timed(step32, args.steps)
     ms64, per64 = timed(step64, args.steps)
     log(f"fp32+ir {ms32:.3f} ms/step, fp64 {ms64:.3f} ms/step")
+    alt32(), alt64()
+    alt_ms32, _ = timed(alt32, args.steps)
+    alt_ms64, _ = timed(alt64, args.steps)
+    log(f"{'fused' if args.separate else 'separate calls'}: fp32+ir {alt_ms32:.3f} ms/step, "
+        f"fp64 {alt_ms64:.3f} ms/step")
+    # the timed path's outputs are the ones checked against the oracle
+    step32(), step64()
 
     # Per-kernel times with HIP events recorded by the library on its stream.
     kt = {}
@@ -456,7 +478,9 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: S={S} N={N} n={n} nrhs={nrhs} delta={delta}, "
-                               f"FP32 factor+solve + {args.ir_steps} FP64-residual refinement step",
+                               f"FP32 factor+solve + {args.ir_steps} FP64-residual refinement step"
+                               + ("" if args.separate else
+                                  "; first forward substitution inside the factorization"),
                    "S": S, "N": N, "n": n, "nrhs": nrhs, "seed": args.seed,
                    "window_depth": p32.cost().window_depth},
         "fp32_ir": {"ms_per_step": round(ms32, 4), "median_ms": round(statistics.median(per32), 4),
@@ -469,6 +493,9 @@ def main():
                  "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
                                          for k, v in kt["fp64"].items()}},
         "fp32_ir_speedup_vs_fp64": round(ms64 / ms32, 3),
+        "forward_in_factor": not args.separate,
+        ("fused" if args.separate else "separate_calls"): {
+            "fp32_ir_ms_per_step": round(alt_ms32, 4), "fp64_ms_per_step": round(alt_ms64, 4)},
         "method_flops_per_step": flops,
         "analyze_ms": round(analyze_ms, 2),
         "roofline": roofline,

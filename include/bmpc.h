@@ -143,6 +143,24 @@ bmpc_status bmpc_refine(bmpc_plan plan, const double* D, const double* E,
                         const double* C, const double* R, const double* b, double* x,
                         double tol, int32_t max_iters);
 
+/* bmpc_factor followed by bmpc_solve(b, x), with the tail forward substitution
+ * (Algorithm 2, lines 1-4) carried out inside the factorization: each chain position
+ * applies its L_jj^{-1} to its right-hand side when it is eliminated and passes
+ * -G y_j to its two neighbours, in the elimination order of Algorithm 1, so the
+ * forward sweep does not read the factor again.  Same result as the two calls up to
+ * rounding order; same arguments and errors as bmpc_factor and bmpc_solve (x may
+ * alias b).  The factor stays in the plan for later bmpc_solve calls. */
+bmpc_status bmpc_factor_solve(bmpc_plan plan, const double* D, const double* E,
+                              const double* C, const double* R, const double* b, double* x);
+
+/* bmpc_factor followed by bmpc_refine, with the first solve's forward substitution
+ * inside the factorization as in bmpc_factor_solve; the correction solves are
+ * ordinary solves.  Same arguments and errors as bmpc_refine (x must not alias b),
+ * except that no earlier factor is needed. */
+bmpc_status bmpc_factor_refine(bmpc_plan plan, const double* D, const double* E,
+                               const double* C, const double* R, const double* b, double* x,
+                               double tol, int32_t max_iters);
+
 /* Gradients of a loss through x = K^{-1} b (not one of the paper's algorithms; the
  * derivative of its linear solve).  Differentiating K x = b for a loss l with
  * g = dl/dx gives the adjoint lam = K^{-1} g (K is symmetric: call bmpc_solve on g

@@ -24,7 +24,8 @@ EXPORTED = [
     "bmpc_export_root_factor", "bmpc_set_profiling", "bmpc_get_kernel_times",
     "bmpc_reset_kernel_times", "bmpc_kernel_class_name", "bmpc_kernel_class_count",
     "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
-    "bmpc_cost_model", "bmpc_grad_blocks", "bmpc_assemble_qp",
+    "bmpc_cost_model", "bmpc_grad_blocks", "bmpc_assemble_qp", "bmpc_factor_solve",
+    "bmpc_factor_refine",
 ]
 
 
@@ -91,6 +92,8 @@ def lib():
         "bmpc_factor": [vp, vp, vp, vp, vp],
         "bmpc_solve": [vp, vp, vp],
         "bmpc_refine": [vp, vp, vp, vp, vp, vp, vp, dbl, i32],
+        "bmpc_factor_solve": [vp, vp, vp, vp, vp, vp, vp],
+        "bmpc_factor_refine": [vp, vp, vp, vp, vp, vp, vp, dbl, i32],
         "bmpc_get_info": [vp, P(i64)],
         "bmpc_get_stats": [vp, P(i32), P(dbl)],
         "bmpc_query_perm": [vp, P(i32)],
@@ -294,6 +297,21 @@ class Plan:
         pb, px, x = self._rhs(b, x)
         _check(lib().bmpc_refine(self._h, *blocks, pb, px, float(tol), int(max_iters)),
                "bmpc_refine")
+        return x
+
+    def factor_solve(self, D, E, C, R, b, x=None):
+        """factor + solve with the forward substitution inside the factorization."""
+        blocks = self._blocks(D, E, C, R)
+        pb, px, x = self._rhs(b, x)
+        _check(lib().bmpc_factor_solve(self._h, *blocks, pb, px), "bmpc_factor_solve")
+        return x
+
+    def factor_refine(self, D, E, C, R, b, x=None, tol: float = 1e-12, max_iters: int = 10):
+        """factor + refine, the first solve's forward part inside the factorization."""
+        blocks = self._blocks(D, E, C, R)
+        pb, px, x = self._rhs(b, x)
+        _check(lib().bmpc_factor_refine(self._h, *blocks, pb, px, float(tol), int(max_iters)),
+               "bmpc_factor_refine")
         return x
 
     def grad_blocks(self, x, lam):

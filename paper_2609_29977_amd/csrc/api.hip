@@ -14,7 +14,7 @@
 #include "bmpc_internal.h"
 
 namespace bmpc {
-size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw);
+size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw, int nrhs_fused);
 }
 
 using namespace bmpc;
@@ -190,6 +190,8 @@ struct bmpc_plan_s {
   double* LR = nullptr;
   void* acc[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   void* accX = nullptr;
+  void* vacc[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // fused forward: R, L
+  void* vaccX = nullptr;
   int* d_permpos = nullptr;
   unsigned long long* d_info = nullptr;
   void* y = nullptr;
@@ -285,16 +287,21 @@ bool dalloc(bmpc_plan p, void** ptr, size_t bytes) {
   return true;
 }
 
-int pick_window_depth(bool fp64, int nmax, const bmpc_options* o) {
+// The LDS of a pass includes the right-hand-side slots of the fused forward
+// substitution for the plan's nrhs, so that path always fits.
+int pick_window_depth(bool fp64, int nmax, int nrhs, const bmpc_options* o) {
   int Tw = (o && o->window_depth > 0) ? o->window_depth : default_window_depth(fp64, nmax);
   Tw = std::min(Tw, kMaxWindowDepth);
-  while (Tw > 1 && factor_pass_lds_bytes(fp64, nmax, Tw) > (size_t)kLdsBudget) --Tw;
+  while (Tw > 1 && factor_pass_lds_bytes(fp64, nmax, Tw, nrhs) > (size_t)kLdsBudget) --Tw;
   return Tw;
 }
 
+// Factor passes and root factor; a non-null b also runs the tail forward substitution
+// of that right-hand side inside the passes (y and w as the forward sweep and the X
+// step of the solve leave them).
 template <typename T>
 void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double* C,
-                    const double* R) {
+                    const double* R, const double* b = nullptr) {
   const bmpc_dims& d = p->d;
   hipStream_t st = p->stream;
   timed(p, KC_FACTOR_INIT, [&] { launch_factor_init(p->d_info, st); });
@@ -333,6 +340,17 @@ void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double*
     a.U = p->U;
     a.permpos = p->d_permpos;
     a.info = p->d_info;
+    if (b) {
+      a.b = b;
+      a.nrhs = d.nrhs;
+      a.y = p->y;
+      a.w = p->w;
+      a.vaccR_in = k > 0 ? p->vacc[in][0] : nullptr;
+      a.vaccL_in = k > 0 ? p->vacc[in][1] : nullptr;
+      a.vaccR_out = p->vacc[out][0];
+      a.vaccL_out = p->vacc[out][1];
+      a.vaccX = p->vaccX;
+    }
     const int cls = pp.is_final ? KC_FACTOR_FINAL : (k == 0 ? KC_FACTOR_FIRST : KC_FACTOR_MID);
     timed(p, cls, [&] { launch_factor_pass<T>(a, p->nmax, st); });
   }
@@ -367,6 +385,18 @@ SolveArgs solve_args(bmpc_plan p, const double* b, double* x) {
   return a;
 }
 
+// Root step, root propagation and tail backward substitution (Algorithm 2 from line 5
+// on), given the y and w of the forward part.
+template <typename T>
+void enqueue_solve_back(bmpc_plan p, const SolveArgs& a) {
+  hipStream_t st = p->stream;
+  const int L = chain_levels(p->m);
+  timed(p, KC_SOLVE_ROOT, [&] { launch_solve_root(a, st); });
+  timed(p, KC_SOLVE_X_BWD, [&] { launch_solve_x_bwd<T>(a, p->nmax, st); });
+  for (int l = L; l >= 1; --l)
+    timed(p, KC_SOLVE_BWD, [&] { launch_solve_bwd_level<T>(a, l, p->nmax, st); });
+}
+
 template <typename T>
 void enqueue_solve(bmpc_plan p, const SolveArgs& a) {
   hipStream_t st = p->stream;
@@ -374,10 +404,7 @@ void enqueue_solve(bmpc_plan p, const SolveArgs& a) {
   for (int l = 1; l <= L; ++l)
     timed(p, KC_SOLVE_FWD, [&] { launch_solve_fwd_level<T>(a, l, p->nmax, st); });
   timed(p, KC_SOLVE_X_FWD, [&] { launch_solve_x_fwd<T>(a, p->nmax, st); });
-  timed(p, KC_SOLVE_ROOT, [&] { launch_solve_root(a, st); });
-  timed(p, KC_SOLVE_X_BWD, [&] { launch_solve_x_bwd<T>(a, p->nmax, st); });
-  for (int l = L; l >= 1; --l)
-    timed(p, KC_SOLVE_BWD, [&] { launch_solve_bwd_level<T>(a, l, p->nmax, st); });
+  enqueue_solve_back<T>(p, a);
 }
 
 bmpc_status last_error_status() {
@@ -438,7 +465,7 @@ bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
       (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
     return BMPC_ERR_INVALID;
   const bool fp64 = prec == BMPC_FP64;
-  const int Tw = pick_window_depth(fp64, nmax_for(dims->n), opts);
+  const int Tw = pick_window_depth(fp64, nmax_for(dims->n), dims->nrhs, opts);
   Costs c = make_costs(*dims, fp64, Tw, systems_of(opts));
   std::memset(cost, 0, sizeof(*cost));
   cost->factor_flops = c.factor_flops;
@@ -467,7 +494,7 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
   p->fp64 = prec == BMPC_FP64;
   p->m = dims->N - 1;
   p->nmax = nmax_for(dims->n);
-  p->Tw = pick_window_depth(p->fp64, p->nmax, opts);
+  p->Tw = pick_window_depth(p->fp64, p->nmax, dims->nrhs, opts);
   p->B = systems_of(opts);
   p->stream = reinterpret_cast<hipStream_t>(stream);
   p->costs = make_costs(*dims, p->fp64, p->Tw, p->B);
@@ -490,6 +517,7 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
             dalloc(p, (void**)&p->Upart, (size_t)B * p->groups * nn * 8) &&
             dalloc(p, (void**)&p->LR, (size_t)B * nn * 8) &&
             dalloc(p, &p->accX, S * npass * nn * tb) &&
+            dalloc(p, &p->vaccX, S * npass * nrhs * n * tb) &&
             dalloc(p, (void**)&p->d_permpos, (size_t)N * sizeof(int)) &&
             dalloc(p, (void**)&p->d_info, sizeof(unsigned long long)) &&
             dalloc(p, &p->y, S * N * nrhs * n * tb) &&
@@ -501,9 +529,12 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
             dalloc(p, (void**)&p->flags, 2 * sizeof(int)) &&
             dalloc(p, (void**)&p->relcorr, sizeof(double));
   if (ok && npass > 1) {
-    for (int set = 0; set < 2 && ok; ++set)
+    for (int set = 0; set < 2 && ok; ++set) {
       for (int b = 0; b < 3 && ok; ++b)
         ok = dalloc(p, &p->acc[set][b], S * p->stride * nn * tb);
+      for (int b = 0; b < 2 && ok; ++b)
+        ok = dalloc(p, &p->vacc[set][b], S * p->stride * nrhs * n * tb);
+    }
   }
   if (!ok) {
     free_plan_memory(p);
@@ -554,12 +585,14 @@ bmpc_status bmpc_solve(bmpc_plan p, const double* b, double* x) {
   return last_error_status();
 }
 
-bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const double* C,
+// x = K^{-1} b by refinement (see bmpc_refine); with fused, the factor is issued here
+// and the first solve's forward part runs inside it.
+static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, const double* C,
                         const double* R, const double* b, double* x, double tol,
-                        int32_t max_iters) {
+                        int32_t max_iters, bool fused) {
   if (!p || !D || !C || !R || !b || !x || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
   if (max_iters < 0 || max_iters > 100 || !(tol >= 0.0) || x == b) return BMPC_ERR_INVALID;
-  if (!p->factored) return BMPC_ERR_STATE;
+  if (!fused && !p->factored) return BMPC_ERR_STATE;
   hipStream_t st = p->stream;
   const int nrhs = p->d.nrhs;
   const int segs = p->B * nrhs;  // norms per (system, right-hand side)
@@ -569,10 +602,23 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
   double* xnorm = p->norms + 2 * segs;
   timed(p, KC_REFINE_MISC, [&] { launch_refine_reset(p->flags, st); });
   SolveArgs a = solve_args(p, b, x);
-  if (p->fp64)
-    enqueue_solve<double>(p, a);
-  else
-    enqueue_solve<float>(p, a);
+  if (fused) {
+    if (p->fp64)
+      enqueue_factor<double>(p, D, E, C, R, b);
+    else
+      enqueue_factor<float>(p, D, E, C, R, b);
+    if (last_error_status() != BMPC_OK) return BMPC_ERR_DEVICE;
+    p->factored = true;
+    if (p->fp64)
+      enqueue_solve_back<double>(p, a);
+    else
+      enqueue_solve_back<float>(p, a);
+  } else {
+    if (p->fp64)
+      enqueue_solve<double>(p, a);
+    else
+      enqueue_solve<float>(p, a);
+  }
   ResidualArgs ra{};
   ra.S = p->d.S;
   ra.B = p->B;
@@ -611,6 +657,36 @@ bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const dou
     });
   }
   p->last_max_iters = max_iters;
+  return last_error_status();
+}
+
+bmpc_status bmpc_refine(bmpc_plan p, const double* D, const double* E, const double* C,
+                        const double* R, const double* b, double* x, double tol,
+                        int32_t max_iters) {
+  return refine_impl(p, D, E, C, R, b, x, tol, max_iters, false);
+}
+
+bmpc_status bmpc_factor_refine(bmpc_plan p, const double* D, const double* E, const double* C,
+                               const double* R, const double* b, double* x, double tol,
+                               int32_t max_iters) {
+  return refine_impl(p, D, E, C, R, b, x, tol, max_iters, true);
+}
+
+bmpc_status bmpc_factor_solve(bmpc_plan p, const double* D, const double* E, const double* C,
+                              const double* R, const double* b, double* x) {
+  if (!p || !D || !C || !R || !b || !x || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
+  if (p->fp64)
+    enqueue_factor<double>(p, D, E, C, R, b);
+  else
+    enqueue_factor<float>(p, D, E, C, R, b);
+  bmpc_status st = last_error_status();
+  if (st != BMPC_OK) return st;
+  p->factored = true;
+  SolveArgs a = solve_args(p, b, x);
+  if (p->fp64)
+    enqueue_solve_back<double>(p, a);
+  else
+    enqueue_solve_back<float>(p, a);
   return last_error_status();
 }
 

@@ -81,6 +81,20 @@ struct FactorPassArgs {
   double* U;
   const int* permpos;   // [N] permuted position of chain position j at j-1 (X at N-1)
   unsigned long long* info;
+  // Forward substitution fused into the elimination (null b: factor only).  b is the
+  // FP64 right-hand side in the vector layout of the solve ([B][nrhs][len]); y
+  // receives L^{-1} Pi b per chain position ([S][N][nrhs][n], precision T) and w the
+  // FP64 products F_s y_X ([S][nrhs][n]).  The vector accumulators mirror accR /
+  // accL / accX per right-hand side ([S][stride][nrhs][n] and [S][npass][nrhs][n]).
+  const double* b;
+  int nrhs;
+  void* y;
+  double* w;
+  const void* vaccR_in;
+  const void* vaccL_in;
+  void* vaccR_out;
+  void* vaccL_out;
+  void* vaccX;
 };
 
 struct SolveArgs {

@@ -37,11 +37,19 @@ struct Slots {
   static constexpr int SZ = Lay<NMAX>::SZ;
   T* base;
   int Tw;
+  int VS;  // one right-hand-side slot: nrhs x NMAX (fused forward substitution)
   __device__ T* A(int t) const { return base + (2 * t) * SZ; }
   __device__ T* Cp(int t) const { return base + (2 * t + 1) * SZ; }
   __device__ T* AL() const { return base + (2 * Tw) * SZ; }
   __device__ T* CL() const { return base + (2 * Tw + 1) * SZ; }
   __device__ T* AR() const { return base + (2 * Tw + 2) * SZ; }
+  // right-hand sides of the live nodes (by level), the boundaries, y_j and the pushes
+  __device__ T* V(int t) const { return base + (2 * Tw + 3) * SZ + t * VS; }
+  __device__ T* VL() const { return V(Tw); }
+  __device__ T* VR() const { return V(Tw + 1); }
+  __device__ T* Y() const { return V(Tw + 2); }
+  __device__ T* Pr() const { return V(Tw + 3); }  // pushes of an elimination
+  __device__ T* Pl() const { return V(Tw + 4); }
 };
 
 // Per-thread share of an NMAX x NMAX block: element e = threadIdx.x + j*NT.
@@ -78,22 +86,189 @@ __device__ inline void slot_load(T* dst, const S* __restrict__ src, int n, bool 
   }
 }
 
+// Fused forward substitution: the right-hand side of a chain node, b at its stage plus
+// (after the first pass) the vector updates carried from earlier passes, in the same
+// order as the diagonal block (D + accR + accL).  Lanes past the data read a clamped
+// in-range element; commit() zero pads.
+// Chain bases of the fused forward substitution, computed once per workgroup: b at
+// stage 0 of the chain (right-hand side 0; the stage of position j is N - j), the
+// vector length, and the chain's carried vector updates.
+template <typename T>
+struct VecChain {
+  const double* b;
+  size_t len;
+  const T* vR;
+  const T* vL;
+};
+
+template <typename T, int NMAX, bool FIRST, bool FWD>
+struct VecFetch {
+  static constexpr int NT = TileCfg<NMAX>::NT;
+  static constexpr int VPER = FWD ? (kMaxRhs * NMAX + NT - 1) / NT : 1;
+  double bv[VPER];
+  T cr[VPER], cl[VPER];
+
+  __device__ void issue(const FactorPassArgs& a, const VecChain<T>& vc, int q) {
+    if constexpr (!FWD) return;
+    const int n = a.n, nrhs = a.nrhs;
+    const double* bj = vc.b + (size_t)(a.N - (q << a.shift)) * n;
+    const int vo = q * nrhs * n;
+#pragma unroll
+    for (int u = 0; u < VPER; ++u) {
+      if (u * NT >= nrhs * NMAX) continue;  // wave-uniform
+      const int idx = threadIdx.x + u * NT;
+      const int qr = min(idx / NMAX, nrhs - 1), i = min(idx % NMAX, n - 1);
+      bv[u] = bj[(size_t)qr * vc.len + i];
+      if constexpr (!FIRST) {
+        cr[u] = vc.vR[vo + qr * n + i];
+        cl[u] = vc.vL[vo + qr * n + i];
+      }
+    }
+  }
+
+  __device__ void commit(const FactorPassArgs& a, T* V) const {
+    if constexpr (!FWD) return;
+    const int n = a.n, nrhs = a.nrhs;
+#pragma unroll
+    for (int u = 0; u < VPER; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      if (u * NT >= nrhs * NMAX || idx >= nrhs * NMAX) continue;
+      T v = T(0);
+      if (idx % NMAX < n) {
+        v = static_cast<T>(bv[u]);
+        if constexpr (!FIRST) v = (v + cr[u]) + cl[u];
+      }
+      V[idx] = v;
+    }
+  }
+};
+
+// Vector part of the window's left boundary: the updates it received in earlier passes
+// (nothing in the first pass).  The right boundary starts from zero.
+template <typename T, int NMAX, bool FIRST, bool FWD>
+struct BoundaryVec {
+  static constexpr int NT = TileCfg<NMAX>::NT;
+  static constexpr int VPER = FWD ? (kMaxRhs * NMAX + NT - 1) / NT : 1;
+  T cr[VPER] = {}, cl[VPER] = {};
+
+  __device__ void issue(const FactorPassArgs& a, int s, int lo) {
+    if constexpr (!FIRST && FWD) {
+      const int n = a.n, nrhs = a.nrhs;
+      const size_t vo = ((size_t)s * a.stride + lo) * nrhs * n;
+#pragma unroll
+      for (int u = 0; u < VPER; ++u) {
+        if (u * NT >= nrhs * NMAX) continue;
+        const int idx = threadIdx.x + u * NT;
+        const int qr = min(idx / NMAX, nrhs - 1), i = min(idx % NMAX, n - 1);
+        cr[u] = reinterpret_cast<const T*>(a.vaccR_in)[vo + qr * n + i];
+        cl[u] = reinterpret_cast<const T*>(a.vaccL_in)[vo + qr * n + i];
+      }
+    }
+  }
+
+  __device__ void commit(const FactorPassArgs& a, T* VL, T* VR) const {
+    if constexpr (!FWD) return;
+    const int n = a.n, nrhs = a.nrhs;
+#pragma unroll
+    for (int u = 0; u < VPER; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      if (u * NT >= nrhs * NMAX || idx >= nrhs * NMAX) continue;
+      T v = T(0);
+      if constexpr (!FIRST)
+        if (idx % NMAX < n) v = cr[u] + cl[u];
+      VL[idx] = v;
+      VR[idx] = T(0);
+    }
+  }
+};
+
+// dst[q][i] (n-compact) = V[q][i] (NMAX-padded) for the nrhs right-hand sides.
+template <typename T, int NMAX>
+__device__ inline void vec_store(T* __restrict__ dst, const T* V, int n, int nrhs) {
+  for (int idx = threadIdx.x; idx < nrhs * n; idx += TileCfg<NMAX>::NT)
+    dst[idx] = V[(idx / n) * NMAX + idx % n];
+}
+
+// out[q][o] = sum_c M[o][c] v[q][c] for the LDS block M (rows of NMAX, stride LD) and
+// the padded vectors v: row o is split over TPR = NT / NMAX threads (DPP sum); the
+// thread with p == 0 calls put(q, o, value).
+template <typename T, int NMAX, typename Put>
+__device__ inline void block_matvec(const T* M, const T* v, int nrhs, Put put) {
+  constexpr int NT = TileCfg<NMAX>::NT;
+  constexpr int LD = Lay<NMAX>::LD;
+  constexpr int TPR = NT / NMAX;
+  constexpr int CPT = NMAX / TPR;
+  const int o = threadIdx.x / TPR, p = threadIdx.x % TPR;
+  for (int q = 0; q < nrhs; ++q) {
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) acc += M[o * LD + p * CPT + u] * v[q * NMAX + p * CPT + u];
+    acc = lane_group_sum_dpp<TPR>(acc);
+    if (p == 0) put(q, o, acc);
+  }
+}
+
+// Both pushes of an elimination, V_r -= G_r y and (with a left neighbour)
+// V_l -= G_l y, in two steps so that each overlaps other work of the elimination:
+// push_products forms the reduced sums (G and y read from LDS, same thread split as
+// block_matvec) into the LDS vectors Pr, Pl; push_apply subtracts them later, one
+// element per thread.
+template <typename T, int NMAX>
+__device__ inline void push_products(const T* Gr, const T* Gl, const T* y, T* Pr, T* Pl,
+                                     int nrhs) {
+  constexpr int NT = TileCfg<NMAX>::NT;
+  constexpr int LD = Lay<NMAX>::LD;
+  constexpr int TPR = NT / NMAX;
+  constexpr int CPT = NMAX / TPR;
+  const int o = threadIdx.x / TPR, p = threadIdx.x % TPR;
+  T gr[CPT], gl[CPT];
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) {
+    gr[u] = Gr[o * LD + p * CPT + u];
+    gl[u] = Gl ? Gl[o * LD + p * CPT + u] : T(0);
+  }
+  for (int q = 0; q < nrhs; ++q) {
+    T r = T(0), l = T(0);
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const T yv = y[q * NMAX + p * CPT + u];
+      r += gr[u] * yv;
+      l += gl[u] * yv;
+    }
+    r = lane_group_sum_dpp<TPR>(r);
+    if (Gl) l = lane_group_sum_dpp<TPR>(l);
+    if (p == 0) {
+      Pr[q * NMAX + o] = r;
+      if (Gl) Pl[q * NMAX + o] = l;
+    }
+  }
+}
+template <typename T, int NMAX>
+__device__ inline void push_apply(T* Vr, T* Vl, const T* Pr, const T* Pl, int nrhs) {
+  for (int idx = threadIdx.x; idx < nrhs * NMAX; idx += TileCfg<NMAX>::NT) {
+    Vr[idx] -= Pr[idx];
+    if (Vl) Vl[idx] -= Pl[idx];
+  }
+}
+
 // Register prefetch of chain nodes, issued a pair of positions ahead so that the
 // global loads overlap the eliminations in between.  Odd pass-local positions were
 // factored by the window prologue: their fetch reloads L^{-1} and the coupling to the
 // successor.  Even positions fetch D plus the updates carried from earlier passes and
 // the coupling.
-template <typename T, int NMAX, bool FIRST>
+template <typename T, int NMAX, bool FIRST, bool FWD>
 struct FetchOdd {
   static constexpr int EL = Share<NMAX>::ELEMS;
   typedef typename std::conditional<FIRST, double, T>::type CT;
   T li[EL];
   CT cp[EL];
+  VecFetch<T, NMAX, FIRST, FWD> vf;
 
-  __device__ void issue(const FactorPassArgs& a, int s, int q) {
+  __device__ void issue(const FactorPassArgs& a, const VecChain<T>& vc, int s, int q) {
     const int n = a.n, N = a.N;
     const size_t nn = (size_t)n * n;
     const int j = q << a.shift;
+    vf.issue(a, vc, q);
     const T* Li = reinterpret_cast<const T*>(a.Linv) + ((size_t)s * N + (j - 1)) * nn;
     const CT* cpl;
     if constexpr (FIRST)
@@ -128,18 +303,20 @@ struct FetchOdd {
   }
 };
 
-template <typename T, int NMAX, bool FIRST>
+template <typename T, int NMAX, bool FIRST, bool FWD>
 struct FetchEven {
   static constexpr int EL = Share<NMAX>::ELEMS;
   typedef typename std::conditional<FIRST, double, T>::type CT;
   double d[EL];
   T ar[EL], al[EL];
   CT cp[EL];
+  VecFetch<T, NMAX, FIRST, FWD> vf;
 
-  __device__ void issue(const FactorPassArgs& a, int s, int q) {
+  __device__ void issue(const FactorPassArgs& a, const VecChain<T>& vc, int s, int q) {
     const int n = a.n, N = a.N;
     const size_t nn = (size_t)n * n;
     const int j = q << a.shift;
+    vf.issue(a, vc, q);
     const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
     const T* accR = nullptr;
     const T* accL = nullptr;
@@ -289,10 +466,15 @@ __device__ __attribute__((always_inline)) inline void factor_diag(T* A, unsigned
 // One elimination (Section IV-B in block form): Aj := L_jj^{-1};
 // G_r = K[r,j] L^{-T} (into Cj), G_l = K[l,j] L^{-T} (into Cl, which holds K[j,l]);
 // A_r -= G_r G_r^T; A_l -= G_l G_l^T; K[r,l] = -G_r G_l^T (into Cl).
-template <typename T, int NMAX>
+// With a fused forward substitution (gy not null) the node's right-hand side Vj,
+// complete once every lower neighbour is eliminated, gives y_j = L_jj^{-1} Vj (into
+// Yt and gy), and the neighbours' right-hand sides take V_r -= G_r y_j and
+// V_l -= G_l y_j (Algorithm 2's forward step in the elimination order).
+template <typename T, int NMAX, bool FWD>
 __device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T* Al, T* Cl, T* Ar, int n, T* gLinv,
                                  T* gGl, T* gGr, unsigned long long perm_row0,
-                                 unsigned long long* info, bool have_inverse) {
+                                 unsigned long long* info, bool have_inverse, T* Vj,
+                                 T* Vl, T* Vr, T* Yt, T* Pr, T* Pl, T* gy, int nrhs) {
   typedef typename Mfma<T>::acc_t acc_t;
   if (!have_inverse) factor_diag<T, NMAX>(Aj, perm_row0, n, info);
   const bool left = Cl != nullptr;
@@ -302,6 +484,11 @@ __device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T*
   __syncthreads();
   mfma_tile_store<T, NMAX, false>(Cj, gr, T(1));
   if (left) mfma_tile_store<T, NMAX, false>(Cl, gl, T(1));
+  if constexpr (FWD)  // y_j = L_jj^{-1} V_j (Aj and Vj are not written in this phase)
+    block_matvec<T, NMAX>(Aj, Vj, nrhs, [&](int q, int o, T v) {
+      Yt[q * NMAX + o] = v;
+      if (o < n) gy[q * n + o] = v;
+    });
   __syncthreads();
   if (!have_inverse) slot_store_packed<T, NMAX>(gLinv, Aj, n);
   slot_store<T, NMAX>(gGr, Cj, n);
@@ -312,19 +499,30 @@ __device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T*
     ul = mfma_tile_nt<T, NMAX, false>(Cl, Cl);
     uf = mfma_tile_nt<T, NMAX, false>(Cj, Cl);
   }
+  if constexpr (FWD)  // G_l is still in Cl
+    push_products<T, NMAX>(Cj, left ? Cl : nullptr, Yt, Pr, Pl, nrhs);
   __syncthreads();
   mfma_tile_store<T, NMAX, true>(Ar, ur, T(-1));
   if (left) {
     mfma_tile_store<T, NMAX, true>(Al, ul, T(-1));
     mfma_tile_store<T, NMAX, false>(Cl, uf, T(-1));
   }
+  if constexpr (FWD) push_apply<T, NMAX>(Vr, left ? Vl : nullptr, Pr, Pl, nrhs);
   __syncthreads();
 }
 
-template <typename T, int NMAX, bool FIRST, bool FINAL>
-__global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPassArgs a) {
+// The last pass has one workgroup per chain; two per CU keep all of them resident, so
+// its register budget is held to that.
+template <bool FINAL>
+constexpr int pass_min_blocks() {
+  return FINAL ? 2 : 1;
+}
+
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+__global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
+    factor_pass_kernel(FactorPassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Slots<T, NMAX> sl{reinterpret_cast<T*>(smem_raw), a.Tw};
+  Slots<T, NMAX> sl{reinterpret_cast<T*>(smem_raw), a.Tw, FWD ? a.nrhs * NMAX : 0};
   const int n = a.n, N = a.N;
   const size_t nn = (size_t)n * n;
   const int s = blockIdx.x / a.windows;
@@ -346,6 +544,19 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
 
   BoundaryFetch<T, NMAX, FIRST> bf;
   if (has_left) bf.issue(a, s, lo);
+  BoundaryVec<T, NMAX, FIRST, FWD> bvf;
+  if (has_left) bvf.issue(a, s, lo);
+  T* ych = FWD ? reinterpret_cast<T*>(a.y) + (size_t)s * N * a.nrhs * n : nullptr;
+  VecChain<T> vc{};
+  if constexpr (FWD) {
+    vc.len = ((size_t)a.Ssys * N + 1) * n;
+    vc.b = a.b + (size_t)sys * a.nrhs * vc.len + (size_t)(s - sys * a.Ssys) * N * n;
+    if constexpr (!FIRST) {
+      const size_t vo = (size_t)s * a.stride * a.nrhs * n;
+      vc.vR = reinterpret_cast<const T*>(a.vaccR_in) + vo;
+      vc.vL = reinterpret_cast<const T*>(a.vaccL_in) + vo;
+    }
+  }
 
   // Prologue: the pass-local level-1 positions (odd q) see no update from inside the
   // window, so their diagonal blocks (D plus updates carried from earlier passes) are
@@ -438,15 +649,16 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
     }
     __threadfence_block();
   }
-  FetchOdd<T, NMAX, FIRST> fo;
-  FetchEven<T, NMAX, FIRST> fe;
-  if (lo + 1 <= hi) fo.issue(a, s, lo + 1);
-  if (lo + 2 <= hi) fe.issue(a, s, lo + 2);
+  FetchOdd<T, NMAX, FIRST, FWD> fo;
+  FetchEven<T, NMAX, FIRST, FWD> fe;
+  if (lo + 1 <= hi) fo.issue(a, vc, s, lo + 1);
+  if (lo + 2 <= hi) fe.issue(a, vc, s, lo + 2);
 
   // The left boundary node keeps the updates it received while it was a window
   // boundary in earlier passes; they travel with it in its left accumulator.
   if (has_left) bf.commit(sl.AL(), sl.CL());
   slot_zero<T, NMAX>(sl.AR());
+  bvf.commit(a, sl.VL(), sl.VR());
   __syncthreads();
 
   unsigned live = 0u;
@@ -464,40 +676,47 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
         // (its slot is free: the previous node of that level is already eliminated)
         // and then fetches the next pair, which the eliminations of step q+1 hide.
         fo.commit(sl.A(0), sl.Cp(0), n);
+        fo.vf.commit(a, sl.V(0));
         if (q + 1 <= hi) {
           const int v1 = __builtin_ctz((unsigned)(q + 1));
           fe.commit(sl.A(v1), sl.Cp(v1), n);
+          fe.vf.commit(a, sl.V(v1));
         }
         __syncthreads();
-        if (q + 2 <= hi) fo.issue(a, s, q + 2);
-        if (q + 3 <= hi) fe.issue(a, s, q + 3);
+        if (q + 2 <= hi) fo.issue(a, vc, s, q + 2);
+        if (q + 3 <= hi) fe.issue(a, vc, s, q + 3);
       }
       todo = live & ((1u << v) - 1u);
     } else {
       todo = live;
     }
     T* Ar = is_rb ? sl.AR() : sl.A(v);
+    T* Vr = is_rb ? sl.VR() : sl.V(v);
     while (todo) {
       const int t = __builtin_ctz(todo);
       todo &= todo - 1u;
       const unsigned above = live & ~((2u << t) - 1u);
       T* Al = nullptr;
       T* Cl = nullptr;
+      T* Vl = nullptr;
       if (above) {
         const int u = __builtin_ctz(above);
         Al = sl.A(u);
         Cl = sl.Cp(u);
+        Vl = sl.V(u);
       } else if (has_left) {
         Al = sl.AL();
         Cl = sl.CL();
+        Vl = sl.VL();
       }
       // position of the live node of level t
       const int pos = !is_rb ? q - (1 << t) : (rb_is_x ? ((hi >> t) << t) : rb - (1 << t));
       const int j = pos << a.shift;  // original chain position
       const unsigned long long prow = chain_row0 + (unsigned long long)a.permpos[j - 1] * n;
-      eliminate<T, NMAX>(sl.A(t), sl.Cp(t), Al, Cl, Ar, n, Linv + (size_t)(j - 1) * nn,
+      eliminate<T, NMAX, FWD>(sl.A(t), sl.Cp(t), Al, Cl, Ar, n, Linv + (size_t)(j - 1) * nn,
                          Gl + (size_t)(j - 1) * nn, Gr + (size_t)(j - 1) * nn, prow, a.info,
-                         (pos & 1) != 0);
+                         (pos & 1) != 0, sl.V(t), Vl, Vr, sl.Y(), sl.Pr(), sl.Pl(),
+                         ych ? ych + (size_t)(j - 1) * a.nrhs * n : nullptr, a.nrhs);
       live &= ~(1u << t);
     }
     if (!is_rb) live |= (1u << v);
@@ -514,6 +733,18 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
     } else {
       slot_store<T, NMAX>(reinterpret_cast<T*>(a.accX) + ((size_t)s * a.npass + a.pass) * nn,
                           sl.AR(), n);
+    }
+    if constexpr (FWD) {
+      const int nr = a.nrhs;
+      const size_t vs = (size_t)nr * n;
+      if (has_left)
+        vec_store<T, NMAX>(reinterpret_cast<T*>(a.vaccL_out) + (base + w) * vs, sl.VL(), n, nr);
+      if (!rb_is_x)
+        vec_store<T, NMAX>(reinterpret_cast<T*>(a.vaccR_out) + (base + w + 1) * vs, sl.VR(), n,
+                           nr);
+      else
+        vec_store<T, NMAX>(
+            reinterpret_cast<T*>(a.vaccX) + ((size_t)s * a.npass + a.pass) * vs, sl.VR(), n, nr);
     }
     return;
   } else {
@@ -557,6 +788,49 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT) factor_pass_kernel(FactorPa
       for (int k = 0; k < n; ++k)
         acc += static_cast<double>(Cx[r * LD + k]) * static_cast<double>(Cx[c * LD + k]);
       U[e] = acc;
+    }
+    if constexpr (FWD) {
+      // Fused forward substitution, X step (Algorithm 2, lines 3-5): the right-hand
+      // side of X is b at stage 0 plus the X updates of every pass (same order as its
+      // diagonal block); y_X = L_X^{-1} of it, and w_s = F_s y_X in FP64.
+      constexpr int NT = TileCfg<NMAX>::NT;
+      constexpr int TPR = NT / NMAX;
+      constexpr int CPT = NMAX / TPR;
+      const int nr = a.nrhs;
+      const int sys_ = s / a.Ssys, sc = s - sys_ * a.Ssys;
+      const size_t len = ((size_t)a.Ssys * N + 1) * n;
+      const size_t offx = (size_t)sys_ * nr * len + (size_t)sc * N * n;
+      const size_t vs = (size_t)nr * n;
+      T* Vx = sl.Y();
+      for (int idx = threadIdx.x; idx < nr * NMAX; idx += NT) {
+        const int q = idx / NMAX, i = idx % NMAX;
+        T v = T(0);
+        if (i < n) {
+          v = static_cast<T>(a.b[offx + (size_t)q * len + i]);
+          for (int p = 0; p < a.pass; ++p)
+            v += reinterpret_cast<const T*>(a.vaccX)[((size_t)s * a.npass + p) * vs + q * n + i];
+          v += sl.VR()[idx];
+        }
+        Vx[idx] = v;
+      }
+      __syncthreads();
+      T* yx = reinterpret_cast<T*>(a.y) + ((size_t)s * N + (N - 1)) * vs;
+      T* Yx = sl.VR();  // the X updates are folded into Vx; VR now holds y_X
+      block_matvec<T, NMAX>(Ax, Vx, nr, [&](int q, int o, T v) {
+        Yx[q * NMAX + o] = v;
+        if (o < n) yx[q * n + o] = v;
+      });
+      __syncthreads();
+      const int o = threadIdx.x / TPR, p = threadIdx.x % TPR;
+      for (int q = 0; q < nr; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u)
+          acc += static_cast<double>(Cx[o * LD + p * CPT + u]) *
+                 static_cast<double>(Yx[q * NMAX + p * CPT + u]);
+        acc = lane_group_sum_dpp<TPR>(acc);
+        if (p == 0 && o < n) a.w[((size_t)s * nr + q) * n + o] = acc;
+      }
     }
   }
 }
@@ -625,24 +899,36 @@ __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restri
   if (r < n && c < n) LR[r * n + c] = A[r * LD + c];
 }
 
+// Block slots, plus (fused forward substitution) Tw + 5 right-hand-side slots.
 template <typename T, int NMAX>
-size_t pass_lds_bytes(int Tw) {
-  return (size_t)(2 * Tw + 3) * Lay<NMAX>::SZ * sizeof(T);
+size_t pass_lds_bytes(int Tw, int nrhs_fused) {
+  return ((size_t)(2 * Tw + 3) * Lay<NMAX>::SZ + (size_t)(Tw + 5) * nrhs_fused * NMAX) *
+         sizeof(T);
 }
 
-template <typename T, int NMAX, bool FIRST, bool FINAL>
-void launch_pass_k(const FactorPassArgs& a, hipStream_t st) {
-  const size_t lds = pass_lds_bytes<T, NMAX>(a.Tw);
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+void launch_pass_kf(const FactorPassArgs& a, hipStream_t st) {
+  const size_t lds = pass_lds_bytes<T, NMAX>(a.Tw, FWD ? a.nrhs : 0);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&factor_pass_kernel<T, NMAX, FIRST, FINAL>),
+        reinterpret_cast<const void*>(&factor_pass_kernel<T, NMAX, FIRST, FINAL, FWD>),
         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   const unsigned grid = (unsigned)a.S * (unsigned)a.windows;
-  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX, FIRST, FINAL>), dim3(grid),
+  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX, FIRST, FINAL, FWD>), dim3(grid),
                      dim3(TileCfg<NMAX>::NT), lds, st, a);
+}
+
+// The fused forward substitution is its own kernel symbol, so the plain factorization
+// carries none of its registers or code.
+template <typename T, int NMAX, bool FIRST, bool FINAL>
+void launch_pass_k(const FactorPassArgs& a, hipStream_t st) {
+  if (a.b)
+    launch_pass_kf<T, NMAX, FIRST, FINAL, true>(a, st);
+  else
+    launch_pass_kf<T, NMAX, FIRST, FINAL, false>(a, st);
 }
 
 template <typename T, int NMAX>
@@ -660,15 +946,15 @@ void launch_pass_t(const FactorPassArgs& a, hipStream_t st) {
 
 }  // namespace
 
-size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw) {
+size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw, int nrhs_fused) {
   if (fp64) {
-    if (nmax <= 8) return pass_lds_bytes<double, 8>(Tw);
-    if (nmax <= 16) return pass_lds_bytes<double, 16>(Tw);
-    return pass_lds_bytes<double, 32>(Tw);
+    if (nmax <= 8) return pass_lds_bytes<double, 8>(Tw, nrhs_fused);
+    if (nmax <= 16) return pass_lds_bytes<double, 16>(Tw, nrhs_fused);
+    return pass_lds_bytes<double, 32>(Tw, nrhs_fused);
   }
-  if (nmax <= 8) return pass_lds_bytes<float, 8>(Tw);
-  if (nmax <= 16) return pass_lds_bytes<float, 16>(Tw);
-  return pass_lds_bytes<float, 32>(Tw);
+  if (nmax <= 8) return pass_lds_bytes<float, 8>(Tw, nrhs_fused);
+  if (nmax <= 16) return pass_lds_bytes<float, 16>(Tw, nrhs_fused);
+  return pass_lds_bytes<float, 32>(Tw, nrhs_fused);
 }
 
 template <typename T>
