@@ -417,6 +417,12 @@ def main():
     dom_name, dom_t = dom
     cls = names.index(dom_name)
     bytes_call, flops_call, launches_call = p32.kernel_cost(cls)
+    if not args.separate and dom_name == "factor_first_pass":
+        # with the forward substitution inside, the first pass also reads b (FP64) and
+        # writes y (FP32) for every position it eliminates (all but the multiples of 2^Tw)
+        tw = p32.cost().window_depth
+        elim = S * ((N - 1) - (N - 1) // (1 << tw))
+        bytes_call += elim * n * nrhs * (8 + 4)
     launches = dom_t["launches_per_step"]
     roofline = None
     if bytes_call > 0 and dom_t["ms_per_step"] > 0:
