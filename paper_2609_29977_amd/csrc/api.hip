@@ -508,7 +508,7 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
   const size_t segs = (size_t)B * nrhs;  // (system, right-hand side) vectors
   const int npass = (int)p->costs.passes.size();
   p->stride = (npass > 1 ? p->costs.passes[0].windows : 1) + 1;
-  const size_t gblocks = (size_t)(N > 1 ? N - 1 : 1);
+  const size_t gblocks = g_chain_blocks(N);
   bool ok = dalloc(p, &p->Linv, S * N * nn * tb) &&
             dalloc(p, &p->Gl, S * gblocks * nn * tb) &&
             dalloc(p, &p->Gr, S * gblocks * nn * tb) &&
@@ -783,7 +783,7 @@ bmpc_status bmpc_export_tail_factor(bmpc_plan p, int32_t s, double* L, double* F
   if (!p->factored) return BMPC_ERR_STATE;
   const int N = p->d.N, n = p->d.n, m = p->m;
   const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
-  const size_t gblocks = (size_t)(N > 1 ? N - 1 : 1);
+  const size_t gblocks = (size_t)(N > 1 ? N - 1 : 1);  // blocks copied per chain
   std::vector<unsigned char> li(N * nn * tb), gl(gblocks * nn * tb), gr(gblocks * nn * tb),
       f(nn * tb);
   if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
@@ -792,8 +792,8 @@ bmpc_status bmpc_export_tail_factor(bmpc_plan p, int32_t s, double* L, double* F
            hipSuccess;
   };
   if (!cp(li.data(), p->Linv, (size_t)s * N * nn * tb, li.size()) ||
-      !cp(gl.data(), p->Gl, (size_t)s * gblocks * nn * tb, gl.size()) ||
-      !cp(gr.data(), p->Gr, (size_t)s * gblocks * nn * tb, gr.size()) ||
+      !cp(gl.data(), p->Gl, (size_t)s * g_chain_blocks(N) * nn * tb, gl.size()) ||
+      !cp(gr.data(), p->Gr, (size_t)s * g_chain_blocks(N) * nn * tb, gr.size()) ||
       !cp(f.data(), p->F, (size_t)s * nn * tb, f.size()))
     return BMPC_ERR_DEVICE;
   auto val = [&](const std::vector<unsigned char>& buf, size_t idx) -> double {

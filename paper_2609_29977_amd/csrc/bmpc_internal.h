@@ -28,6 +28,12 @@ namespace bmpc {
 constexpr int kFactorThreads = 256;
 constexpr int kSolveThreads = 64;
 constexpr int kMaxRhs = 8;
+
+// Blocks per chain in the G_l and G_r arrays: the N-1 blocks of the positions 1..N-1,
+// padded to N so that every factor array (L^{-1} has N) shares one chain stride; the
+// solve streams read the three arrays at the same offsets, which HBM serves faster than
+// offsets that drift apart by one block per chain.
+inline __host__ __device__ size_t g_chain_blocks(int N) { return (size_t)N; }
 constexpr int kMaxWindowDepth = 6;
 
 // Kernel classes for per-kernel event timing.

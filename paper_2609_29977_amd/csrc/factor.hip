@@ -534,8 +534,8 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
   const bool rb_is_x = rb > a.mk;
 
   T* Linv = reinterpret_cast<T*>(a.Linv) + (size_t)s * N * nn;
-  T* Gl = reinterpret_cast<T*>(a.Gl) + (size_t)s * (N > 1 ? N - 1 : 1) * nn;
-  T* Gr = reinterpret_cast<T*>(a.Gr) + (size_t)s * (N > 1 ? N - 1 : 1) * nn;
+  T* Gl = reinterpret_cast<T*>(a.Gl) + (size_t)s * g_chain_blocks(N) * nn;
+  T* Gr = reinterpret_cast<T*>(a.Gr) + (size_t)s * g_chain_blocks(N) * nn;
   // natural row of the chain's first entry: systems in order, tails before the root
   const int sys = s / a.Ssys;
   const unsigned long long chain_row0 =

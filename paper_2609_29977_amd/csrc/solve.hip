@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
   const int s = blockIdx.x / count;
   const int i = blockIdx.x - s * count;
   const int j = (2 * i + 1) << (level - 1);
-  const size_t gstride = (size_t)(N > 1 ? N - 1 : 1);
+  const size_t gstride = g_chain_blocks(N);
   const T* Gl = reinterpret_cast<const T*>(a.Gl) + (size_t)s * gstride * nn;
   const T* Gr = reinterpret_cast<const T*>(a.Gr) + (size_t)s * gstride * nn;
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_kernel(So
   const int i = blockIdx.x, sl = blockIdx.y, sys = blockIdx.z;
   const size_t s = (size_t)sys * a.S + sl;
   const int j = (2 * i + 1) << (level - 1);
-  const size_t gstride = (size_t)(N > 1 ? N - 1 : 1);
+  const size_t gstride = g_chain_blocks(N);
   const T* Gl = reinterpret_cast<const T*>(a.Gl) + s * gstride * nn;
   const T* Gr = reinterpret_cast<const T*>(a.Gr) + s * gstride * nn;
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + s * N * nn;
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   const int n = a.n, N = a.N, nrhs = a.nrhs, m = a.m;
   const size_t nn = (size_t)n * n;
   const int s = blockIdx.x;
-  const size_t gstride = (size_t)(N > 1 ? N - 1 : 1);
+  const size_t gstride = g_chain_blocks(N);
   const T* Gr = reinterpret_cast<const T*>(a.Gr) + (size_t)s * gstride * nn;
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
