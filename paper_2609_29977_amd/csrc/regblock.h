@@ -190,4 +190,35 @@ __device__ inline T lane_group_sum_dpp(T p) {
   return p;
 }
 
+// Value of lane ^ OFF for OFF in {8, 16, 32}: DPP row rotation by 8 within a row of 16,
+// ds_swizzle with xor 16 within 32 lanes, a shuffle across the halves of the wave.
+template <int OFF>
+__device__ inline float xor_lane(float v) {
+  static_assert(OFF == 8 || OFF == 16 || OFF == 32, "lane distance");
+  if constexpr (OFF == 8)
+    return dpp_perm<0x128>(v);  // row_ror:8
+  else if constexpr (OFF == 16)
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+  else
+    return __shfl_xor(v, 32);
+}
+template <int OFF>
+__device__ inline double xor_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const float lo = xor_lane<OFF>(__int_as_float((int)(b & 0xffffffffll)));
+  const float hi = xor_lane<OFF>(__int_as_float((int)(b >> 32)));
+  return __longlong_as_double(((long long)__float_as_int(hi) << 32) |
+                              (unsigned)__float_as_int(lo));
+}
+// Sum over the lanes that agree in lane % QPR (QPR = 8 or 16: a column group whose rows
+// are spread over the wave); every lane of a group gets the same sum.
+template <int QPR, typename T>
+__device__ inline T column_group_sum(T p) {
+  static_assert(QPR == 8 || QPR == 16, "lanes per row");
+  if constexpr (QPR == 8) p += xor_lane<8>(p);
+  p += xor_lane<16>(p);
+  p += xor_lane<32>(p);
+  return p;
+}
+
 }  // namespace bmpc

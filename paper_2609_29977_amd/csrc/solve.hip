@@ -581,6 +581,130 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_kernel(So
   }
 }
 
+// Backward level kernel for one right-hand side and n = 32 that reads every block by
+// rows: lane l holds the 16-byte piece (VEC elements) at columns VEC*q of rows
+// mrow + RPI*k (q = l % QPR, mrow = l / QPR, k < K), so one load instruction covers RPI
+// whole rows of a block, as in the forward sweep, instead of reading columns with
+// dword loads.  The transposed products G^T x and L_jj^{-T} r sum over rows, i.e. over
+// the lanes that share q (column_group_sum); the residual r, produced by columns, is
+// re-indexed by rows through LDS.  Position j's own G_l slot is read even without a
+// left neighbour (it is then never written and not used), so that no load waits on a
+// branch.  Same result as solve_level_one_kernel<T, 32, false> up to summation order.
+template <typename T>
+__global__ void __launch_bounds__(64) solve_bwd_rows_kernel(SolveArgs a, int level) {
+  if (a.done && *a.done) return;
+  constexpr int NMAX = 32;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int QPR = NMAX / VEC;
+  constexpr int RPI = 64 / QPR;
+  constexpr int K = NMAX / RPI;
+  constexpr int n = NMAX;
+  constexpr size_t nn = (size_t)NMAX * NMAX;
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  __shared__ T xs[3][NMAX];  // x of the left and right neighbours, y_j; then r by rows
+  const int lane = threadIdx.x, q = lane % QPR, mrow = lane / QPR;
+  const int N = a.N, m = a.m;
+  const int i = blockIdx.x, sl = blockIdx.y, sys = blockIdx.z;
+  const size_t s = (size_t)sys * a.S + sl;
+  const int j = (2 * i + 1) << (level - 1);
+  const int half = 1 << (level - 1);
+  const size_t gstride = g_chain_blocks(N);
+  const T* Glb = reinterpret_cast<const T*>(a.Gl) + (s * gstride + (j - 1)) * nn;
+  const T* Grb = reinterpret_cast<const T*>(a.Gr) + (s * gstride + (j - 1)) * nn;
+  const T* Lb = reinterpret_cast<const T*>(a.Linv) + (s * N + (j - 1)) * nn;
+  T* y = reinterpret_cast<T*>(a.y) + s * N * n;
+  T* yj = y + (size_t)(j - 1) * n;
+  const bool has_left = j - half >= 1;
+  const int ir = j + half <= m ? j + half - 1 : N - 1;
+  const size_t len = ((size_t)a.S * N + 1) * n;
+  const size_t off = (size_t)sys * len + ((size_t)sl * N + (N - j)) * n;
+  vt gl[K], gr[K];
+  T li[K][VEC];
+  const auto rsL = block_rsrc(Lb, (unsigned)(NMAX * (NMAX + 1) / 2) * sizeof(T));
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int R = mrow + RPI * k;
+    gr[k] = *reinterpret_cast<const vt*>(Grb + R * NMAX + VEC * q);
+    gl[k] = *reinterpret_cast<const vt*>(Glb + R * NMAX + VEC * q);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const unsigned o = (unsigned)(R * (R + 1) / 2 + VEC * q + e) * sizeof(T);
+      if constexpr (sizeof(T) == 8)
+        li[k][e] = buf_load_f64(rsL, o);
+      else
+        li[k][e] = buf_load_f32(rsL, o);
+    }
+  }
+  const int vl = lane & (NMAX - 1);
+  const T v0 = y[(size_t)(has_left ? j - half - 1 : j - 1) * n + vl];
+  const T v1 = y[(size_t)ir * n + vl];
+  const T v2 = yj[vl];
+  double xo[VEC];
+  if (a.accumulate) {  // wave-uniform; the x being updated, at the output lanes' columns
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) xo[e] = a.x[off + VEC * q + e];
+  }
+  if (lane < NMAX) {
+    xs[0][lane] = has_left ? v0 : T(0);
+    xs[1][lane] = v1;
+    xs[2][lane] = v2;
+  }
+  wave_lds_fence();
+  // r = y_j - G_l^T x_l - G_r^T x_r, by columns c = VEC*q + e
+  T p[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) p[e] = T(0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int R = mrow + RPI * k;
+    const T al = xs[0][R], ar = xs[1][R];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      if (has_left) p[e] += gl[k][e] * al;
+      p[e] += gr[k][e] * ar;
+    }
+  }
+  T r[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) r[e] = xs[2][VEC * q + e] - column_group_sum<QPR>(p[e]);
+  wave_lds_fence();
+  if (mrow == 0) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) xs[0][VEC * q + e] = r[e];
+  }
+  wave_lds_fence();
+  // x_j = L_jj^{-T} r: sum over rows R >= c of L^{-1}[R][c] r[R]
+  T x[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) x[e] = T(0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int R = mrow + RPI * k;
+    const T rr = xs[0][R];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      if (VEC * q + e <= R) x[e] += li[k][e] * rr;
+  }
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) x[e] = column_group_sum<QPR>(x[e]);
+  if (mrow == 0) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int c = VEC * q + e;
+      yj[c] = x[e];
+      const size_t idx = off + c;
+      const double d = static_cast<double>(x[e]);
+      if (a.accumulate) {
+        const double dd = a.rnorm[sys] * d;
+        a.x[idx] = xo[e] + dd;
+        a.dstore[idx] = dd;
+      } else {
+        a.x[idx] = d;
+      }
+    }
+  }
+}
+
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   if (a.done && *a.done) return;
@@ -801,7 +925,10 @@ void bwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
   const int count = level_count(a.m, level);
   if (count <= 0) return;
   const size_t sh = level_smem_bytes<T, NMAX>(1, a.nrhs);
-  if (one_rhs_full<NMAX>(a))
+  if (NMAX == 32 && one_rhs_full<NMAX>(a))
+    hipLaunchKernelGGL((solve_bwd_rows_kernel<T>), dim3(count, a.S, a.B), dim3(64), 0, st, a,
+                       level);
+  else if (one_rhs_full<NMAX>(a))
     hipLaunchKernelGGL((solve_level_one_kernel<T, NMAX, false>), dim3(count, a.S, a.B), dim3(64),
                        sh, st, a, level);
   else if (a.n == NMAX)
