@@ -298,6 +298,48 @@ def bench_gradients(args):
     print(json.dumps(out))
 
 
+FP64_CLASSES = ("root_reduce", "root_potrf", "solve_root", "residual", "residual_root",
+                "refine_misc")
+
+
+def device_copy_rate(torch, mib=1024, reps=10):
+    """Read + write GB/s of a plain 1 GiB device copy: the practical streaming ceiling."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * (mib << 20) / sec / 1e9
+
+
+def kernel_rooflines(plan, times, names, fp32, first_pass_extra, copy_gbs):
+    """Algorithmic GB/s and TFLOP/s of each kernel class over its measured time per step,
+    as fractions of the HBM peak, of the copy rate and of the arithmetic peak."""
+    out = {}
+    for name, t in times.items():
+        bytes_call, flops_call, launches_call = plan.kernel_cost(names.index(name))
+        if name == "factor_first_pass":
+            bytes_call += first_pass_extra
+        sec = t["ms_per_step"] * 1e-3
+        if sec <= 0 or (bytes_call <= 0 and flops_call <= 0):
+            continue
+        calls = t["launches_per_step"] / max(1, launches_call)
+        gbs = bytes_call * calls / sec / 1e9
+        tfs = flops_call * calls / sec / 1e12
+        peak = FP32_MFMA_PEAK_TFS if fp32 and name not in FP64_CLASSES else FP64_PEAK_TFS
+        out[name] = {"ms_per_step": round(t["ms_per_step"], 4), "gb_s": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "copy_frac": round(gbs / copy_gbs, 4),
+                     "tflop_s": round(tfs, 3), "flop_frac": round(tfs / peak, 4)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -412,17 +454,32 @@ def main():
                    for k, v in times.items() if v[0] > 0}
     torch.cuda.synchronize()
 
+    # Every kernel class against the HBM peak, the measured copy rate and the peak of
+    # the arithmetic it computes in (FP32 for the factor and sweeps of the FP32 path;
+    # the residual and the root steps are FP64 in both paths).
+    copy_gbs = device_copy_rate(torch)
+
+    def fused_extra(plan, ybytes):
+        # with the forward substitution inside, the first pass also reads b (FP64) and
+        # writes y for every position it eliminates (all but the multiples of 2^Tw)
+        if args.separate:
+            return 0.0
+        tw = plan.cost().window_depth
+        return S * ((N - 1) - (N - 1) // (1 << tw)) * n * nrhs * (8 + ybytes)
+
+    extra32 = fused_extra(p32, 4)
+    per_kernel = {"fp32_ir": kernel_rooflines(p32, kt["fp32_ir"], names, True, extra32,
+                                              copy_gbs),
+                  "fp64": kernel_rooflines(p64, kt["fp64"], names, False,
+                                           fused_extra(p64, 8), copy_gbs)}
+
     # Dominant kernel of the headline path and its roofline.
     dom = max(kt["fp32_ir"].items(), key=lambda kv: kv[1]["ms_per_step"])
     dom_name, dom_t = dom
     cls = names.index(dom_name)
     bytes_call, flops_call, launches_call = p32.kernel_cost(cls)
-    if not args.separate and dom_name == "factor_first_pass":
-        # with the forward substitution inside, the first pass also reads b (FP64) and
-        # writes y (FP32) for every position it eliminates (all but the multiples of 2^Tw)
-        tw = p32.cost().window_depth
-        elim = S * ((N - 1) - (N - 1) // (1 << tw))
-        bytes_call += elim * n * nrhs * (8 + 4)
+    if dom_name == "factor_first_pass":
+        bytes_call += extra32
     launches = dom_t["launches_per_step"]
     roofline = None
     if bytes_call > 0 and dom_t["ms_per_step"] > 0:
@@ -505,6 +562,8 @@ def main():
         "method_flops_per_step": flops,
         "analyze_ms": round(analyze_ms, 2),
         "roofline": roofline,
+        "copy_gb_s": round(copy_gbs, 1),
+        "kernels_roofline": per_kernel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

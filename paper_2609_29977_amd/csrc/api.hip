@@ -146,6 +146,10 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B) {
   c.pass_bytes[KC_SOLVE_ROOT] = 8.0 * ((double)S * n * q + 2.0 * n * q + tri);
   c.pass_bytes[KC_RESIDUAL] = K_bytes - 8.0 * tri + 3.0 * 8.0 * (double)S * N * n * q;
   c.pass_bytes[KC_RESIDUAL_ROOT] = 8.0 * (tri + (double)S * n * q + 3.0 * n * q);
+  // r = b - K x: one multiply-add per stored block entry and side it acts on (D
+  // symmetric, E and C each acting as themselves and transposed)
+  c.pass_flops[KC_RESIDUAL] = q * 2.0 * (double)S * (N * nn + 2.0 * m * nn + nn);
+  c.pass_flops[KC_RESIDUAL_ROOT] = q * 2.0 * ((double)S * nn + nn);
   const int L = chain_levels(m);
   for (int k = 0; k < KC_COUNT; ++k) c.launches[k] = 1;
   c.launches[KC_SOLVE_FWD] = L;
