@@ -141,9 +141,13 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   const bool rowl = lane < NMAX;
   const int j = lane - NMAX;
   const int idx = rowl ? lane : (j < NMAX ? j : NMAX - 1);
+  // Every lane reads a row (column lanes a row they then discard): loads under a lane
+  // condition become a branch per element, each waiting for its own read.
   T v[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) v[c] = rowl ? A[idx * LD + c] : ((c == idx) ? T(1) : T(0));
+  for (int c = 0; c < NMAX; ++c) v[c] = A[idx * LD + c];
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) v[c] = rowl ? v[c] : ((c == idx) ? T(1) : T(0));
   int fail = -1;
   T dinv[NMAX];
 #pragma unroll
