@@ -304,6 +304,83 @@ def bench_gradients(args):
     print(json.dumps(out))
 
 
+def bench_paper_grid(args):
+    """The paper's own workload shape (Section V): n = 16, FP64, one right-hand side, M
+    scenarios x N stages on the two lines of its grid that it quotes times for (N = 30
+    with M = 20..200, and M = 100 with N = 40..160).  Factor and solve are timed
+    separately, each as the median of 50 calls after 10 warm-ups, each call replayed from
+    a HIP graph (the paper captures its factor and solve pipelines as graphs).  Seeded
+    synthetic systems (delta = 1e-2) stand in for the quadrotor systems."""
+    import numpy as np
+    import torch
+
+    from paper_2609_29977_amd import bmpc
+    from synth.branch_system import make_system
+
+    n, warm, runs = 16, 10, 50
+    grid = [(M, 30) for M in range(20, 201, 20)] + [(100, N) for N in range(40, 161, 20)]
+    dev = torch.device("cuda:0")
+    points, worst = [], 0.0
+    for M, N in grid:
+        s = make_system(M, N, n, 1, 1e-2, args.seed)
+        D, E, C, R, b = (torch.from_numpy(a).to(dev) for a in (s.D, s.E, s.C, s.R, s.b))
+        x = torch.empty_like(b)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        p = bmpc.Plan(M, N, n, 1, "fp64", stream=side)
+        with torch.cuda.stream(side):
+            p.factor(D, E, C, R)
+            p.solve(b, x)
+        torch.cuda.synchronize()
+        gf, gs = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gf, stream=side):
+            p.factor(D, E, C, R)
+        with torch.cuda.graph(gs, stream=side):
+            p.solve(b, x)
+        torch.cuda.synchronize()
+
+        def med(g):
+            for _ in range(warm):
+                g.replay()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(runs)]
+            for e0, e1 in ev:
+                e0.record()
+                g.replay()
+                e1.record()
+            torch.cuda.synchronize()
+            return statistics.median(e0.elapsed_time(e1) for e0, e1 in ev)
+
+        tf, ts = med(gf), med(gs)
+        gf.replay()
+        gs.replay()
+        torch.cuda.synchronize()
+        if p.info() != 0:
+            raise RuntimeError(f"factorization failed at M={M} N={N}")
+        if not args.no_cpu:
+            from oracle import oracle
+            ref, _ = oracle.solve(s.D, s.E, s.C, s.R, s.b, nthreads=16)
+            worst = max(worst, float(np.max(np.abs(x.cpu().numpy() - ref)) /
+                                     np.max(np.abs(ref))))
+        cost = p.cost()
+        points.append({"M": M, "N": N, "factor_ms": round(tf, 4), "solve_ms": round(ts, 4),
+                       "factor_gflops": round(cost.factor_flops / (tf * 1e-3) / 1e9, 1)})
+        log(f"M={M} N={N}: factor {tf:.4f} ms, solve {ts:.4f} ms")
+        p.close()
+        del gf, gs
+    top = next(q for q in points if q["M"] == 100 and q["N"] == 160)
+    out = {"metric": "FP64 factor and solve times on the paper's workload grid (n=16)",
+           "value": top["factor_ms"], "unit": "ms", "n_gpus": 1, "steps": runs,
+           "warmup": warm, "ms_per_step": round(top["factor_ms"] + top["solve_ms"], 4),
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "paper grid: n=16, N=30 with M=20..200, M=100 with "
+                                  "N=40..160; value = factor ms at M=100 N=160",
+                      "n": n, "nrhs": 1, "delta": 1e-2, "graph": True},
+           "points": points,
+           "max_rel_err_vs_oracle": None if args.no_cpu else worst}
+    print(json.dumps(out))
+
+
 FP64_CLASSES = ("root_reduce", "root_potrf", "solve_root", "residual", "residual_root",
                 "refine_misc")
 
@@ -377,6 +454,8 @@ def main():
         return bench_hetero(args)
     if args.config == "qp":
         return bench_qp(args)
+    if args.config == "paper":
+        return bench_paper_grid(args)
 
     S, N, n, nrhs, delta = CONFIGS[args.config]
     t0 = time.perf_counter()
