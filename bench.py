@@ -327,7 +327,7 @@ def bench_paper_grid(args):
         x = torch.empty_like(b)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
-        p = bmpc.Plan(M, N, n, 1, "fp64", stream=side)
+        p = bmpc.Plan(M, N, n, 1, "fp64", args.window_depth, stream=side)
         with torch.cuda.stream(side):
             p.factor(D, E, C, R)
             p.solve(b, x)

@@ -109,8 +109,10 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
   for (int k = 0; k < NMAX; ++k) {
     const T piv = wave_bcast(a[k], k);
     if (fail < 0 && !(piv > T(0))) fail = k;
-    const T d = sqrt(piv);
-    const T lik = (lane == k) ? d : a[k] / d;
+    // L[k][k] = piv * piv^{-1/2} and L[i][k] = a[i][k] * piv^{-1/2}: one refined
+    // reciprocal square root instead of a square root and a division per column
+    const T inv = rsqrt_refined(piv);
+    const T lik = (lane == k) ? piv * inv : a[k] * inv;
     a[k] = lik;
 #pragma unroll
     for (int c = k + 1; c < NMAX; ++c) a[c] -= lik * wave_bcast(lik, c);

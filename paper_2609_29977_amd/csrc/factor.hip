@@ -840,63 +840,79 @@ __global__ void factor_init_kernel(unsigned long long* info) {
 }
 
 // part[sys][g][e] = sum of U[s][e] over the scenarios of group g of system sys, in
-// scenario order (one workgroup per (system, group)).
-__global__ void __launch_bounds__(256) root_reduce_kernel(const double* __restrict__ U,
-                                                          double* part, int S, int nn,
-                                                          int groups) {
+// scenario order (one workgroup per (system, group), one thread per element).  The
+// loads of a group are issued together (clamped to the group's last scenario) and
+// added in order afterwards.
+__global__ void __launch_bounds__(1024) root_reduce_kernel(const double* __restrict__ U,
+                                                           double* part, int S, int nn,
+                                                           int groups) {
   const int sys = blockIdx.x / groups;
   const int g = blockIdx.x - sys * groups;
   const int per = (S + groups - 1) / groups;
   const int s0 = g * per, s1 = min(S, s0 + per);
   const double* Us = U + (size_t)sys * S * nn;
-  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-    double acc = 0.0;
-    for (int s = s0; s < s1; ++s) acc += Us[(size_t)s * nn + e];
-    part[((size_t)sys * groups + g) * nn + e] = acc;
+  const int e = threadIdx.x;
+  if (e >= nn || s0 >= s1) {
+    if (e < nn) part[((size_t)sys * groups + g) * nn + e] = 0.0;
+    return;
   }
+  constexpr int B = 16;
+  double acc = 0.0;
+  for (int s = s0; s < s1; s += B) {
+    double t[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) t[u] = Us[(size_t)min(s + u, s1 - 1) * nn + e];
+#pragma unroll
+    for (int u = 0; u < B; ++u) acc = (s + u < s1) ? acc + t[u] : acc;
+  }
+  part[((size_t)sys * groups + g) * nn + e] = acc;
 }
 
 // R~ = R - sum_g part[g] (group order), L_R = chol(R~) in FP64 (Algorithm 1, 7-8).
-// 1024 threads: thread e owns element e and loads all group partials at once.
+// 1024 threads: thread e owns element e of the NMAX x NMAX block (identity padded
+// beyond n) and loads all group partials at once.
+template <int NMAX>
 __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restrict__ R,
                                                           const double* __restrict__ part,
                                                           int groups, int n, double* LR,
                                                           unsigned long long sys_rows,
                                                           unsigned long long root_row,
                                                           unsigned long long* info) {
-  __shared__ double A[32 * 33];
+  constexpr int LD = NMAX + 1;
+  __shared__ double A[NMAX * LD];
   // one workgroup per system of the batch
   const int sys = blockIdx.x;
   R += (size_t)sys * n * n;
   part += (size_t)sys * groups * n * n;
   LR += (size_t)sys * n * n;
   const unsigned long long row_base = sys * sys_rows + root_row;
-  constexpr int LD = 33;
   const int e = threadIdx.x;
-  const int r = e / 32, c = e % 32;
-  double v = (r == c) ? 1.0 : 0.0;  // identity padding
-  if (r < n && c < n) {
-    constexpr int B = 16;
-    double acc = 0.0;
-    for (int g0 = 0; g0 < groups; g0 += B) {
-      double t[B];
+  const int r = e / NMAX, c = e % NMAX;
+  if (e < NMAX * NMAX) {
+    double v = (r == c) ? 1.0 : 0.0;  // identity padding
+    if (r < n && c < n) {
+      constexpr int B = 32;
+      double acc = 0.0;
+      for (int g0 = 0; g0 < groups; g0 += B) {
+        double t[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u)
-        t[u] = (g0 + u < groups) ? part[(size_t)(g0 + u) * n * n + r * n + c] : 0.0;
+        for (int u = 0; u < B; ++u)
+          t[u] = part[(size_t)min(g0 + u, groups - 1) * n * n + r * n + c];
 #pragma unroll
-      for (int u = 0; u < B; ++u) acc += t[u];
+        for (int u = 0; u < B; ++u) acc = (g0 + u < groups) ? acc + t[u] : acc;
+      }
+      const double rv = (r >= c) ? R[r * n + c] : R[c * n + r];
+      v = rv - acc;
     }
-    const double rv = (r >= c) ? R[r * n + c] : R[c * n + r];
-    v = rv - acc;
+    A[r * LD + c] = v;
   }
-  A[r * LD + c] = v;
   __syncthreads();
   if (threadIdx.x < 64) {
-    const int fail = wave_potrf<double, 32>(A);
+    const int fail = wave_potrf<double, NMAX>(A);
     if (fail >= 0 && fail < n && threadIdx.x == 0) atomicMin(info, row_base + fail + 1);
   }
   __syncthreads();
-  if (r < n && c < n) LR[r * n + c] = A[r * LD + c];
+  if (e < NMAX * NMAX && r < n && c < n) LR[r * n + c] = A[r * LD + c];
 }
 
 // Block slots, plus (fused forward substitution) Tw + 5 right-hand-side slots.
@@ -975,15 +991,19 @@ void launch_factor_init(unsigned long long* info, hipStream_t st) {
 
 void launch_root_reduce(const double* U, double* part, int B, int S, int n, int groups,
                         hipStream_t st) {
-  hipLaunchKernelGGL(root_reduce_kernel, dim3(B * groups), dim3(256), 0, st, U, part, S, n * n,
+  hipLaunchKernelGGL(root_reduce_kernel, dim3(B * groups), dim3(1024), 0, st, U, part, S, n * n,
                      groups);
 }
 
 void launch_root_potrf(const double* R, const double* part, int B, int groups, int n,
                        double* LR, int64_t sys_rows, int64_t root_row,
                        unsigned long long* info, hipStream_t st) {
-  hipLaunchKernelGGL(root_potrf_kernel, dim3(B), dim3(1024), 0, st, R, part, groups, n, LR,
-                     (unsigned long long)sys_rows, (unsigned long long)root_row, info);
+  if (n <= 16)
+    hipLaunchKernelGGL(root_potrf_kernel<16>, dim3(B), dim3(1024), 0, st, R, part, groups, n,
+                       LR, (unsigned long long)sys_rows, (unsigned long long)root_row, info);
+  else
+    hipLaunchKernelGGL(root_potrf_kernel<32>, dim3(B), dim3(1024), 0, st, R, part, groups, n,
+                       LR, (unsigned long long)sys_rows, (unsigned long long)root_row, info);
 }
 
 }  // namespace bmpc

@@ -783,7 +783,8 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
   const int t = threadIdx.x, i = t & 31, g = t >> 5;
   {
     const int r = t / 32, c = t % 32;
-    L[r * 33 + c] = (r < n && c < n) ? a.LR[(size_t)sys * n * n + r * n + c] : 0.0;
+    L[r * 33 + c] = (r < n && c < n) ? a.LR[(size_t)sys * n * n + r * n + c]
+                                     : (r == c ? 1.0 : 0.0);  // identity padding
   }
   for (int q = 0; q < nrhs; ++q) {
     double acc = 0.0;
@@ -814,19 +815,29 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
     }
     __syncthreads();
   }
-  // L_R y = r, then L_R^T x = y: wave q handles right-hand side q, lane k row k
+  // L_R y = r, then L_R^T x = y: wave q handles right-hand side q, lane k row k.  L is
+  // identity padded to 32 x 32, so both sweeps run 32 unrolled steps (the padded
+  // unknowns stay 0); each lane holds the row (forward) or column (backward) of L it
+  // updates with, and 1 / L[k][k] is formed once per lane and broadcast with x_k.
   const int wv = t >> 6, lane = t & 63;
   if (wv < nrhs) {
+    const int row = lane < 32 ? lane : 31;
     double v = (lane < n) ? r0[wv][lane] : 0.0;
-    for (int k = 0; k < n; ++k) {
-      const double xk = __shfl(v, k) / L[k * 33 + k];
-      if (lane == k) v = xk;
-      if (lane > k && lane < n) v -= L[lane * 33 + k] * xk;
+    const double rd = 1.0 / L[row * 33 + row];
+    double lk[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) lk[k] = L[row * 33 + k];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const double xk = wave_bcast(v, k) * wave_bcast(rd, k);
+      v = (lane == k) ? xk : (lane > k ? v - lk[k] * xk : v);
     }
-    for (int k = n - 1; k >= 0; --k) {
-      const double xk = __shfl(v, k) / L[k * 33 + k];
-      if (lane == k) v = xk;
-      if (lane < k) v -= L[k * 33 + lane] * xk;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) lk[k] = L[k * 33 + row];
+#pragma unroll
+    for (int k = 31; k >= 0; --k) {
+      const double xk = wave_bcast(v, k) * wave_bcast(rd, k);
+      v = (lane == k) ? xk : (lane < k ? v - lk[k] * xk : v);
     }
     if (lane < n) r0[wv][lane] = v;
   }
