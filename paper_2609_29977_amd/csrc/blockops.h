@@ -76,14 +76,16 @@ __device__ inline double wave_bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// 1/sqrt(x): hardware estimate refined by Newton steps y <- y (3 - x y^2) / 2
-// (one step for FP32, two for FP64: the estimate's error squares each step).
-__device__ inline float rsqrt_refined(float x) {
-  float y = __builtin_amdgcn_rsqf(x);
-  y = y * (1.5f - 0.5f * x * y * y);
-  return y;
+// 1/sqrt(x).  FP32: the hardware reciprocal square root, accurate to about one unit in
+// the last place, which is the rounding level of the FP32 factor anyway (and the
+// refinement around the FP32 path removes it); a Newton step would only lengthen the
+// dependency chain of every column of a factorization.  FP64: the hardware estimate
+// refined by two Newton steps y <- y (3 - x y^2) / 2 (the estimate's error squares
+// each step).
+__device__ inline float pivot_rsqrt(float x) {
+  return __builtin_amdgcn_rsqf(x);
 }
-__device__ inline double rsqrt_refined(double x) {
+__device__ inline double pivot_rsqrt(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * (1.5 - 0.5 * x * y * y);
   y = y * (1.5 - 0.5 * x * y * y);
@@ -111,7 +113,7 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
     if (fail < 0 && !(piv > T(0))) fail = k;
     // L[k][k] = piv * piv^{-1/2} and L[i][k] = a[i][k] * piv^{-1/2}: one refined
     // reciprocal square root instead of a square root and a division per column
-    const T inv = rsqrt_refined(piv);
+    const T inv = pivot_rsqrt(piv);
     const T lik = (lane == k) ? piv * inv : a[k] * inv;
     a[k] = lik;
 #pragma unroll
@@ -156,7 +158,7 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   for (int k = 0; k < NMAX; ++k) {
     const T piv = wave_bcast(v[k], k);
     if (fail < 0 && !(piv > T(0))) fail = k;
-    const T inv = rsqrt_refined(piv);
+    const T inv = pivot_rsqrt(piv);
     dinv[k] = inv;
     const T lik = v[k] * inv;               // L[i][k] on row lane i (>= k)
     const T y = rowl ? lik : inv * v[k];    // Z[k][j] / L[k][k] on column lane j

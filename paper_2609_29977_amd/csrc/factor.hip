@@ -558,6 +558,14 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
     }
   }
 
+  // The first even position's fetch does not depend on the prologue: in FP32 it is
+  // issued before it, so that the prologue hides its latency (the odd position's fetch
+  // reloads inverses the prologue writes).  In FP64 the registers it holds across the
+  // prologue cost more than the wait they save.
+  constexpr bool kEarlyEvenFetch = sizeof(T) == 4;
+  FetchEven<T, NMAX, FIRST, FWD> fe;
+  if constexpr (kEarlyEvenFetch)
+    if (lo + 2 <= hi) fe.issue(a, vc, s, lo + 2);
   // Prologue: the pass-local level-1 positions (odd q) see no update from inside the
   // window, so their diagonal blocks (D plus updates carried from earlier passes) are
   // factored and inverted up front.  Up to kBatch blocks at a time are loaded by the
@@ -650,9 +658,9 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
     __threadfence_block();
   }
   FetchOdd<T, NMAX, FIRST, FWD> fo;
-  FetchEven<T, NMAX, FIRST, FWD> fe;
   if (lo + 1 <= hi) fo.issue(a, vc, s, lo + 1);
-  if (lo + 2 <= hi) fe.issue(a, vc, s, lo + 2);
+  if constexpr (!kEarlyEvenFetch)
+    if (lo + 2 <= hi) fe.issue(a, vc, s, lo + 2);
 
   // The left boundary node keeps the updates it received while it was a window
   // boundary in earlier passes; they travel with it in its left accumulator.
