@@ -136,3 +136,24 @@ def test_fused_metric_workload_full_size():
     assert p32.info() == 0 and iters == 1
     assert rel(x32, ref) <= 1e-10
     p32.close()
+
+
+@pytest.mark.parametrize("S,N,n", [(3, 17, 16), (2, 33, 32), (2, 9, 7)])
+def test_maximum_right_hand_sides(S, N, n):
+    """kMaxRhs = 8 right-hand sides, the most a plan accepts (9 is rejected by the
+    analysis), through the fused and the separate entry points in both precisions."""
+    bm = _bm()
+    s = make_system(S, N, n, 8, 1e-2, 25)
+    ref, _ = oracle.solve(s.D, s.E, s.C, s.R, s.b, nthreads=4)
+    b = _dev(s.b)
+    p64 = bm.Plan(S, N, n, 8, "fp64")
+    assert rel(p64.factor_solve(*blocks(s), b).cpu().numpy(), ref) <= 1e-11
+    assert rel(p64.solve(b).cpu().numpy(), ref) <= 1e-11
+    p64.close()
+    p32 = bm.Plan(S, N, n, 8, "fp32")
+    x = p32.factor_refine(*blocks(s), b, tol=1e-13, max_iters=10).cpu().numpy()
+    assert p32.info() == 0 and p32.stats()[2]
+    assert rel(x, ref) <= 1e-10
+    x = p32.refine(*blocks(s), b, tol=1e-13, max_iters=10).cpu().numpy()
+    assert rel(x, ref) <= 1e-10
+    p32.close()
