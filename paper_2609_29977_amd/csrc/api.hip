@@ -288,6 +288,9 @@ bool dalloc(bmpc_plan p, void** ptr, size_t bytes) {
   bytes = std::max<size_t>(bytes, 256);
   if (hipMalloc(ptr, bytes) != hipSuccess) {
     *ptr = nullptr;
+    // the runtime keeps the failure as its last error; cleared here, since it is reported
+    // as BMPC_ERR_ALLOC and would otherwise surface in the next call that checks it
+    (void)hipGetLastError();
     return false;
   }
   p->allocs.push_back(*ptr);
@@ -551,6 +554,7 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
   }
   if (hipMemcpy(p->d_permpos, p->permpos.data(), (size_t)N * sizeof(int),
                 hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();  // reported here, not by a later call
     free_plan_memory(p);
     delete p;
     return BMPC_ERR_DEVICE;

@@ -65,3 +65,20 @@ def test_nan_in_rhs_propagates_and_refinement_does_not_converge():
     assert not conv and iters == 3
     assert math.isnan(relc) or relc > 1e-12
     p32.close()
+
+
+def test_allocation_failure_is_reported_and_leaves_no_error_behind():
+    """A plan within the dimension limits whose workspaces cannot fit in HBM (S = 31000,
+    N = 1000, n = 32 in FP64: three factor arrays of 254 GB each) fails with
+    BMPC_ERR_ALLOC and frees what it had allocated; the failure does not surface as an
+    error of later, valid calls."""
+    bm = _bm()
+    with pytest.raises(bm.BmpcError) as e:
+        bm.Plan(31000, 1000, 32, 1, "fp64")
+    assert e.value.status == bm.ERR_ALLOC
+    s = make_system(S, N, n, 1, 1e-2, 63)
+    p = bm.Plan(S, N, n, 1, "fp64")
+    p.factor(_dev(s.D), _dev(s.E), _dev(s.C), _dev(s.R))
+    x = p.solve(_dev(s.b)).cpu().numpy()
+    assert p.info() == 0 and np.isfinite(x).all()
+    p.close()
