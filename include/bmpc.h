@@ -144,9 +144,9 @@ bmpc_status bmpc_refine(bmpc_plan plan, const double* D, const double* E,
                         double tol, int32_t max_iters);
 
 /* bmpc_factor followed by bmpc_solve(b, x), with the tail forward substitution
- * (Algorithm 2, lines 1-4) carried out inside the factorization: each chain position
- * applies its L_jj^{-1} to its right-hand side when it is eliminated and passes
- * -G y_j to its two neighbours, in the elimination order of Algorithm 1, so the
+ * (the tail forward steps of Algorithm 2) carried out inside the factorization: each
+ * chain position applies its L_jj^{-1} to its right-hand side when it is eliminated
+ * and passes -G y_j to its two neighbours, in the elimination order of Algorithm 1, so the
  * forward sweep does not read the factor again.  Same result as the two calls up to
  * rounding order; same arguments and errors as bmpc_factor and bmpc_solve (x may
  * alias b).  The factor stays in the plan for later bmpc_solve calls. */

@@ -396,8 +396,8 @@ SolveArgs solve_args(bmpc_plan p, const double* b, double* x) {
   return a;
 }
 
-// Root step, root propagation and tail backward substitution (Algorithm 2 from line 5
-// on), given the y and w of the forward part.
+// Root step, root propagation and tail backward substitution (Algorithm 2 from its root
+// step on), given the y and w of the forward part.
 template <typename T>
 void enqueue_solve_back(bmpc_plan p, const SolveArgs& a) {
   hipStream_t st = p->stream;

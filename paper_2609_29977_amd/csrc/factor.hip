@@ -14,7 +14,8 @@
 // and so on.  A boundary node's updates from all earlier passes ride along in the
 // left accumulator of the window it starts, so its A is always D + all updates.
 // The last pass also eliminates x_1 (position X) and forms the coupling solve
-// F = C L_X^{-T} and the local Schur update U = F F^T (Algorithm 1, lines 4-5).
+// F = C L_X^{-T} and the local Schur update U = F F^T (Algorithm 1, coupling solve
+// and local Schur update).
 // FIRST (the pass reading D and E) and FINAL are template flags so that each pass
 // kind is its own kernel symbol in profiles.
 //
@@ -756,7 +757,7 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
     }
     return;
   } else {
-    // ---- last pass: x_1 step (Algorithm 1, lines 3-5 for the terminal block) ----
+    // ---- last pass: x_1 step (Algorithm 1, the tail steps for the terminal block) ----
     constexpr int LD = Lay<NMAX>::LD;
     T* Ax = sl.A(0);
     T* Cx = sl.Cp(0);
@@ -798,9 +799,9 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
       U[e] = acc;
     }
     if constexpr (FWD) {
-      // Fused forward substitution, X step (Algorithm 2, lines 3-5): the right-hand
-      // side of X is b at stage 0 plus the X updates of every pass (same order as its
-      // diagonal block); y_X = L_X^{-1} of it, and w_s = F_s y_X in FP64.
+      // Fused forward substitution, X step (the terminal forward step of Algorithm 2):
+      // the right-hand side of X is b at stage 0 plus the X updates of every pass (same
+      // order as its diagonal block); y_X = L_X^{-1} of it, and w_s = F_s y_X in FP64.
       constexpr int NT = TileCfg<NMAX>::NT;
       constexpr int TPR = NT / NMAX;
       constexpr int CPT = NMAX / TPR;
@@ -876,7 +877,8 @@ __global__ void __launch_bounds__(1024) root_reduce_kernel(const double* __restr
   part[((size_t)sys * groups + g) * nn + e] = acc;
 }
 
-// R~ = R - sum_g part[g] (group order), L_R = chol(R~) in FP64 (Algorithm 1, 7-8).
+// R~ = R - sum_g part[g] (group order), L_R = chol(R~) in FP64 (Algorithm 1, root
+// reduction and root factorization).
 // 1024 threads: thread e owns element e of the NMAX x NMAX block (identity padded
 // beyond n) and loads all group partials at once.
 template <int NMAX>

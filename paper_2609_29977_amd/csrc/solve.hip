@@ -6,9 +6,9 @@
 // so every factor block is read exactly once per sweep and no two work items write
 // the same vector (no atomics, fixed summation order).  Then X (x_1), whose row holds
 // the G_r blocks of the last position of every level with an odd chain length, and
-// the FP64 root step (Algorithm 2, lines 5-7).  Backward substitution walks the
+// the FP64 root step (Algorithm 2, root step).  Backward substitution walks the
 // levels in reverse; position j reads the already known x of its two neighbours.
-// The permutation Pi_i (Algorithm 2, lines 2 and 11) is applied as an index map:
+// The permutation Pi_i (Algorithm 2, gather and scatter) is applied as an index map:
 // chain position j reads and writes stage N-j of the natural-order vectors.
 //
 // Factor blocks are held in registers (RegBlock).  In the level kernels every block
@@ -749,7 +749,7 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
     }
   }
   __syncthreads();
-  // w_s = F_s y_X in FP64 (root reduction input, Algorithm 2 line 5)
+  // w_s = F_s y_X in FP64 (the root reduction input of Algorithm 2)
   const int b = RB::base(), o = RB::out_index();
 #pragma unroll
   for (int q = 0; q < kMaxRhs; ++q) {
@@ -764,7 +764,7 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   }
 }
 
-// Root step in FP64 (Algorithm 2, lines 5-7).  One workgroup of 1024 threads per
+// Root step in FP64 (Algorithm 2, root step).  One workgroup of 1024 threads per
 // system of the batch:
 // r~_0 = r_0 - sum_s w_s with thread (g, i) summing the scenarios s = g mod 32 of
 // element i and the 32 group partials combined in order; then the two triangular
@@ -869,7 +869,7 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
     sm.rhs[q][i] = i < n ? yx[q * n + i] : T(0);
   }
   __syncthreads();
-  // dy_X -= F^T x_0 (root propagation, Algorithm 2 line 9), product in FP64
+  // dy_X -= F^T x_0 (root propagation of Algorithm 2), product in FP64
   const int b = RB::base(), o = RB::out_index();
 #pragma unroll
   for (int q = 0; q < kMaxRhs; ++q) {
