@@ -157,7 +157,8 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B) {
   const int L = chain_levels(m);
   for (int k = 0; k < KC_COUNT; ++k) c.launches[k] = 1;
   c.launches[KC_SOLVE_FWD] = L;
-  c.launches[KC_SOLVE_BWD] = L;
+  const int top = bwd_top_level(m, n, d.nrhs, S, B);
+  c.launches[KC_SOLVE_BWD] = top <= L ? top : L;  // levels below top, plus one for the rest
   // a batch of B systems does B times the work in the same launches
   for (PassPlan& pp : c.passes) {
     pp.flops *= B;
@@ -404,7 +405,10 @@ void enqueue_solve_back(bmpc_plan p, const SolveArgs& a) {
   const int L = chain_levels(p->m);
   timed(p, KC_SOLVE_ROOT, [&] { launch_solve_root(a, st); });
   timed(p, KC_SOLVE_X_BWD, [&] { launch_solve_x_bwd<T>(a, p->nmax, st); });
-  for (int l = L; l >= 1; --l)
+  // the top levels (few positions per chain) in one launch, the others one by one
+  const int top = bwd_top_level(p->m, p->d.n, p->d.nrhs, p->d.S, p->B);
+  if (top <= L) timed(p, KC_SOLVE_BWD, [&] { launch_solve_bwd_top<T>(a, top, st); });
+  for (int l = std::min(L, top - 1); l >= 1; --l)
     timed(p, KC_SOLVE_BWD, [&] { launch_solve_bwd_level<T>(a, l, p->nmax, st); });
 }
 

@@ -170,6 +170,10 @@ template <typename T>
 void launch_solve_x_bwd(const SolveArgs& a, int nmax, hipStream_t st);
 template <typename T>
 void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st);
+// The backward levels from level_lo up to the top, in one launch (one workgroup per
+// chain, one wave per position, top level first); only where bwd_top_level says so.
+template <typename T>
+void launch_solve_bwd_top(const SolveArgs& a, int level_lo, hipStream_t st);
 
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st);
 void launch_grad_blocks(const GradArgs& a, hipStream_t st);
@@ -197,6 +201,20 @@ __host__ __device__ inline int chain_levels(int m) {
   int L = 0;
   while ((m >> L) > 0) ++L;
   return L;  // floor(log2 m) + 1 for m >= 1, 0 for m = 0
+}
+
+// Positions per chain up to which backward levels share one launch.
+constexpr int kBwdTopWaves = 8;
+// Lowest backward level walked by launch_solve_bwd_top: the levels with at most
+// kBwdTopWaves positions per chain, when the plan's backward levels use the row-read
+// kernel (n = 32, one right-hand side, S and B within the grid's y and z limits);
+// otherwise chain_levels(m) + 1, i.e. no level.
+inline int bwd_top_level(int m, int n, int nrhs, int S, int B) {
+  const int L = chain_levels(m);
+  if (n != 32 || nrhs != 1 || S > 65535 || B > 65535) return L + 1;
+  int l = L + 1;
+  while (l > 1 && level_count(m, l - 1) <= kBwdTopWaves) --l;
+  return l;
 }
 
 }  // namespace bmpc

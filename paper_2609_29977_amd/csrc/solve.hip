@@ -591,8 +591,8 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_kernel(So
 // left neighbour (it is then never written and not used), so that no load waits on a
 // branch.  Same result as solve_level_one_kernel<T, 32, false> up to summation order.
 template <typename T>
-__global__ void __launch_bounds__(64) solve_bwd_rows_kernel(SolveArgs a, int level) {
-  if (a.done && *a.done) return;
+__device__ __attribute__((always_inline)) inline void bwd_rows_position(
+    const SolveArgs& a, int level, int i, int sl, int sys, T (*xs)[32]) {
   constexpr int NMAX = 32;
   constexpr int VEC = 16 / (int)sizeof(T);
   constexpr int QPR = NMAX / VEC;
@@ -601,10 +601,9 @@ __global__ void __launch_bounds__(64) solve_bwd_rows_kernel(SolveArgs a, int lev
   constexpr int n = NMAX;
   constexpr size_t nn = (size_t)NMAX * NMAX;
   typedef T vt __attribute__((ext_vector_type(VEC)));
-  __shared__ T xs[3][NMAX];  // x of the left and right neighbours, y_j; then r by rows
-  const int lane = threadIdx.x, q = lane % QPR, mrow = lane / QPR;
+  // xs[3][NMAX] (this wave's LDS): x of the left and right neighbours, y_j; then r by rows
+  const int lane = threadIdx.x & 63, q = lane % QPR, mrow = lane / QPR;
   const int N = a.N, m = a.m;
-  const int i = blockIdx.x, sl = blockIdx.y, sys = blockIdx.z;
   const size_t s = (size_t)sys * a.S + sl;
   const int j = (2 * i + 1) << (level - 1);
   const int half = 1 << (level - 1);
@@ -702,6 +701,33 @@ __global__ void __launch_bounds__(64) solve_bwd_rows_kernel(SolveArgs a, int lev
         a.x[idx] = d;
       }
     }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) solve_bwd_rows_kernel(SolveArgs a, int level) {
+  if (a.done && *a.done) return;
+  __shared__ T xs[3][32];
+  bwd_rows_position<T>(a, level, blockIdx.x, blockIdx.y, blockIdx.z, xs);
+}
+
+// The top backward levels of every chain in one launch: one workgroup per chain (grid
+// y: system), wave w solves position w of each level from the top level down to
+// level_lo (at most kBwdTopWaves positions per level), with a barrier between levels.
+// A position reads the x of its neighbours from y, written by other waves of the
+// workgroup at higher levels; the barrier orders those stores before the reads (the
+// waves of a workgroup share one CU and its vector cache).  Same arithmetic as
+// solve_bwd_rows_kernel level by level, so the results are bitwise equal.
+template <typename T>
+__global__ void __launch_bounds__(64 * kBwdTopWaves) solve_bwd_top_kernel(SolveArgs a,
+                                                                          int level_lo) {
+  if (a.done && *a.done) return;
+  __shared__ T xs[kBwdTopWaves][3][32];
+  const int w = threadIdx.x >> 6;
+  for (int level = chain_levels(a.m); level >= level_lo; --level) {
+    if (w < level_count(a.m, level))
+      bwd_rows_position<T>(a, level, w, blockIdx.x, blockIdx.y, xs[w]);
+    __syncthreads();
   }
 }
 
@@ -969,6 +995,13 @@ void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t
   BMPC_DISPATCH_NMAX(nmax, bwd_level_t, a, level, st);
 }
 template <typename T>
+void launch_solve_bwd_top(const SolveArgs& a, int level_lo, hipStream_t st) {
+  const int waves = level_count(a.m, level_lo);
+  if (waves < 1 || waves > kBwdTopWaves) return;
+  hipLaunchKernelGGL((solve_bwd_top_kernel<T>), dim3(a.S, a.B), dim3(64 * waves), 0, st, a,
+                     level_lo);
+}
+template <typename T>
 void launch_solve_x_fwd(const SolveArgs& a, int nmax, hipStream_t st) {
   BMPC_DISPATCH_NMAX(nmax, x_fwd_t, a, st);
 }
@@ -984,6 +1017,8 @@ template void launch_solve_fwd_level<double>(const SolveArgs&, int, int, hipStre
 template void launch_solve_fwd_level<float>(const SolveArgs&, int, int, hipStream_t);
 template void launch_solve_bwd_level<double>(const SolveArgs&, int, int, hipStream_t);
 template void launch_solve_bwd_level<float>(const SolveArgs&, int, int, hipStream_t);
+template void launch_solve_bwd_top<double>(const SolveArgs&, int, hipStream_t);
+template void launch_solve_bwd_top<float>(const SolveArgs&, int, hipStream_t);
 template void launch_solve_x_fwd<double>(const SolveArgs&, int, hipStream_t);
 template void launch_solve_x_fwd<float>(const SolveArgs&, int, hipStream_t);
 template void launch_solve_x_bwd<double>(const SolveArgs&, int, hipStream_t);
