@@ -206,12 +206,12 @@ __host__ __device__ inline int chain_levels(int m) {
 // Positions per chain up to which backward levels share one launch.
 constexpr int kBwdTopWaves = 8;
 // Lowest backward level walked by launch_solve_bwd_top: the levels with at most
-// kBwdTopWaves positions per chain, when the plan's backward levels use the row-read
-// kernel (n = 32, one right-hand side, S and B within the grid's y and z limits);
-// otherwise chain_levels(m) + 1, i.e. no level.
+// kBwdTopWaves positions per chain, when the plan's backward levels use the one-vector
+// kernels (one right-hand side, n = 8, 16 or 32, S and B within the grid's y and z
+// limits); otherwise chain_levels(m) + 1, i.e. no level.
 inline int bwd_top_level(int m, int n, int nrhs, int S, int B) {
   const int L = chain_levels(m);
-  if (n != 32 || nrhs != 1 || S > 65535 || B > 65535) return L + 1;
+  if ((n != 8 && n != 16 && n != 32) || nrhs != 1 || S > 65535 || B > 65535) return L + 1;
   int l = L + 1;
   while (l > 1 && level_count(m, l - 1) <= kBwdTopWaves) --l;
   return l;

@@ -447,22 +447,22 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
 // several right-hand sides taken out.  Lane l holds element l % NMAX of each vector it
 // stages; the chain comes from the grid (position index, scenario, system), and each
 // wave keeps its partial sums in a register across rounds.
+// One position (index i of the level, scenario sl, system sys) served by W waves, this
+// thread's wave being wv; smem holds (W * kPullsPerWave + W + 1) * NMAX elements.
 template <typename T, int NMAX, bool FWD>
-__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_kernel(SolveArgs a,
-                                                                             int level) {
-  if (a.done && *a.done) return;
+__device__ __attribute__((always_inline)) inline void level_one_position(
+    const SolveArgs& a, int level, int i, int sl, int sys, int W, int wv,
+    unsigned char* smem) {
   typedef RegBlock<T, NMAX> RB;
   constexpr int P = kPullsPerWave;
   constexpr int n = NMAX;
   constexpr size_t nn = (size_t)NMAX * NMAX;
   const int N = a.N, m = a.m;
-  const int W = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  extern __shared__ __align__(16) unsigned char level_smem[];
+  const int lane = threadIdx.x & 63;
   typedef T Vec[NMAX];
-  Vec* vbuf = reinterpret_cast<Vec*>(level_smem);  // [w * P + u]
-  Vec* partial = vbuf + W * P;                     // [w]
-  T* t = partial[W];                               // right-hand side, then residual
-  const int i = blockIdx.x, sl = blockIdx.y, sys = blockIdx.z;
+  Vec* vbuf = reinterpret_cast<Vec*>(smem);  // [w * P + u]
+  Vec* partial = vbuf + W * P;               // [w]
+  T* t = partial[W];                         // right-hand side, then residual
   const size_t s = (size_t)sys * a.S + sl;
   const int j = (2 * i + 1) << (level - 1);
   const size_t gstride = g_chain_blocks(N);
@@ -579,6 +579,15 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_kernel(So
       }
     }
   }
+}
+
+template <typename T, int NMAX, bool FWD>
+__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_kernel(SolveArgs a,
+                                                                             int level) {
+  if (a.done && *a.done) return;
+  extern __shared__ __align__(16) unsigned char level_smem[];
+  level_one_position<T, NMAX, FWD>(a, level, blockIdx.x, blockIdx.y, blockIdx.z,
+                                   (int)(blockDim.x >> 6), (int)(threadIdx.x >> 6), level_smem);
 }
 
 // Backward level kernel for one right-hand side and n = 32 that reads every block by
@@ -716,17 +725,25 @@ __global__ void __launch_bounds__(64) solve_bwd_rows_kernel(SolveArgs a, int lev
 // level_lo (at most kBwdTopWaves positions per level), with a barrier between levels.
 // A position reads the x of its neighbours from y, written by other waves of the
 // workgroup at higher levels; the barrier orders those stores before the reads (the
-// waves of a workgroup share one CU and its vector cache).  Same arithmetic as
-// solve_bwd_rows_kernel level by level, so the results are bitwise equal.
-template <typename T>
+// waves of a workgroup share one CU and its vector cache).  Each position runs the code
+// of the single-level kernel (row reads at n = 32, one wave of the general one-vector
+// kernel otherwise), so the results are bitwise those of the launches level by level.
+template <typename T, int NMAX>
 __global__ void __launch_bounds__(64 * kBwdTopWaves) solve_bwd_top_kernel(SolveArgs a,
                                                                           int level_lo) {
   if (a.done && *a.done) return;
-  __shared__ T xs[kBwdTopWaves][3][32];
+  constexpr int PER = NMAX == 32 ? 3 * NMAX : (kPullsPerWave + 2) * NMAX;  // per wave
+  __shared__ __align__(16) T sm[kBwdTopWaves * PER];
   const int w = threadIdx.x >> 6;
   for (int level = chain_levels(a.m); level >= level_lo; --level) {
-    if (w < level_count(a.m, level))
-      bwd_rows_position<T>(a, level, w, blockIdx.x, blockIdx.y, xs[w]);
+    if (w < level_count(a.m, level)) {
+      if constexpr (NMAX == 32)
+        bwd_rows_position<T>(a, level, w, blockIdx.x, blockIdx.y,
+                             reinterpret_cast<T(*)[NMAX]>(sm + w * PER));
+      else
+        level_one_position<T, NMAX, false>(a, level, w, blockIdx.x, blockIdx.y, 1, 0,
+                                           reinterpret_cast<unsigned char*>(sm + w * PER));
+    }
     __syncthreads();
   }
 }
@@ -998,8 +1015,13 @@ template <typename T>
 void launch_solve_bwd_top(const SolveArgs& a, int level_lo, hipStream_t st) {
   const int waves = level_count(a.m, level_lo);
   if (waves < 1 || waves > kBwdTopWaves) return;
-  hipLaunchKernelGGL((solve_bwd_top_kernel<T>), dim3(a.S, a.B), dim3(64 * waves), 0, st, a,
-                     level_lo);
+  const dim3 grid(a.S, a.B), block(64 * waves);
+  if (a.n == 32)
+    hipLaunchKernelGGL((solve_bwd_top_kernel<T, 32>), grid, block, 0, st, a, level_lo);
+  else if (a.n == 16)
+    hipLaunchKernelGGL((solve_bwd_top_kernel<T, 16>), grid, block, 0, st, a, level_lo);
+  else if (a.n == 8)
+    hipLaunchKernelGGL((solve_bwd_top_kernel<T, 8>), grid, block, 0, st, a, level_lo);
 }
 template <typename T>
 void launch_solve_x_fwd(const SolveArgs& a, int nmax, hipStream_t st) {
