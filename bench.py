@@ -471,10 +471,16 @@ def main():
     p32 = bmpc.Plan(S, N, n, nrhs, "fp32", args.window_depth)
     p64 = bmpc.Plan(S, N, n, nrhs, "fp64", args.window_depth)
     analyze_ms = (time.perf_counter() - ta) * 1e3
+    # the same FP32 path with the library deciding when to stop: refinement until the
+    # normwise backward error of x, taken from its own FP64 residual, is <= 16 u
+    p32c = bmpc.Plan(S, N, n, nrhs, "fp32", args.window_depth)
+    p32c.set_refine_stop("backward_error")
+    cert_tol = 16 * bmpc.UNIT_ROUNDOFF
     cost = p64.cost()
     flops = cost.factor_flops + cost.solve_flops
     x32 = torch.empty_like(b)
     x64 = torch.empty_like(b)
+    x32c = torch.empty_like(b)
 
     # The timed step: factor + solve with the first solve's forward substitution inside
     # the factorization (bmpc_factor_refine / bmpc_factor_solve); --separate times the
@@ -492,6 +498,9 @@ def main():
     def step64_sep():
         p64.factor(D, E, C, R)
         p64.solve(b, x64)
+
+    def step32_cert():
+        p32c.factor_refine(D, E, C, R, b, x32c, tol=cert_tol, max_iters=10)
 
     step32, step64 = (step32_sep, step64_sep) if args.separate else (step32_fused, step64_fused)
     alt32, alt64 = (step32_fused, step64_fused) if args.separate else (step32_sep, step64_sep)
@@ -512,11 +521,15 @@ def main():
     for _ in range(args.warmup):
         step32()
         step64()
+        step32_cert()
     torch.cuda.synchronize()
     log("warmup done")
     ms32, per32 = timed(step32, args.steps)
     ms64, per64 = timed(step64, args.steps)
-    log(f"fp32+ir {ms32:.3f} ms/step, fp64 {ms64:.3f} ms/step")
+    ms32c, per32c = timed(step32_cert, args.steps)
+    cert_iters, cert_eta, cert_ok = p32c.stats()
+    log(f"fp32+ir {ms32:.3f} ms/step, fp64 {ms64:.3f} ms/step, fp32+ir with the backward-error "
+        f"stop {ms32c:.3f} ms/step ({cert_iters} corrections, eta {cert_eta:.2e})")
     alt32(), alt64()
     alt_ms32, _ = timed(alt32, args.steps)
     alt_ms64, _ = timed(alt64, args.steps)
@@ -585,31 +598,22 @@ def main():
                     "source_digest": digest}
 
     # Accuracy against the FP64 oracle and the CPU baseline (oracle timed on the host).
-    err32 = err64 = None
+    err32 = err64 = err32c = None
     cpu = None
+    kappa = None
     iters, relc, _ = p32.stats()
     if not args.no_cpu:
         from oracle import oracle
-        threads = os.cpu_count() or 1
-        try:
-            threads = len(os.sched_getaffinity(0))
-        except AttributeError:
-            pass
-        threads = min(threads, 16)
         ref, info, (tf, ts) = oracle.solve(sysd.D, sysd.E, sysd.C, sysd.R, sysd.b,
-                                           nthreads=threads, return_times=True)
-        X32 = x32.cpu().numpy()
-        X64 = x64.cpu().numpy()
+                                           nthreads=host_threads(), return_times=True)
         scale = float(np.max(np.abs(ref)))
-        err32 = float(np.max(np.abs(X32 - ref)) / scale)
-        err64 = float(np.max(np.abs(X64 - ref)) / scale)
-        cpu = {"value": round(flops / (tf + ts) / 1e9, 3), "unit": "GFLOP/s",
-               "cores": oracle.threads_used(threads), "kind": "oracle",
-               "sample": f"whole {args.config} system (S={S} N={N} n={n}), one factor+solve "
-                         f"in {tf + ts:.2f}s; natural-order band Cholesky, OpenMP over scenarios",
-               "ms": round((tf + ts) * 1e3, 1)}
-        log(f"oracle {tf + ts:.2f}s on {threads} threads; err fp32+ir {err32:.2e} fp64 {err64:.2e}")
-
+        err32 = float(np.max(np.abs(x32.cpu().numpy() - ref)) / scale)
+        err64 = float(np.max(np.abs(x64.cpu().numpy() - ref)) / scale)
+        err32c = float(np.max(np.abs(x32c.cpu().numpy() - ref)) / scale)
+        log(f"oracle on the whole system {tf + ts:.2f}s; err fp32+ir {err32:.2e} fp64 "
+            f"{err64:.2e} certified {err32c:.2e}")
+        cpu = cpu_baseline(sysd, args.config)
+        kappa = measured_kappa(args.config)
     gfs32 = flops / (ms32 * 1e-3) / 1e9
     gfs64 = flops / (ms64 * 1e-3) / 1e9
     out = {
@@ -636,6 +640,12 @@ def main():
                     "ir_corrections": iters, "last_rel_correction": relc,
                     "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
                                             for k, v in kt["fp32_ir"].items()}},
+        "fp32_ir_certified": {
+            "ms_per_step": round(ms32c, 4), "median_ms": round(statistics.median(per32c), 4),
+            "gflops": round(flops / (ms32c * 1e-3) / 1e9, 2), "rel_err_vs_oracle": err32c,
+            "stop": "normwise backward error <= 16u from the FP64 residual of the returned x",
+            "ir_corrections": cert_iters, "backward_error": cert_eta, "converged": cert_ok,
+            "speedup_vs_fp64": round(ms64 / ms32c, 3)},
         "fp64": {"ms_per_step": round(ms64, 4), "median_ms": round(statistics.median(per64), 4),
                  "gflops": round(gfs64, 2), "rel_err_vs_oracle": err64,
                  "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
@@ -650,10 +660,101 @@ def main():
         "copy_gb_s": round(copy_gbs, 1),
         "kernels_roofline": per_kernel,
         "cpu_baseline": cpu,
+        "kappa": kappa,
     }
     print(json.dumps(out), flush=True)
     p32.close()
     p64.close()
+    p32c.close()
+
+
+def host_threads():
+    """Threads the oracle may use: the CPU affinity of this process, at most 16 (the
+    host's CPU share for one GPU)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(avail, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sysd, config):
+    """The oracle (natural-order band Cholesky + solve, FP64, OpenMP over scenarios)
+    timed on this host: single-threaded and on every thread of the host's share, each
+    the median of 3 runs after 1 warm-up, on a bounded sample of the workload (the
+    first scenarios of the system, all stages, its root block); the oracle's work is
+    linear in the scenarios, so the rate holds for the whole system."""
+    import numpy as np
+
+    from oracle import oracle
+    from paper_2609_29977_amd import bmpc
+
+    S, N, n = sysd.S, sysd.N, sysd.n
+
+    def sample(Ss):
+        Ss = min(S, Ss)
+        b = np.concatenate([sysd.b[:, :Ss * N * n], sysd.b[:, S * N * n:]], axis=1)
+        c = bmpc.cost_model(Ss, N, n, sysd.nrhs, "fp64")
+        return (sysd.D[:Ss], sysd.E[:Ss], sysd.C[:Ss], sysd.R, b), Ss, c.factor_flops + c.solve_flops
+
+    def med(args, threads):
+        ts = []
+        for _ in range(4):
+            _, _, (tf, tsol) = oracle.solve(*args, nthreads=threads, return_times=True)
+            ts.append(tf + tsol)
+        return statistics.median(ts[1:])
+
+    threads = host_threads()
+    used = oracle.threads_used(threads)
+    args1, s1, fl1 = sample(max(1, S // 32))
+    t1 = med(args1, 1)
+    argsT, sT, flT = sample(max(1, S // 8))
+    tT = med(argsT, threads)
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"value": round(flT / tT / 1e9, 3), "unit": "GFLOP/s", "cores": used,
+            "kind": "oracle",
+            "sample": f"{config} with its first {sT} of {S} scenarios (all {N} stages, "
+                      f"n={n}, root block), one factor+solve, median of 3 after 1: "
+                      f"{tT * 1e3:.0f} ms on {used} threads; natural-order band Cholesky, "
+                      "OpenMP over scenarios",
+            "single_thread": {"value": round(fl1 / t1 / 1e9, 3), "unit": "GFLOP/s",
+                              "sample_scenarios": s1, "ms": round(t1 * 1e3, 1),
+                              "est_full_system_s": round(t1 * S / s1, 1)},
+            "all_threads": {"value": round(flT / tT / 1e9, 3), "threads": used,
+                            "sample_scenarios": sT, "ms": round(tT * 1e3, 1),
+                            "est_full_system_s": round(tT * S / sT, 2)},
+            "cpu_model": cpu_model(), "host_cpus": nproc, "os_cpu_count": os.cpu_count(),
+            "thread_cap": "16 = the host's CPU share for one GPU"}
+
+
+def measured_kappa(config):
+    """kappa(K) = lambda_max / lambda_min of the workload's generator on a copy with 8
+    stages (same S, n, delta, seed; kappa is set by S, not N), by Lanczos and
+    shift-invert Lanczos (oracle.conditioning)."""
+    from oracle.conditioning import extreme_eigenvalues
+    from synth.branch_system import CONFIGS, make_system
+    S, N, n, nrhs, delta = CONFIGS[config]
+    Nk = min(N, 8)
+    s = make_system(S, Nk, n, 1, delta, 0)
+    t0 = time.perf_counter()
+    lmin, lmax = extreme_eigenvalues(s.D, s.E, s.C, s.R)
+    return {"value": round(lmax / lmin, 1), "lambda_min": lmin, "lambda_max": lmax,
+            "measured_on": f"{config} generator with N={Nk} (S={S}, n={n}, delta={delta}, seed 0)",
+            "seconds": round(time.perf_counter() - t0, 1)}
 
 
 if __name__ == "__main__":

@@ -71,17 +71,30 @@ typedef enum {
 typedef struct {
   int32_t S;    /* scenarios, >= 1 */
   int32_t N;    /* stages per tail, >= 1 */
-  int32_t n;    /* block size, 1..32 */
-  int32_t nrhs; /* right-hand sides per solve, 1..8 */
+  int32_t n;    /* block size n_b (Assumption 1, uniform), 1..32 */
+  int32_t nrhs; /* right-hand sides per solve, >= 1 (Section III-B partitions each
+                   right-hand side like the unknowns; their number is free).  The
+                   kernels take them in chunks of 8. */
 } bmpc_dims;
+
+/* bmpc_options.flags */
+#define BMPC_FLAG_NO_BWD_TOP_MERGE 0x1 /* backward sweep: one launch per level even where
+                                          the top levels could share one launch */
 
 typedef struct {
   int32_t window_depth; /* 0 = automatic; else levels eliminated per factor pass
                            (1..6), bounded by the shared-memory budget */
   int32_t num_systems;  /* 0 or 1: one system; B > 1: a batch of B independent
                            systems of the same dims (layouts: see "Batches") */
-  int32_t reserved[6];
+  int32_t flags;        /* BMPC_FLAG_* bits, 0 = defaults */
+  int32_t reserved[5];
 } bmpc_options;
+
+/* Stop tests of bmpc_refine / bmpc_factor_refine (bmpc_set_refine_stop). */
+typedef enum {
+  BMPC_STOP_CORRECTION = 0,     /* |d|_inf <= tol |x|_inf for the last correction d */
+  BMPC_STOP_BACKWARD_ERROR = 1  /* |b - K x|_inf <= tol (|K|_inf |x|_inf + |b|_inf) */
+} bmpc_refine_stop;
 
 typedef struct {
   double factor_flops;    /* exact flop count of Algorithm 1 (method's count) */
@@ -115,6 +128,10 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
 /* Replace the stream later calls enqueue on (e.g. a graph-capture stream). */
 bmpc_status bmpc_set_stream(bmpc_plan plan, void* stream);
 
+/* Stop test of later bmpc_refine / bmpc_factor_refine calls on this plan (a
+ * bmpc_refine_stop value); BMPC_ERR_INVALID for another value. */
+bmpc_status bmpc_set_refine_stop(bmpc_plan plan, int32_t stop);
+
 /* Algorithm 1: L_i = chol(Pi_i K_i Pi_i^T) for every tail (horizon-parallel block
  * elimination in the Gamma order), F_{i,1} = C_{i,1} L_{i,1}^{-T},
  * U_i = F_{i,1} F_{i,1}^T, R~ = R - sum_i U_i (FP64, fixed summation order) and
@@ -134,10 +151,19 @@ bmpc_status bmpc_solve(bmpc_plan plan, const double* b, double* x);
 
 /* Mixed-precision iterative refinement (not in the paper; classical scheme, Moler
  * 1967): x = solve(b); then repeat r = b - K x in FP64 from the caller's FP64
- * blocks, d = solve(r / |r|_inf) * |r|_inf, x += d, until |d|_inf <= tol * |x|_inf
- * for every right-hand side or max_iters corrections were applied.  Needs the
- * factor of the same D, E, C, R.  x on entry is ignored.  The stop test runs on the
- * device (later launches of a converged loop return at once), so the launch
+ * blocks, d = solve(r / |r|_inf) * |r|_inf, x += d, until the plan's stop test holds
+ * for every right-hand side (and system of a batch) or max_iters corrections were
+ * applied.  Stop tests (bmpc_set_refine_stop):
+ *   BMPC_STOP_CORRECTION (default): |d|_inf <= tol |x|_inf after a correction d;
+ *   BMPC_STOP_BACKWARD_ERROR: the normwise backward error of x,
+ *     |b - K x|_inf / (|K|_inf |x|_inf + |b|_inf) <= tol, on the FP64 residual the
+ *     loop forms anyway (|K|_inf = the largest row sum of |K|, taken in the first
+ *     residual); a converged x needs no further correction, and an x that passes the
+ *     test is certified by its own residual, so max_iters corrections take up to
+ *     max_iters + 1 residuals (tol = c * 2^-53 with c of order 10 asks for the backward
+ *     stability of an FP64 solve).
+ * Needs the factor of the same D, E, C, R.  x on entry is ignored.  The stop test runs
+ * on the device (later launches of a converged loop return at once), so the launch
  * sequence is fixed and capturable.  max_iters in 0..100. */
 bmpc_status bmpc_refine(bmpc_plan plan, const double* D, const double* E,
                         const double* C, const double* R, const double* b, double* x,
@@ -186,15 +212,24 @@ bmpc_status bmpc_grad_blocks(bmpc_plan plan, const double* x, const double* lam,
  * the elimination order Pi, and the call returns BMPC_ERR_NOT_SPD. */
 bmpc_status bmpc_get_info(bmpc_plan plan, int64_t* info);
 
-/* Synchronizes.  Corrections applied by the last bmpc_refine and the final
- * max |d_q|_inf / |x_q|_inf over the right-hand sides (and systems of a batch; the
- * stop test holds for each of them).  Returns BMPC_ERR_NOT_CONVERGED if the stop test
- * was not met within max_iters. */
+/* Synchronizes.  Corrections applied by the last bmpc_refine and its final stop-test
+ * quantity, the largest over the right-hand sides (and systems of a batch; the stop
+ * test holds for each of them): |d_q|_inf / |x_q|_inf of the last correction
+ * (BMPC_STOP_CORRECTION) or the normwise backward error of the returned x
+ * (BMPC_STOP_BACKWARD_ERROR).  Returns BMPC_ERR_NOT_CONVERGED if the stop test was not
+ * met within max_iters. */
 bmpc_status bmpc_get_stats(bmpc_plan plan, int32_t* iters, double* rel_correction);
 
 /* Host copies of the analysis.  perm: int32[N], the 0-based stage at each permuted
  * position of a tail (the same for every tail; x_1 = stage 0 is last). */
 bmpc_status bmpc_query_perm(bmpc_plan plan, int32_t* perm);
+/* The factor's block structure under the plan's ordering (Theorem 1 and the
+ * elimination levels of Section IV-A): the same pairs as bmpc_structure(N) for the
+ * plan's N -- one tail (positions 0..N-1 in permuted order) plus the root (N); every
+ * tail of every system has it.  Writes at most cap pairs, *count = the full number
+ * (cap = 0 sizes). */
+bmpc_status bmpc_query_structure(bmpc_plan plan, int32_t* rows, int32_t* cols, int64_t cap,
+                                 int64_t* count);
 bmpc_status bmpc_query_cost(bmpc_plan plan, bmpc_cost* cost);
 
 /* Algorithmic HBM bytes and flops that kernel class cls (see bmpc_kernel_class_name)
@@ -248,9 +283,12 @@ typedef struct {
  * the terminal term on u = x_{s,N-1} (its v columns must be zero).  Device arrays:
  *   Q [S][N+1][2n][2n]   link cost Hessians (P = sum of links), variables (u, v)
  *   A [S][N+1][me][2n]   equality rows,  G [S][N+1][mi][2n] inequality rows
- *   w [S][N+1][mi]       diagonal of W (positive)
+ *   w [S][N+1][mi]       diagonal of W (nonnegative; the IPM weights are positive)
  * Outputs (device, overwritten): D [S][N][n][n] (both triangles), E [S][N-1][n][n],
  * C [S][n][n], R [n][n]; work: device scratch of S*n*n doubles.  tau >= 0, delta > 0.
+ * The ADMM system of the same appendix (the OSQP form [[P + sigma I, A^T, G^T],
+ * [A, -rho^{-1} I, 0], [G, 0, -rho^{-1} I]], reduced to P + sigma I + rho A^T A +
+ * rho G^T G) is this assembly with w = 0, tau = sigma and delta = 1/rho.
  * Asynchronous on stream (NULL = legacy default); allocates nothing.  The root block
  * is summed over the scenarios in scenario order (deterministic). */
 bmpc_status bmpc_assemble_qp(const bmpc_qp_dims* dims, const double* Q, const double* A,

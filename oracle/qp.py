@@ -6,6 +6,9 @@ order (tails in stage order, root last, as the right-hand side b), the regulariz
 IPM KKT matrix is [[P + tau I, A^T, G^T], [A, -delta I, 0], [G, 0, -(W + delta I)]]
 and eliminating its second and third block rows gives the SPD matrix
 K = P + tau I + delta^{-1} A^T A + G^T (W + delta I)^{-1} G.
+The ADMM matrix of the same appendix (the OSQP form) is written out the same way:
+[[P + sigma I, A^T, G^T], [A, -rho^{-1} I, 0], [G, 0, -rho^{-1} I]], and eliminating
+its second and third block rows gives P + sigma I + rho A^T A + rho G^T G.
 `blocks` reads D, E, C, R out of the dense K in the layout of synth.branch_system.
 """
 from __future__ import annotations
@@ -80,3 +83,25 @@ def blocks(K, S, N, n):
         o = s * N * n
         C[s] = K[r:r + n, o:o + n]
     return D, E, C, K[r:, r:].copy()
+
+
+def admm_kkt(qp, sigma: float, rho: float):
+    """The ADMM KKT matrix of the appendix (OSQP form) for the QP data of ``qp``
+    (its IPM weights and regularization are not used)."""
+    P, A, G, _ = dense_qp(qp)
+    nv, ne, ni = P.shape[0], A.shape[0], G.shape[0]
+    M = np.zeros((nv + ne + ni, nv + ne + ni))
+    M[:nv, :nv] = P + sigma * np.eye(nv)
+    M[:nv, nv:nv + ne] = A.T
+    M[nv:nv + ne, :nv] = A
+    M[:nv, nv + ne:] = G.T
+    M[nv + ne:, :nv] = G
+    M[nv:, nv:] = -np.eye(ne + ni) / rho
+    return M
+
+
+def admm_reduced_K(qp, sigma: float, rho: float):
+    """The reduced ADMM matrix P + sigma I + rho (A^T A + G^T G)."""
+    P, A, G, _ = dense_qp(qp)
+    K = P + sigma * np.eye(P.shape[0]) + rho * (A.T @ A + G.T @ G)
+    return 0.5 * (K + K.T)

@@ -16,6 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libbmpc.so")
 OK, ERR_INVALID, ERR_NOT_SPD, ERR_ALLOC, ERR_DEVICE, ERR_STATE, ERR_NOT_CONVERGED = \
     0, -1, -2, -3, -4, -5, -6
 FP64, FP32_REFINE = 0, 1
+FLAG_NO_BWD_TOP_MERGE = 0x1
+STOP_CORRECTION, STOP_BACKWARD_ERROR = 0, 1
+UNIT_ROUNDOFF = 2.0 ** -53
 
 EXPORTED = [
     "bmpc_analyze", "bmpc_analyze_ex", "bmpc_set_stream", "bmpc_factor", "bmpc_solve",
@@ -25,7 +28,7 @@ EXPORTED = [
     "bmpc_reset_kernel_times", "bmpc_kernel_class_name", "bmpc_kernel_class_count",
     "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
     "bmpc_cost_model", "bmpc_grad_blocks", "bmpc_assemble_qp", "bmpc_factor_solve",
-    "bmpc_factor_refine",
+    "bmpc_factor_refine", "bmpc_set_refine_stop", "bmpc_query_structure",
 ]
 
 
@@ -47,7 +50,7 @@ class _QpDims(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("window_depth", ctypes.c_int32), ("num_systems", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class _Cost(ctypes.Structure):
@@ -89,6 +92,8 @@ def lib():
         "bmpc_analyze": [P(_Dims), i32, vp, P(vp)],
         "bmpc_analyze_ex": [P(_Dims), i32, vp, P(_Options), P(vp)],
         "bmpc_set_stream": [vp, vp],
+        "bmpc_set_refine_stop": [vp, i32],
+        "bmpc_query_structure": [vp, P(i32), P(i32), i64, P(i64)],
         "bmpc_factor": [vp, vp, vp, vp, vp],
         "bmpc_solve": [vp, vp, vp],
         "bmpc_refine": [vp, vp, vp, vp, vp, vp, vp, dbl, i32],
@@ -165,9 +170,9 @@ def structure(N: int) -> list:
 
 
 def cost_model(S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
-               window_depth: int = 0, num_systems: int = 1) -> Cost:
+               window_depth: int = 0, num_systems: int = 1, flags: int = 0) -> Cost:
     d = _Dims(S, N, n, nrhs)
-    o = _Options(window_depth, num_systems)
+    o = _Options(window_depth, num_systems, flags)
     c = _Cost()
     _check(lib().bmpc_cost_model(ctypes.byref(d), _prec(precision), ctypes.byref(o),
                                  ctypes.byref(c)), "bmpc_cost_model")
@@ -232,7 +237,7 @@ class Plan:
     along the leading dimension, see include/bmpc.h)."""
 
     def __init__(self, S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
-                 window_depth: int = 0, stream=None, num_systems: int = 1):
+                 window_depth: int = 0, stream=None, num_systems: int = 1, flags: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("bmpc needs a HIP device (torch.cuda.is_available() is False)")
@@ -244,7 +249,7 @@ class Plan:
             stream = torch.cuda.current_stream()
         self._stream = stream
         d = _Dims(self.S, self.N, self.n, self.nrhs)
-        o = _Options(int(window_depth), self.B)
+        o = _Options(int(window_depth), self.B, int(flags))
         _check(lib().bmpc_analyze_ex(ctypes.byref(d), self.precision,
                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
                                      ctypes.byref(self._h)), "bmpc_analyze")
@@ -268,6 +273,13 @@ class Plan:
         self._stream = stream
         _check(lib().bmpc_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)),
                "bmpc_set_stream")
+
+    def set_refine_stop(self, stop):
+        """Stop test of later refine / factor_refine calls: "correction"
+        (|d| <= tol |x|, the default) or "backward_error"
+        (|b - K x| <= tol (|K| |x| + |b|), infinity norms)."""
+        code = {"correction": STOP_CORRECTION, "backward_error": STOP_BACKWARD_ERROR}.get(stop, stop)
+        _check(lib().bmpc_set_refine_stop(self._h, int(code)), "bmpc_set_refine_stop")
 
     def _blocks(self, D, E, C, R):
         import torch
@@ -351,6 +363,17 @@ class Plan:
         buf = (ctypes.c_int32 * self.N)()
         _check(lib().bmpc_query_perm(self._h, buf), "bmpc_query_perm")
         return list(buf)
+
+    def structure(self) -> list:
+        """(row, col) permuted block pairs of one tail's factor plus the root row."""
+        cnt = ctypes.c_int64(0)
+        _check(lib().bmpc_query_structure(self._h, None, None, 0, ctypes.byref(cnt)),
+               "bmpc_query_structure")
+        k = cnt.value
+        rows, cols = (ctypes.c_int32 * k)(), (ctypes.c_int32 * k)()
+        _check(lib().bmpc_query_structure(self._h, rows, cols, k, ctypes.byref(cnt)),
+               "bmpc_query_structure")
+        return list(zip(rows, cols))
 
     def cost(self) -> Cost:
         c = _Cost()

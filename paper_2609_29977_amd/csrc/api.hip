@@ -78,7 +78,7 @@ struct Costs {
   int levels = 0, Tw = 0;
 };
 
-Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B) {
+Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B, bool no_top_merge) {
   Costs c;
   c.Tw = Tw;
   const int S = d.S, N = d.N, n = d.n, m = N - 1;
@@ -156,9 +156,17 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B) {
   c.pass_flops[KC_RESIDUAL_ROOT] = q * 2.0 * ((double)S * nn + nn);
   const int L = chain_levels(m);
   for (int k = 0; k < KC_COUNT; ++k) c.launches[k] = 1;
-  c.launches[KC_SOLVE_FWD] = L;
-  const int top = bwd_top_level(m, n, d.nrhs, S, B);
-  c.launches[KC_SOLVE_BWD] = top <= L ? top : L;  // levels below top, plus one for the rest
+  // the solve and residual classes run once per chunk of right-hand sides
+  const int ck = rhs_chunk(nmax_for(n));
+  const int chunks = (d.nrhs + ck - 1) / ck, last = d.nrhs - (chunks - 1) * ck;
+  for (int k : {KC_SOLVE_X_FWD, KC_SOLVE_ROOT, KC_SOLVE_X_BWD, KC_RESIDUAL, KC_RESIDUAL_ROOT})
+    c.launches[k] = chunks;
+  c.launches[KC_SOLVE_FWD] = L * chunks;
+  auto bwd_launches = [&](int q) {
+    const int top = no_top_merge ? L + 1 : bwd_top_level(m, n, q, S, B);
+    return top <= L ? top : L;  // levels below top, plus one for the rest
+  };
+  c.launches[KC_SOLVE_BWD] = (chunks - 1) * bwd_launches(ck) + bwd_launches(last);
   // a batch of B systems does B times the work in the same launches
   for (PassPlan& pp : c.passes) {
     pp.flops *= B;
@@ -184,7 +192,10 @@ struct bmpc_plan_s {
   bmpc_precision prec = BMPC_FP64;
   bool fp64 = true;
   int m = 0, nmax = 8, Tw = 1, groups = 1;
-  int B = 1;  // systems in the batch
+  int B = 1;      // systems in the batch
+  int opt_flags = 0;  // BMPC_FLAG_*
+  int chunk = kMaxRhs;  // right-hand sides per launch
+  int refine_stop = BMPC_STOP_CORRECTION;
   hipStream_t stream = nullptr;
   Costs costs;
   std::vector<int> perm, permpos;
@@ -211,6 +222,14 @@ struct bmpc_plan_s {
   double* npart = nullptr;  // partial maxima: 2 * nrhs * kNormBlocks
   int* flags = nullptr;     // done, iterations
   double* relcorr = nullptr;
+  // backward-error stop: |b| per segment, |K| per system, the residual's row-sum
+  // partials (per tail workgroup), root-row maxima and per-chain |C_s| row sums
+  double* bnorm = nullptr;
+  double* knorm = nullptr;
+  double* kpart = nullptr;
+  double* kroot = nullptr;
+  double* crow = nullptr;
+  int kper = 0;  // residual workgroups per system
   std::vector<void*> allocs;
   double workspace_bytes = 0;
   bool factored = false;
@@ -265,11 +284,19 @@ void collect_timings(bmpc_plan p) {
   p->timings.clear();
 }
 
+// Right-hand sides per plan: no limit of the method; this bound keeps the per-segment
+// norm arrays and index arithmetic small.
+constexpr int kMaxPlanRhs = 4096;
+
 bool dims_ok(const bmpc_dims* d, int B = 1) {
   return d && d->S >= 1 && d->N >= 1 && d->n >= 1 && d->n <= 32 && d->nrhs >= 1 &&
-         d->nrhs <= kMaxRhs && B >= 1 && (double)B * d->S * d->N * d->n < 2.0e9 &&
-         (double)B * d->S * d->N < 2.0e9 / 64;
+         d->nrhs <= kMaxPlanRhs && B >= 1 && (double)B * d->S * d->N * d->n < 2.0e9 &&
+         (double)B * d->S * d->N < 2.0e9 / 64 &&
+         (double)B * d->nrhs * ((double)d->S * d->N + 1) * d->n < 4.0e9;
 }
+
+int flags_of(const bmpc_options* o) { return o ? o->flags : 0; }
+bool no_top_merge_of(const bmpc_options* o) { return (flags_of(o) & BMPC_FLAG_NO_BWD_TOP_MERGE) != 0; }
 
 int systems_of(const bmpc_options* o) { return (o && o->num_systems > 0) ? o->num_systems : 1; }
 
@@ -300,11 +327,12 @@ bool dalloc(bmpc_plan p, void** ptr, size_t bytes) {
 }
 
 // The LDS of a pass includes the right-hand-side slots of the fused forward
-// substitution for the plan's nrhs, so that path always fits.
+// substitution for one chunk of the plan's right-hand sides, so that path always fits.
 int pick_window_depth(bool fp64, int nmax, int nrhs, const bmpc_options* o) {
   int Tw = (o && o->window_depth > 0) ? o->window_depth : default_window_depth(fp64, nmax);
   Tw = std::min(Tw, kMaxWindowDepth);
-  while (Tw > 1 && factor_pass_lds_bytes(fp64, nmax, Tw, nrhs) > (size_t)kLdsBudget) --Tw;
+  const int q = std::min(nrhs, rhs_chunk(nmax));
+  while (Tw > 1 && factor_pass_lds_bytes(fp64, nmax, Tw, q) > (size_t)kLdsBudget) --Tw;
   return Tw;
 }
 
@@ -313,7 +341,7 @@ int pick_window_depth(bool fp64, int nmax, int nrhs, const bmpc_options* o) {
 // step of the solve leave them).
 template <typename T>
 void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double* C,
-                    const double* R, const double* b = nullptr) {
+                    const double* R, const double* b = nullptr, int nq = 0) {
   const bmpc_dims& d = p->d;
   hipStream_t st = p->stream;
   timed(p, KC_FACTOR_INIT, [&] { launch_factor_init(p->d_info, st); });
@@ -354,7 +382,8 @@ void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double*
     a.info = p->d_info;
     if (b) {
       a.b = b;
-      a.nrhs = d.nrhs;
+      a.nrhs = nq;
+      a.vsys = (size_t)d.nrhs * (((size_t)d.S * d.N + 1) * d.n);
       a.y = p->y;
       a.w = p->w;
       a.vaccR_in = k > 0 ? p->vacc[in][0] : nullptr;
@@ -376,21 +405,29 @@ void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double*
   });
 }
 
-SolveArgs solve_args(bmpc_plan p, const double* b, double* x) {
+size_t vec_len(bmpc_plan p) { return ((size_t)p->d.S * p->d.N + 1) * p->d.n; }
+int chunks_of(bmpc_plan p) { return (p->d.nrhs + p->chunk - 1) / p->chunk; }
+int chunk_rhs(bmpc_plan p, int c) { return std::min(p->chunk, p->d.nrhs - c * p->chunk); }
+
+// Arguments of a solve of the chunk of right-hand sides starting at q0 (nq of them).
+SolveArgs solve_args(bmpc_plan p, const double* b, double* x, int q0, int nq) {
   SolveArgs a{};
+  const size_t off = (size_t)q0 * vec_len(p);
   a.S = p->d.S;
   a.B = p->B;
   a.N = p->d.N;
   a.n = p->d.n;
   a.m = p->m;
-  a.nrhs = p->d.nrhs;
+  a.nrhs = nq;
+  a.vsys = (size_t)p->d.nrhs * vec_len(p);
+  a.seg_sys = p->d.nrhs;
   a.Linv = p->Linv;
   a.Gl = p->Gl;
   a.Gr = p->Gr;
   a.F = p->F;
   a.LR = p->LR;
-  a.b = b;
-  a.x = x;
+  a.b = b + off;
+  a.x = x + off;
   a.y = p->y;
   a.w = p->w;
   a.x0 = p->x0;
@@ -406,20 +443,47 @@ void enqueue_solve_back(bmpc_plan p, const SolveArgs& a) {
   timed(p, KC_SOLVE_ROOT, [&] { launch_solve_root(a, st); });
   timed(p, KC_SOLVE_X_BWD, [&] { launch_solve_x_bwd<T>(a, p->nmax, st); });
   // the top levels (few positions per chain) in one launch, the others one by one
-  const int top = bwd_top_level(p->m, p->d.n, p->d.nrhs, p->d.S, p->B);
+  const int top = (p->opt_flags & BMPC_FLAG_NO_BWD_TOP_MERGE)
+                      ? L + 1
+                      : bwd_top_level(p->m, p->d.n, a.nrhs, p->d.S, p->B);
   if (top <= L) timed(p, KC_SOLVE_BWD, [&] { launch_solve_bwd_top<T>(a, top, st); });
   for (int l = std::min(L, top - 1); l >= 1; --l)
     timed(p, KC_SOLVE_BWD, [&] { launch_solve_bwd_level<T>(a, l, p->nmax, st); });
 }
 
 template <typename T>
-void enqueue_solve(bmpc_plan p, const SolveArgs& a) {
+void enqueue_solve_chunk(bmpc_plan p, const SolveArgs& a) {
   hipStream_t st = p->stream;
   const int L = chain_levels(p->m);
   for (int l = 1; l <= L; ++l)
     timed(p, KC_SOLVE_FWD, [&] { launch_solve_fwd_level<T>(a, l, p->nmax, st); });
   timed(p, KC_SOLVE_X_FWD, [&] { launch_solve_x_fwd<T>(a, p->nmax, st); });
   enqueue_solve_back<T>(p, a);
+}
+
+// Algorithm 2 for every chunk of right-hand sides in turn (the scratch y, w, x0 is
+// sized for one chunk); mod adjusts each chunk's arguments (refinement scaling).
+template <typename T, typename Mod>
+void enqueue_solve(bmpc_plan p, const double* b, double* x, int first_chunk, Mod mod) {
+  for (int c = first_chunk; c < chunks_of(p); ++c) {
+    SolveArgs a = solve_args(p, b, x, c * p->chunk, chunk_rhs(p, c));
+    mod(a, c * p->chunk);
+    enqueue_solve_chunk<T>(p, a);
+  }
+}
+template <typename T>
+void enqueue_solve(bmpc_plan p, const double* b, double* x, int first_chunk = 0) {
+  enqueue_solve<T>(p, b, x, first_chunk, [](SolveArgs&, int) {});
+}
+
+// Factor, then the whole solve of b into x with the first chunk's forward substitution
+// inside the factorization.
+template <typename T>
+void enqueue_factor_solve(bmpc_plan p, const double* D, const double* E, const double* C,
+                          const double* R, const double* b, double* x) {
+  enqueue_factor<T>(p, D, E, C, R, b, chunk_rhs(p, 0));
+  enqueue_solve_back<T>(p, solve_args(p, b, x, 0, chunk_rhs(p, 0)));
+  enqueue_solve<T>(p, b, x, 1);
 }
 
 bmpc_status last_error_status() {
@@ -481,7 +545,7 @@ bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
     return BMPC_ERR_INVALID;
   const bool fp64 = prec == BMPC_FP64;
   const int Tw = pick_window_depth(fp64, nmax_for(dims->n), dims->nrhs, opts);
-  Costs c = make_costs(*dims, fp64, Tw, systems_of(opts));
+  Costs c = make_costs(*dims, fp64, Tw, systems_of(opts), no_top_merge_of(opts));
   std::memset(cost, 0, sizeof(*cost));
   cost->factor_flops = c.factor_flops;
   cost->solve_flops = c.solve_flops;
@@ -511,16 +575,21 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
   p->nmax = nmax_for(dims->n);
   p->Tw = pick_window_depth(p->fp64, p->nmax, dims->nrhs, opts);
   p->B = systems_of(opts);
+  p->opt_flags = flags_of(opts);
+  p->chunk = rhs_chunk(p->nmax);
   p->stream = reinterpret_cast<hipStream_t>(stream);
-  p->costs = make_costs(*dims, p->fp64, p->Tw, p->B);
+  p->costs = make_costs(*dims, p->fp64, p->Tw, p->B, no_top_merge_of(opts));
   p->perm = make_perm(dims->N);
   p->permpos = make_permpos(dims->N);
   p->groups = std::min(dims->S, 32);
   const int B = p->B, N = dims->N, n = dims->n, nrhs = dims->nrhs;
+  const int cq = std::min(nrhs, p->chunk);  // right-hand sides of one chunk
   const size_t S = (size_t)B * dims->S;  // chains of the batch
   const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
   const size_t len = ((size_t)dims->S * N + 1) * n;
   const size_t segs = (size_t)B * nrhs;  // (system, right-hand side) vectors
+  const int res_chunks = (N + 15) / 16;   // tail residual workgroups per chain
+  p->kper = dims->S * res_chunks;
   const int npass = (int)p->costs.passes.size();
   p->stride = (npass > 1 ? p->costs.passes[0].windows : 1) + 1;
   const size_t gblocks = g_chain_blocks(N);
@@ -532,23 +601,28 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
             dalloc(p, (void**)&p->Upart, (size_t)B * p->groups * nn * 8) &&
             dalloc(p, (void**)&p->LR, (size_t)B * nn * 8) &&
             dalloc(p, &p->accX, S * npass * nn * tb) &&
-            dalloc(p, &p->vaccX, S * npass * nrhs * n * tb) &&
+            dalloc(p, &p->vaccX, S * npass * cq * n * tb) &&
             dalloc(p, (void**)&p->d_permpos, (size_t)N * sizeof(int)) &&
             dalloc(p, (void**)&p->d_info, sizeof(unsigned long long)) &&
-            dalloc(p, &p->y, S * N * nrhs * n * tb) &&
-            dalloc(p, (void**)&p->w, S * nrhs * n * 8) &&
-            dalloc(p, (void**)&p->x0, segs * n * 8) &&
+            dalloc(p, &p->y, S * N * cq * n * tb) &&
+            dalloc(p, (void**)&p->w, S * cq * n * 8) &&
+            dalloc(p, (void**)&p->x0, (size_t)B * cq * n * 8) &&
             dalloc(p, (void**)&p->rbuf, segs * len * 8) &&
             dalloc(p, (void**)&p->norms, 3 * segs * 8) &&
             dalloc(p, (void**)&p->npart, 2 * segs * kNormBlocks * 8) &&
             dalloc(p, (void**)&p->flags, 2 * sizeof(int)) &&
-            dalloc(p, (void**)&p->relcorr, sizeof(double));
+            dalloc(p, (void**)&p->relcorr, sizeof(double)) &&
+            dalloc(p, (void**)&p->bnorm, segs * 8) &&
+            dalloc(p, (void**)&p->knorm, (size_t)B * 8) &&
+            dalloc(p, (void**)&p->kpart, S * res_chunks * 8) &&
+            dalloc(p, (void**)&p->kroot, (size_t)B * 8) &&
+            dalloc(p, (void**)&p->crow, S * n * 8);
   if (ok && npass > 1) {
     for (int set = 0; set < 2 && ok; ++set) {
       for (int b = 0; b < 3 && ok; ++b)
         ok = dalloc(p, &p->acc[set][b], S * p->stride * nn * tb);
       for (int b = 0; b < 2 && ok; ++b)
-        ok = dalloc(p, &p->vacc[set][b], S * p->stride * nrhs * n * tb);
+        ok = dalloc(p, &p->vacc[set][b], S * p->stride * cq * n * tb);
     }
   }
   if (!ok) {
@@ -593,86 +667,121 @@ bmpc_status bmpc_factor(bmpc_plan p, const double* D, const double* E, const dou
 bmpc_status bmpc_solve(bmpc_plan p, const double* b, double* x) {
   if (!p || !b || !x) return BMPC_ERR_INVALID;
   if (!p->factored) return BMPC_ERR_STATE;
-  SolveArgs a = solve_args(p, b, x);
   if (p->fp64)
-    enqueue_solve<double>(p, a);
+    enqueue_solve<double>(p, b, x);
   else
-    enqueue_solve<float>(p, a);
+    enqueue_solve<float>(p, b, x);
   return last_error_status();
 }
 
 // x = K^{-1} b by refinement (see bmpc_refine); with fused, the factor is issued here
-// and the first solve's forward part runs inside it.
+// and the first solve's forward part (first chunk of right-hand sides) runs inside it.
 static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, const double* C,
-                        const double* R, const double* b, double* x, double tol,
-                        int32_t max_iters, bool fused) {
+                               const double* R, const double* b, double* x, double tol,
+                               int32_t max_iters, bool fused) {
   if (!p || !D || !C || !R || !b || !x || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
   if (max_iters < 0 || max_iters > 100 || !(tol >= 0.0) || x == b) return BMPC_ERR_INVALID;
   if (!fused && !p->factored) return BMPC_ERR_STATE;
   hipStream_t st = p->stream;
   const int nrhs = p->d.nrhs;
   const int segs = p->B * nrhs;  // norms per (system, right-hand side)
-  const size_t len = ((size_t)p->d.S * p->d.N + 1) * p->d.n;
+  const size_t len = vec_len(p);
+  const bool be = p->refine_stop == BMPC_STOP_BACKWARD_ERROR;
   double* rnorm = p->norms;
   double* dnorm = p->norms + segs;
   double* xnorm = p->norms + 2 * segs;
   timed(p, KC_REFINE_MISC, [&] { launch_refine_reset(p->flags, st); });
-  SolveArgs a = solve_args(p, b, x);
   if (fused) {
     if (p->fp64)
-      enqueue_factor<double>(p, D, E, C, R, b);
+      enqueue_factor_solve<double>(p, D, E, C, R, b, x);
     else
-      enqueue_factor<float>(p, D, E, C, R, b);
+      enqueue_factor_solve<float>(p, D, E, C, R, b, x);
     if (last_error_status() != BMPC_OK) return BMPC_ERR_DEVICE;
     p->factored = true;
-    if (p->fp64)
-      enqueue_solve_back<double>(p, a);
-    else
-      enqueue_solve_back<float>(p, a);
   } else {
     if (p->fp64)
-      enqueue_solve<double>(p, a);
+      enqueue_solve<double>(p, b, x);
     else
-      enqueue_solve<float>(p, a);
+      enqueue_solve<float>(p, b, x);
   }
-  ResidualArgs ra{};
-  ra.S = p->d.S;
-  ra.B = p->B;
-  ra.N = p->d.N;
-  ra.n = p->d.n;
-  ra.nrhs = nrhs;
-  ra.chunk = 16;
-  ra.D = D;
-  ra.E = E;
-  ra.C = C;
-  ra.R = R;
-  ra.b = b;
-  ra.x = x;
-  ra.r = p->rbuf;
-  ra.w = p->w;
-  ra.done = p->flags;
+  if (be && max_iters >= 0)
+    timed(p, KC_REFINE_MISC, [&] { launch_maxabs(b, segs, len, p->npart, p->bnorm, nullptr, st); });
+  // r = b - K x for every chunk; the first residual of a backward-error loop also takes
+  // the row sums of |K|
+  auto residual = [&](bool knorm) {
+    for (int c = 0; c < chunks_of(p); ++c) {
+      const size_t off = (size_t)c * p->chunk * len;
+      ResidualArgs ra{};
+      ra.S = p->d.S;
+      ra.B = p->B;
+      ra.N = p->d.N;
+      ra.n = p->d.n;
+      ra.nrhs = chunk_rhs(p, c);
+      ra.vsys = (size_t)nrhs * len;
+      ra.chunk = 16;
+      ra.D = D;
+      ra.E = E;
+      ra.C = C;
+      ra.R = R;
+      ra.b = b + off;
+      ra.x = x + off;
+      ra.r = p->rbuf + off;
+      ra.w = p->w;
+      ra.done = p->flags;
+      if (knorm && c == 0) {
+        ra.knorm_part = p->kpart;
+        ra.knorm_root = p->kroot;
+        ra.crow = p->crow;
+      }
+      timed(p, KC_RESIDUAL, [&] { launch_residual(ra, p->nmax, st); });
+      timed(p, KC_RESIDUAL_ROOT, [&] { launch_residual_root(ra, st); });
+    }
+  };
   // correction solve: reads r / |r|, adds |r| d to x and keeps |r| d in place of r
-  SolveArgs c = solve_args(p, p->rbuf, x);
-  c.rnorm = rnorm;
-  c.dstore = p->rbuf;
-  c.done = p->flags;
-  c.accumulate = 1;
-  for (int it = 0; it < max_iters; ++it) {
-    timed(p, KC_RESIDUAL, [&] { launch_residual(ra, p->nmax, st); });
-    timed(p, KC_RESIDUAL_ROOT, [&] { launch_residual_root(ra, st); });
-    timed(p, KC_REFINE_MISC, [&] {
-      launch_maxabs(p->rbuf, segs, len, p->npart, rnorm, p->flags, st);
-    });
+  auto correction = [&] {
+    auto mod = [&](SolveArgs& c, int q0) {
+      c.rnorm = rnorm + q0;
+      c.dstore = p->rbuf + (size_t)q0 * len;
+      c.done = p->flags;
+      c.accumulate = 1;
+    };
     if (p->fp64)
-      enqueue_solve<double>(p, c);
+      enqueue_solve<double>(p, p->rbuf, x, 0, mod);
     else
-      enqueue_solve<float>(p, c);
+      enqueue_solve<float>(p, p->rbuf, x, 0, mod);
+  };
+  for (int it = 0; it < max_iters; ++it) {
+    residual(be && it == 0);
+    if (be) {
+      // stop before the correction when x is already backward stable
+      timed(p, KC_REFINE_MISC, [&] {
+        launch_refine_be_check(p->rbuf, x, p->B, nrhs, len, p->npart, it == 0 ? p->kpart : nullptr,
+                               p->kper, p->kroot, p->knorm, p->bnorm, tol, 1, p->flags,
+                               p->relcorr, rnorm, st);
+      });
+    } else {
+      timed(p, KC_REFINE_MISC, [&] {
+        launch_maxabs(p->rbuf, segs, len, p->npart, rnorm, p->flags, st);
+      });
+    }
+    correction();
+    if (!be) {
+      timed(p, KC_REFINE_MISC, [&] {
+        launch_refine_check(p->rbuf, x, segs, len, p->npart, tol, p->flags, p->relcorr, dnorm,
+                            xnorm, st);
+      });
+    }
+  }
+  if (be) {
+    // the returned x is certified by its own residual
+    residual(max_iters == 0);
     timed(p, KC_REFINE_MISC, [&] {
-      launch_refine_check(p->rbuf, x, segs, len, p->npart, tol, p->flags, p->relcorr, dnorm,
-                          xnorm, st);
+      launch_refine_be_check(p->rbuf, x, p->B, nrhs, len, p->npart,
+                             max_iters == 0 ? p->kpart : nullptr, p->kper, p->kroot, p->knorm,
+                             p->bnorm, tol, 0, p->flags, p->relcorr, rnorm, st);
     });
   }
-  p->last_max_iters = max_iters;
+  p->last_max_iters = be ? std::max(max_iters, 1) : max_iters;
   return last_error_status();
 }
 
@@ -692,18 +801,25 @@ bmpc_status bmpc_factor_solve(bmpc_plan p, const double* D, const double* E, con
                               const double* R, const double* b, double* x) {
   if (!p || !D || !C || !R || !b || !x || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
   if (p->fp64)
-    enqueue_factor<double>(p, D, E, C, R, b);
+    enqueue_factor_solve<double>(p, D, E, C, R, b, x);
   else
-    enqueue_factor<float>(p, D, E, C, R, b);
-  bmpc_status st = last_error_status();
-  if (st != BMPC_OK) return st;
-  p->factored = true;
-  SolveArgs a = solve_args(p, b, x);
-  if (p->fp64)
-    enqueue_solve_back<double>(p, a);
-  else
-    enqueue_solve_back<float>(p, a);
-  return last_error_status();
+    enqueue_factor_solve<float>(p, D, E, C, R, b, x);
+  const bmpc_status st = last_error_status();
+  if (st == BMPC_OK) p->factored = true;
+  return st;
+}
+
+bmpc_status bmpc_set_refine_stop(bmpc_plan p, int32_t stop) {
+  if (!p || (stop != BMPC_STOP_CORRECTION && stop != BMPC_STOP_BACKWARD_ERROR))
+    return BMPC_ERR_INVALID;
+  p->refine_stop = stop;
+  return BMPC_OK;
+}
+
+bmpc_status bmpc_query_structure(bmpc_plan p, int32_t* rows, int32_t* cols, int64_t cap,
+                                 int64_t* count) {
+  if (!p) return BMPC_ERR_INVALID;
+  return bmpc_structure(p->d.N, rows, cols, cap, count);
 }
 
 bmpc_status bmpc_grad_blocks(bmpc_plan p, const double* x, const double* lam, double* dD,

@@ -27,7 +27,12 @@ namespace bmpc {
 
 constexpr int kFactorThreads = 256;
 constexpr int kSolveThreads = 64;
+// Right-hand sides per kernel launch: the solve, the fused forward substitution and the
+// residual take them in chunks of at most kMaxRhs (kMaxRhs64 at n > 32, where the
+// residual's LDS holds fewer vectors); a plan's nrhs has no such limit.
 constexpr int kMaxRhs = 8;
+constexpr int kMaxRhs64 = 4;
+inline __host__ __device__ int rhs_chunk(int nmax) { return nmax > 32 ? kMaxRhs64 : kMaxRhs; }
 
 // Blocks per chain in the G_l and G_r arrays: the N-1 blocks of the positions 1..N-1,
 // padded to N so that every factor array (L^{-1} has N) shares one chain stride; the
@@ -92,8 +97,9 @@ struct FactorPassArgs {
   // receives L^{-1} Pi b per chain position ([S][N][nrhs][n], precision T) and w the
   // FP64 products F_s y_X ([S][nrhs][n]).  The vector accumulators mirror accR /
   // accL / accX per right-hand side ([S][stride][nrhs][n] and [S][npass][nrhs][n]).
-  const double* b;
-  int nrhs;
+  const double* b;       // right-hand side q = 0 of this chunk (b + q0 * len)
+  int nrhs;              // right-hand sides of this chunk
+  size_t vsys;           // vector elements per system (all right-hand sides)
   void* y;
   double* w;
   const void* vaccR_in;
@@ -103,9 +109,15 @@ struct FactorPassArgs {
   void* vaccX;
 };
 
+// Vectors b, x, r are [B][nrhs][len]; a launch takes a chunk of the right-hand sides:
+// its pointers are those of the chunk's first right-hand side in system 0 (offset by
+// q0 * len), nrhs counts the chunk, vsys = (all right-hand sides) * len is the stride
+// between systems and seg_sys the stride of the per-(system, right-hand side) norms.
 struct SolveArgs {
-  int S, N, n, m, nrhs;  // S = scenarios per system
+  int S, N, n, m, nrhs;  // S = scenarios per system, nrhs of this chunk
   int B;                 // systems in the batch
+  size_t vsys;           // vector elements per system
+  int seg_sys;           // norm entries per system
   const void* Linv;
   const void* Gl;
   const void* Gr;
@@ -123,8 +135,9 @@ struct SolveArgs {
 };
 
 struct ResidualArgs {
-  int S, N, n, nrhs;     // S = scenarios per system
+  int S, N, n, nrhs;     // S = scenarios per system, nrhs of this chunk
   int B;                 // systems in the batch
+  size_t vsys;           // vector elements per system (all right-hand sides)
   int chunk;             // stages per work item of the tail residual
   const double* D;
   const double* E;
@@ -135,10 +148,17 @@ struct ResidualArgs {
   double* r;             // [B][nrhs][len]
   double* w;             // [S][nrhs][n] products C_s x_{s,0}
   const int* done;
+  // Row sums of |K| (backward-error stop): per workgroup of the tail residual the
+  // maximum over its rows (knorm_part[blockIdx]), per system the maximum over the
+  // root rows (knorm_root[sys]) and the per-chain |C_s| row sums (crow [B*S][n]).
+  // Null: not computed.
+  double* knorm_part;
+  double* knorm_root;
+  double* crow;
 };
 
 struct GradArgs {
-  int S, N, n, nrhs;     // S = scenarios per system
+  int S, N, n, nrhs;     // S = scenarios per system, all right-hand sides
   int B;                 // systems in the batch
   const double* x;       // [nrhs][len] solution
   const double* lam;     // [nrhs][len] adjoint K^{-1} g
@@ -191,6 +211,17 @@ void launch_maxabs(const double* v, int nrhs, size_t len, double* partial, doubl
 void launch_refine_check(const double* d, const double* x, int nrhs, size_t len,
                          double* partial, double tol, int* flags, double* relcorr,
                          double* dnorm, double* xnorm, hipStream_t st);
+
+// Backward-error stop test after a residual r = b - K x of B systems with nrhs
+// right-hand sides each (see refine_be_check_kernel): |r| and |x| by block partials,
+// |K| per system reduced from the residual's row-sum partials when kpart is not null
+// (kper partials per system), |b| from bnorm.  Sets flags[0] when every normwise
+// backward error is <= tol, else counts a correction (flags[1]) if count; |r| into rnorm.
+void launch_refine_be_check(const double* r, const double* x, int B, int nrhs, size_t len,
+                            double* partial, const double* kpart, int kper,
+                            const double* kroot, double* knorm, const double* bnorm,
+                            double tol, int count, int* flags, double* relcorr, double* rnorm,
+                            hipStream_t st);
 
 // number of chain positions eliminated at level l (1-based) of a chain of length m
 __host__ __device__ inline int level_count(int m, int l) {

@@ -551,7 +551,7 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
   VecChain<T> vc{};
   if constexpr (FWD) {
     vc.len = ((size_t)a.Ssys * N + 1) * n;
-    vc.b = a.b + (size_t)sys * a.nrhs * vc.len + (size_t)(s - sys * a.Ssys) * N * n;
+    vc.b = a.b + (size_t)sys * a.vsys + (size_t)(s - sys * a.Ssys) * N * n;
     if constexpr (!FIRST) {
       const size_t vo = (size_t)s * a.stride * a.nrhs * n;
       vc.vR = reinterpret_cast<const T*>(a.vaccR_in) + vo;
@@ -808,7 +808,7 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
       const int nr = a.nrhs;
       const int sys_ = s / a.Ssys, sc = s - sys_ * a.Ssys;
       const size_t len = ((size_t)a.Ssys * N + 1) * n;
-      const size_t offx = (size_t)sys_ * nr * len + (size_t)sc * N * n;
+      const size_t offx = (size_t)sys_ * a.vsys + (size_t)sc * N * n;
       const size_t vs = (size_t)nr * n;
       T* Vx = sl.Y();
       for (int idx = threadIdx.x; idx < nr * NMAX; idx += NT) {

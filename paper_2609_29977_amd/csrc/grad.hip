@@ -16,10 +16,13 @@ namespace bmpc {
 namespace {
 
 constexpr int GT = 256;
+constexpr int GQ = 8;                // right-hand sides staged per round
+constexpr int GN = 64;               // largest block size
+constexpr int EPT = GN * GN / GT;    // output elements per thread
 
 __global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a) {
-  __shared__ double xs[kMaxRhs][3][32];  // x of stage k, stage k+1, root
-  __shared__ double ls[kMaxRhs][3][32];  // lam of the same
+  __shared__ double xs[GQ][3][GN];  // x of stage k, stage k+1, root
+  __shared__ double ls[GQ][3][GN];  // lam of the same
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
   const size_t nn = (size_t)n * n;
   const size_t len = ((size_t)S * N + 1) * n;
@@ -32,49 +35,58 @@ __global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a) {
   const int sl = s - (s / S) * S;
   const size_t vbase = (size_t)sys * nrhs * len;
   const size_t root = vbase + (size_t)S * N * n;
-  for (int idx = threadIdx.x; idx < nrhs * 3 * n; idx += GT) {
-    const int q = idx / (3 * n), rem = idx - q * 3 * n, w = rem / n, i = rem - w * n;
-    size_t off;
-    bool ok = true;
-    if (w == 2) {
-      off = root + i;
-    } else {
-      const int st = k + w;
-      ok = !is_root && st < N;
-      off = vbase + ((size_t)sl * N + (ok ? st : 0)) * n + i;
+  // sums over the right-hand sides, GQ of them staged at a time: d0 (dD or dR),
+  // dE, dC for this thread's elements e = threadIdx.x + t * GT
+  double d0[EPT], dE[EPT], dC[EPT];
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) d0[t] = dE[t] = dC[t] = 0.0;
+  for (int q0 = 0; q0 < nrhs; q0 += GQ) {
+    const int nq = min(GQ, nrhs - q0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nq * 3 * n; idx += GT) {
+      const int q = idx / (3 * n), rem = idx - q * 3 * n, w = rem / n, i = rem - w * n;
+      size_t off;
+      bool ok = true;
+      if (w == 2) {
+        off = root + i;
+      } else {
+        const int st = k + w;
+        ok = !is_root && st < N;
+        off = vbase + ((size_t)sl * N + (ok ? st : 0)) * n + i;
+      }
+      const size_t qo = (size_t)(q0 + q) * len + off;
+      xs[q][w][i] = ok ? a.x[qo] : 0.0;
+      ls[q][w][i] = ok ? a.lam[qo] : 0.0;
     }
-    xs[q][w][i] = ok ? a.x[(size_t)q * len + off] : 0.0;
-    ls[q][w][i] = ok ? a.lam[(size_t)q * len + off] : 0.0;
-  }
-  __syncthreads();
-  if (is_root) {
-    if (!a.dR) return;
-    for (int e = threadIdx.x; e < n * n; e += GT) {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < EPT; ++t) {
+      const int e = threadIdx.x + t * GT;
+      if (e >= n * n) continue;
       const int r = e / n, c = e - r * n;
-      double acc = 0.0;
-      for (int q = 0; q < nrhs; ++q) acc += ls[q][2][r] * xs[q][2][c] + ls[q][2][c] * xs[q][2][r];
-      a.dR[(size_t)sys * nn + e] = -0.5 * acc;
+      if (is_root) {
+        for (int q = 0; q < nq; ++q) d0[t] += ls[q][2][r] * xs[q][2][c] + ls[q][2][c] * xs[q][2][r];
+      } else {
+        for (int q = 0; q < nq; ++q) {
+          d0[t] += ls[q][0][r] * xs[q][0][c] + ls[q][0][c] * xs[q][0][r];
+          dE[t] += ls[q][1][r] * xs[q][0][c] + xs[q][1][r] * ls[q][0][c];
+          dC[t] += ls[q][2][r] * xs[q][0][c] + xs[q][2][r] * ls[q][0][c];
+        }
+      }
     }
-    return;
   }
   const size_t blk = (size_t)s * N + k;
-  for (int e = threadIdx.x; e < n * n; e += GT) {
-    const int r = e / n, c = e - r * n;
-    if (a.dD) {
-      double acc = 0.0;
-      for (int q = 0; q < nrhs; ++q) acc += ls[q][0][r] * xs[q][0][c] + ls[q][0][c] * xs[q][0][r];
-      a.dD[blk * nn + e] = -0.5 * acc;
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) {
+    const int e = threadIdx.x + t * GT;
+    if (e >= n * n) continue;
+    if (is_root) {
+      if (a.dR) a.dR[(size_t)sys * nn + e] = -0.5 * d0[t];
+      continue;
     }
-    if (a.dE && k + 1 < N) {
-      double acc = 0.0;
-      for (int q = 0; q < nrhs; ++q) acc += ls[q][1][r] * xs[q][0][c] + xs[q][1][r] * ls[q][0][c];
-      a.dE[((size_t)s * (N - 1) + k) * nn + e] = -acc;
-    }
-    if (a.dC && k == 0) {
-      double acc = 0.0;
-      for (int q = 0; q < nrhs; ++q) acc += ls[q][2][r] * xs[q][0][c] + xs[q][2][r] * ls[q][0][c];
-      a.dC[(size_t)s * nn + e] = -acc;
-    }
+    if (a.dD) a.dD[blk * nn + e] = -0.5 * d0[t];
+    if (a.dE && k + 1 < N) a.dE[((size_t)s * (N - 1) + k) * nn + e] = -dE[t];
+    if (a.dC && k == 0) a.dC[(size_t)s * nn + e] = -dC[t];
   }
 }
 

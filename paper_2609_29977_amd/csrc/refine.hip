@@ -135,13 +135,14 @@ __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chu
   const int s = blockIdx.x / chunks;  // chain of the batch
   const int ch = blockIdx.x - s * chunks;
   const int sys = s / S, sl = s - sys * S;
-  const size_t vbase = (size_t)sys * nrhs * len;
+  const size_t vbase = (size_t)sys * a.vsys;
   const size_t xk = vbase + (size_t)sl * N * n;  // stage 0 of this chain, q = 0
   const int k0 = ch * a.chunk, k1 = min(N, k0 + a.chunk);
   const double* Dc = a.D + (size_t)s * N * nn;
   const double* Ec = a.E + (size_t)s * (N > 1 ? N - 1 : 0) * nn;
   const int t = threadIdx.x, orow = t / RT, p = t - orow * RT;
   const int o = orow < NMAX ? orow : 0;  // rows past NMAX (NMAX = 8) compute row 0, unused
+  double kmax = 0.0;  // largest row sum of |K| over this workgroup's rows (knorm_part)
 
   // Prologue: stage k0 with x_{k0+1} and b_{k0}, E_{k0-1} (or C_s at k0 = 0), x_{k0-1},
   // x_{k0} and (k0 = 0) the root x, all straight into LDS.
@@ -206,6 +207,29 @@ __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chu
           if (p == 0 && orow < NMAX) ws[q * NMAX + o] = accw;
         }
       }
+      if (a.knorm_part) {
+        // row sums of |K| over the same entries (independent of the right-hand side):
+        // the largest one goes into the norm; at stage 0 the rows of |C_s| are kept for
+        // the root rows (zero padding adds nothing)
+        double ab = 0.0, abc = 0.0;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+          const int c = p * CPT + u;
+          ab += fabs(c <= o ? D[o * LD + c] : D[c * LD + o]);
+          if (has_prev) ab += fabs(Ep[o * LD + c]);
+          if (has_next) ab += fabs(Ek[c * LD + o]);
+          if (!has_prev) {
+            ab += fabs(Ep[c * LD + o]);
+            abc += fabs(Ep[o * LD + c]);
+          }
+        }
+        ab = lane_group_sum_dpp<RT>(ab);
+        kmax = fmax(kmax, ab);
+        if (!has_prev) {
+          abc = lane_group_sum_dpp<RT>(abc);
+          if (p == 0 && orow < n) a.crow[(size_t)s * n + o] = abc;
+        }
+      }
     }
     __syncthreads();
     f.commit(a, k + 1, Ds + ((k + 1) & 1) * BS, Es + ((k + 1) & 1) * BS,
@@ -221,6 +245,17 @@ __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chu
     step(k, fa);
     step(k + 1, fb);
   }
+  if (a.knorm_part) {
+    __shared__ double wmax[RES_T / 64];
+    for (int off = 32; off > 0; off >>= 1) kmax = fmax(kmax, __shfl_xor(kmax, off));
+    if ((t & 63) == 0) wmax[t >> 6] = kmax;
+    __syncthreads();
+    if (t == 0) {
+      double m = 0.0;
+      for (int i = 0; i < RES_T / 64; ++i) m = fmax(m, wmax[i]);
+      a.knorm_part[blockIdx.x] = m;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
@@ -229,7 +264,7 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
   const int sys = blockIdx.x;  // one workgroup per system
   const size_t len = ((size_t)S * N + 1) * n;
-  const size_t root = (size_t)sys * nrhs * len + (size_t)S * N * n;
+  const size_t root = (size_t)sys * a.vsys + (size_t)S * N * n;
   const double* w = a.w + (size_t)sys * S * nrhs * n;
   const double* R = a.R + (size_t)sys * n * n;
   const int t = threadIdx.x, i = t & 31, g = t >> 5;
@@ -262,6 +297,19 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
       a.r[(size_t)q * len + root + row] = a.b[(size_t)q * len + root + row] - rx - sum;
     }
     __syncthreads();
+  }
+  if (a.knorm_root) {
+    // root rows of |K|: |C_s| rows summed over the scenarios in order, plus |R|
+    double m = 0.0;
+    if (t < n) {
+      const double* cr = a.crow + (size_t)sys * S * n;
+      double acc = 0.0;
+      for (int sc = 0; sc < S; ++sc) acc += cr[(size_t)sc * n + t];
+      for (int c = 0; c < n; ++c) acc += fabs(t >= c ? R[t * n + c] : R[c * n + t]);
+      m = acc;
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (t == 0) a.knorm_root[sys] = m;  // n <= 64: the rows sit in wave 0
   }
 }
 
@@ -362,7 +410,73 @@ __global__ void __launch_bounds__(64) refine_check_kernel(const double* partial,
   }
 }
 
+// Backward-error stop test (one workgroup).  For every system sys and right-hand side q
+// (segment sys * nrhs + q): |r|_inf and |x|_inf from the block partials of
+// maxabs_partial_kernel (partial[0] over r, partial[1] over x), |b|_inf from bnorm and
+// |K|_inf of the system (reduced here from the residual's per-workgroup row-sum maxima
+// and its root rows when kpart is not null, kept in knorm); then
+// eta = |r| / (|K| |x| + |b|), the normwise backward error of x.  The loop is done
+// (flags[0] = 1) when eta <= tol for every segment; otherwise flags[1] counts one more
+// correction if count is set.  rnorm receives |r| for the correction solve, relcorr the
+// largest eta.
+__global__ void __launch_bounds__(256) refine_be_check_kernel(
+    const double* partial, int blocks, int B, int nrhs, const double* kpart, int kper,
+    const double* kroot, double* knorm, const double* bnorm, double tol, int count, int* flags,
+    double* relcorr, double* rnorm) {
+  if (flags[0]) return;
+  __shared__ double sh[4];
+  const int segs = B * nrhs;
+  bool ok = true;
+  double worst = 0.0;
+  for (int sys = 0; sys < B; ++sys) {
+    if (kpart) {
+      double m = 0.0;
+      for (int i = threadIdx.x; i < kper; i += blockDim.x) m = nan_max(kpart[(size_t)sys * kper + i], m);
+      m = block_max(m, sh);
+      if (threadIdx.x == 0) knorm[sys] = nan_max(m, kroot[sys]);
+      __syncthreads();
+    }
+    const double kn = knorm[sys];
+    for (int q = 0; q < nrhs; ++q) {
+      const int seg = sys * nrhs + q;
+      double mr = 0.0, mx = 0.0;
+      for (int i = threadIdx.x; i < blocks; i += blockDim.x) {
+        mr = nan_max(partial[(size_t)seg * blocks + i], mr);
+        mx = nan_max(partial[((size_t)segs + seg) * blocks + i], mx);
+      }
+      mr = block_max(mr, sh);
+      mx = block_max(mx, sh);
+      if (threadIdx.x == 0) {
+        const double den = kn * mx + bnorm[seg];
+        const double eta = den > 0.0 ? mr / den : (mr > 0.0 ? HUGE_VAL : 0.0);
+        worst = nan_max(worst, eta);
+        if (!(eta <= tol)) ok = false;
+        rnorm[seg] = mr;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    *relcorr = worst;
+    if (ok)
+      flags[0] = 1;
+    else if (count)
+      flags[1] += 1;
+  }
+}
+
 }  // namespace
+
+void launch_refine_be_check(const double* r, const double* x, int B, int nrhs, size_t len,
+                            double* partial, const double* kpart, int kper,
+                            const double* kroot, double* knorm, const double* bnorm,
+                            double tol, int count, int* flags, double* relcorr, double* rnorm,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(maxabs_partial_kernel, dim3(kNormBlocks), dim3(256), 0, st, r, x, B * nrhs,
+                     len, partial, (const int*)flags);
+  hipLaunchKernelGGL(refine_be_check_kernel, dim3(1), dim3(256), 0, st, (const double*)partial,
+                     kNormBlocks, B, nrhs, kpart, kper, kroot, knorm, bnorm, tol, count, flags,
+                     relcorr, rnorm);
+}
 
 template <int NMAX>
 static void launch_residual_t(const ResidualArgs& a, dim3 grid, int chunks, hipStream_t st) {

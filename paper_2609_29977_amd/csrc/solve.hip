@@ -27,15 +27,16 @@ namespace {
 constexpr int NT = kSolveThreads;
 
 // Vectors b, x, r are [B][nrhs][len], len = (S*N+1)*n: system sys, right-hand side q
-// starts at (sys*nrhs + q)*len, its tails in stage order, its root last.  Chain g of
-// the batch (0 <= g < B*S) is scenario g % S of system g / S.  vec_off gives the
-// offset of (chain g, q = 0, stage); seg_of the first norm index (sys*nrhs) of g.
+// of the launch's chunk starts at sys*vsys + q*len (the pointers are offset to the
+// chunk), its tails in stage order, its root last.  Chain g of the batch
+// (0 <= g < B*S) is scenario g % S of system g / S.  vec_off gives the offset of
+// (chain g, q = 0, stage); seg_of the first norm index of g's system in the chunk.
 __device__ inline size_t vec_len(const SolveArgs& a) { return ((size_t)a.S * a.N + 1) * a.n; }
 __device__ inline size_t vec_off(const SolveArgs& a, int g, int stage) {
   const int sys = g / a.S, sl = g - sys * a.S;
-  return (size_t)sys * a.nrhs * vec_len(a) + ((size_t)sl * a.N + stage) * a.n;
+  return (size_t)sys * a.vsys + ((size_t)sl * a.N + stage) * a.n;
 }
-__device__ inline int seg_of(const SolveArgs& a, int g) { return (g / a.S) * a.nrhs; }
+__device__ inline int seg_of(const SolveArgs& a, int g) { return (g / a.S) * a.seg_sys; }
 
 // Gathered right-hand side of a position: dst[q][i] = b[off + q*len + i] / rnorm, zero
 // padded to NMAX (seg0 = norm index of q = 0).
@@ -473,8 +474,8 @@ __device__ __attribute__((always_inline)) inline void level_one_position(
   T* yj = y + (size_t)(j - 1) * n;
   const int half = 1 << (level - 1);
   const int npull = FWD ? 2 * (level - 1) : 2;
-  const size_t len = ((size_t)a.S * N + 1) * n;
-  const size_t off = (size_t)sys * len + ((size_t)sl * N + (N - j)) * n;
+  const size_t off = (size_t)sys * a.vsys + ((size_t)sl * N + (N - j)) * n;
+  const int seg = sys * a.seg_sys;
   const int o = RB::out_index();
   const bool writer = RB::base() == 0;
   const int vl = lane & (NMAX - 1);
@@ -530,7 +531,7 @@ __device__ __attribute__((always_inline)) inline void level_one_position(
     }
     if (first && wv == 0 && lane < NMAX) {
       if constexpr (FWD) {
-        const double rn = a.rnorm ? a.rnorm[sys] : 1.0;
+        const double rn = a.rnorm ? a.rnorm[seg] : 1.0;
         t[lane] = static_cast<T>(rn > 0.0 ? rb / rn : 0.0);
       } else {
         t[lane] = rv;
@@ -571,7 +572,7 @@ __device__ __attribute__((always_inline)) inline void level_one_position(
       const size_t idx = off + o;
       const double d = static_cast<double>(v);
       if (a.accumulate) {
-        const double dd = a.rnorm[sys] * d;
+        const double dd = a.rnorm[seg] * d;
         a.x[idx] = xo + dd;
         a.dstore[idx] = dd;
       } else {
@@ -624,8 +625,7 @@ __device__ __attribute__((always_inline)) inline void bwd_rows_position(
   T* yj = y + (size_t)(j - 1) * n;
   const bool has_left = j - half >= 1;
   const int ir = j + half <= m ? j + half - 1 : N - 1;
-  const size_t len = ((size_t)a.S * N + 1) * n;
-  const size_t off = (size_t)sys * len + ((size_t)sl * N + (N - j)) * n;
+  const size_t off = (size_t)sys * a.vsys + ((size_t)sl * N + (N - j)) * n;
   vt gl[K], gr[K];
   T li[K][VEC];
   const auto rsL = block_rsrc(Lb, (unsigned)(NMAX * (NMAX + 1) / 2) * sizeof(T));
@@ -703,7 +703,7 @@ __device__ __attribute__((always_inline)) inline void bwd_rows_position(
       const size_t idx = off + c;
       const double d = static_cast<double>(x[e]);
       if (a.accumulate) {
-        const double dd = a.rnorm[sys] * d;
+        const double dd = a.rnorm[sys * a.seg_sys] * d;
         a.x[idx] = xo[e] + dd;
         a.dstore[idx] = dd;
       } else {
@@ -820,8 +820,8 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
   const int n = a.n, S = a.S, nrhs = a.nrhs;
   const int sys = blockIdx.x;
   const size_t len = vec_len(a);
-  const size_t root_off = (size_t)sys * nrhs * len + (size_t)S * a.N * n;
-  const int seg0 = sys * nrhs;
+  const size_t root_off = (size_t)sys * a.vsys + (size_t)S * a.N * n;
+  const int seg0 = sys * a.seg_sys;
   const double* w = a.w + (size_t)sys * S * nrhs * n;  // this system's chains
   const int t = threadIdx.x, i = t & 31, g = t >> 5;
   {

@@ -45,3 +45,31 @@ def test_generator_lambda_min_at_least_delta(delta):
         s = make_system(3, 7, 4, 1, delta, seed)
         w = np.linalg.eigvalsh(assemble_K(s.D, s.E, s.C, s.R))
         assert w[0] >= delta * (1 - 1e-12)
+
+
+def test_condition_number_of_a_diagonal_system():
+    # E = 0, C = 0 and diagonal D, R: K is diagonal, so kappa is the ratio of its
+    # largest to its smallest diagonal entry (a closed form).
+    from oracle.conditioning import condition_number
+    S, N, n = 3, 4, 3
+    rng = np.random.default_rng(7)
+    diag = rng.uniform(0.5, 40.0, size=(S * N + 1) * n)
+    D = np.zeros((S, N, n, n))
+    for s in range(S):
+        for k in range(N):
+            o = (s * N + k) * n
+            D[s, k] = np.diag(diag[o:o + n])
+    E = np.zeros((S, N - 1, n, n))
+    C = np.zeros((S, n, n))
+    R = np.diag(diag[S * N * n:])
+    assert condition_number(D, E, C, R) == pytest.approx(diag.max() / diag.min(), rel=1e-9)
+
+
+@pytest.mark.parametrize("S,N,n,delta,seed", [(2, 5, 3, 1e-2, 11), (3, 4, 4, 1.0, 12)])
+def test_condition_number_matches_svd_ratio(S, N, n, delta, seed):
+    # For SPD K the 2-norm condition number is also the ratio of the extreme singular
+    # values (LAPACK's SVD, a different route from the Lanczos iterations).
+    from oracle.conditioning import condition_number
+    s = make_system(S, N, n, 1, delta, seed)
+    assert condition_number(s.D, s.E, s.C, s.R) == pytest.approx(
+        np.linalg.cond(assemble_K(s.D, s.E, s.C, s.R), 2), rel=1e-8)

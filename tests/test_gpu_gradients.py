@@ -78,3 +78,55 @@ def test_batched_gradients_at_workload_shape():
         assert rel(E.grad[i].cpu().numpy(), dE) <= 1e-9
         assert rel(C.grad[i].cpu().numpy(), dC) <= 1e-9
         assert rel(R.grad[i].cpu().numpy(), dR) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pooled_plan_follows_the_current_stream(precision):
+    """A plan pooled on the default stream, reused by a forward and backward issued on
+    a side stream: its kernels must run on that stream (ordered after the inputs are
+    produced there and before the outputs are read there)."""
+    from paper_2609_29977_amd.autograd import branch_solve
+    s = make_system(3, 9, 8, 1, 1e-2, 33)
+    _, _, (db, dD, dE, dC, dR) = gradients.loss_gradients(s.D, s.E, s.C, s.R, s.b)
+    # warm the pool on the default stream
+    args = [_dev(a).requires_grad_() for a in (s.D, s.E, s.C, s.R, s.b)]
+    x = branch_solve(*args, precision)
+    (0.5 * (x * x).sum()).backward()
+    del x
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        # inputs produced on the side stream right before the solve
+        D, E, C, R, b = (_dev(np.zeros_like(a)) for a in (s.D, s.E, s.C, s.R, s.b))
+        for t, a in zip((D, E, C, R, b), (s.D, s.E, s.C, s.R, s.b)):
+            t.add_(torch.from_numpy(a).to("cuda", non_blocking=True))
+        for t in (D, E, C, R, b):
+            t.requires_grad_()
+        x = branch_solve(D, E, C, R, b, precision)
+        (0.5 * (x * x).sum()).backward()
+    side.synchronize()
+    assert rel(b.grad.cpu().numpy(), db) <= 1e-9
+    assert rel(D.grad.cpu().numpy(), dD) <= 1e-9
+    assert rel(E.grad.cpu().numpy(), dE) <= 1e-9
+    assert rel(C.grad.cpu().numpy(), dC) <= 1e-9
+    assert rel(R.grad.cpu().numpy(), dR) <= 1e-9
+
+
+def test_second_backward_with_retained_graph():
+    """retain_graph=True: the plan (and its factor) stays with the graph, so a second
+    backward gives the same gradients (accumulated twice)."""
+    from paper_2609_29977_amd.autograd import branch_solve
+    s = make_system(2, 7, 4, 1, 1e-2, 34)
+    _, _, (db, dD, dE, dC, dR) = gradients.loss_gradients(s.D, s.E, s.C, s.R, s.b)
+    D, E, C, R, b = (_dev(a).requires_grad_() for a in (s.D, s.E, s.C, s.R, s.b))
+    x = branch_solve(D, E, C, R, b, "fp64")
+    loss = 0.5 * (x * x).sum()
+    loss.backward(retain_graph=True)
+    # another solve of the same shape in between must not take the retained plan
+    y = branch_solve(*(_dev(a) for a in (s.D, s.E, s.C, s.R, s.b)), "fp64")
+    loss.backward()
+    torch.cuda.synchronize()
+    assert rel(b.grad.cpu().numpy(), 2 * db) <= 1e-9
+    assert rel(D.grad.cpu().numpy(), 2 * dD) <= 1e-9
+    assert rel(E.grad.cpu().numpy(), 2 * dE) <= 1e-9
+    del y

@@ -52,3 +52,38 @@ def test_ipm_step_matches_full_kkt_solve(precision):
     x = x.cpu().numpy()[0]
     assert np.max(np.abs(x - full)) <= 1e-9 * np.max(np.abs(full))
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_admm_system_through_the_ipm_assembly(precision):
+    # ADMM paragraph of the appendix: with W = 0, tau = sigma and delta = 1/rho the
+    # assembly builds P + sigma I + rho (A^T A + G^T G); checked block by block against
+    # the dense ADMM reduction and, solved through the library, against the full ADMM
+    # KKT solve.
+    from paper_2609_29977_amd import bmpc
+    S, N, nx, nu = 3, 10, 4, 2
+    sigma, rho = 1e-6, 0.5
+    q = make_qp(S, N, nx, nu, seed=10)
+    n = q.n
+    ref = oqp.blocks(oqp.admm_reduced_K(q, sigma, rho), S, N, n)
+    w0 = np.zeros_like(q.w)
+    D, E, C, R = bmpc.assemble_qp(_dev(q.Q), _dev(q.A), _dev(q.G), _dev(w0), sigma, 1.0 / rho)
+    torch.cuda.synchronize()
+    scale = max(np.max(np.abs(r)) for r in ref)
+    for g, r, name in zip((D, E, C, R), ref, "DECR"):
+        assert np.max(np.abs(g.cpu().numpy() - r)) <= 1e-13 * scale, name
+    M = oqp.admm_kkt(q, sigma, rho)
+    nv = (S * N + 1) * n
+    rng = np.random.default_rng(11)
+    rhs = np.zeros(M.shape[0])
+    rhs[:nv] = rng.standard_normal(nv)
+    full = np.linalg.solve(M, rhs)[:nv]
+    plan = bmpc.Plan(S, N, n, 1, precision)
+    plan.factor(D, E, C, R)
+    b = _dev(rhs[:nv][None, :])
+    x = plan.solve(b) if precision == "fp64" else plan.refine(D, E, C, R, b, tol=1e-14,
+                                                             max_iters=20)
+    assert plan.info() == 0
+    x = x.cpu().numpy()[0]
+    assert np.max(np.abs(x - full)) <= 1e-9 * np.max(np.abs(full))
+    plan.close()

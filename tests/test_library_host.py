@@ -73,8 +73,17 @@ def test_metric_workload_counts():
 
 
 @pytest.mark.parametrize("dims", [(0, 4, 4, 1), (4, 0, 4, 1), (4, 4, 0, 1), (4, 4, 33, 1),
-                                  (4, 4, 4, 0), (4, 4, 4, 9)])
+                                  (4, 4, 4, 0), (4, 4, 4, 5000)])
 def test_cost_model_rejects_bad_dims(dims):
     with pytest.raises(bmpc.BmpcError) as e:
         bmpc.cost_model(*dims)
     assert e.value.status == bmpc.ERR_INVALID
+
+
+def test_cost_model_counts_right_hand_side_chunks():
+    # Right-hand sides run through the solve kernels eight at a time: flops and bytes
+    # scale with nrhs, the numbers of solve launches with the number of chunks.
+    one = bmpc.cost_model(16, 33, 8, 1, "fp64")
+    twelve = bmpc.cost_model(16, 33, 8, 12, "fp64")
+    assert twelve.solve_flops == pytest.approx(12 * one.solve_flops, rel=1e-12)
+    assert twelve.factor_flops == one.factor_flops

@@ -151,3 +151,39 @@ def test_fill_invariant_of_dense_reordered_cholesky(S, N, n, seed):
                 assert np.any(blk != 0.0), (I, J)
             else:
                 assert np.all(blk == 0.0), (I, J)
+
+
+def test_global_perm_written_out_for_two_tails():
+    # Pi = blkdiag(Pi_1, ..., Pi_M, I) (Section IV-A) for S = 2, N = 3: each tail is
+    # reversed, Gamma_2 leaves (x_3, x_2) in place, x_1 stays last, the root follows.
+    assert symbolic.global_perm(2, 3) == [(0, 2), (0, 1), (0, 0), (1, 2), (1, 1), (1, 0),
+                                         symbolic.ROOT]
+    assert symbolic.global_perm(1, 1) == [(0, 0), symbolic.ROOT]
+
+
+@pytest.mark.parametrize("S,N,n", [(1, 1, 2), (2, 9, 3), (3, 5, 1), (2, 16, 2)])
+def test_global_perm_is_blockwise_the_scalar_permutation(S, N, n):
+    # Expanding every block variable of Pi into its n scalars gives the permutation
+    # that puts K into the factored order; checked against an independent expansion
+    # (the scalar index vector built from each tail's ordering).
+    gp = symbolic.global_perm(S, N)
+    assert len(gp) == S * N + 1 and len(set(gp)) == len(gp)
+    idx = []
+    for v in gp:
+        base = S * N * n if v == symbolic.ROOT else (v[0] * N + v[1]) * n
+        idx.extend(range(base, base + n))
+    assert idx == dense.perm_index(S, N, n, "d").tolist()
+
+
+@pytest.mark.parametrize("S,N", [(2, 9), (3, 4), (1, 17)])
+def test_global_perm_keeps_one_root_block_per_tail(S, N):
+    # Theorem 1 on the whole system: eliminating the block graph of K in the order of
+    # Pi leaves exactly one root-row block per tail, the tail's last (x_1) variable;
+    # the forward order of Fig. 2(a) fills the whole border.
+    blocks, _ = symbolic.elimination_game(symbolic.block_graph(S, N),
+                                          symbolic.global_perm(S, N))
+    root_row = sorted(c for r, c in blocks if r == symbolic.ROOT and c != symbolic.ROOT)
+    assert root_row == [(s, 0) for s in range(S)]
+    fwd = [(s, k) for s in range(S) for k in range(N)] + [symbolic.ROOT]
+    blocks_a, _ = symbolic.elimination_game(symbolic.block_graph(S, N), fwd)
+    assert sum(1 for r, c in blocks_a if r == symbolic.ROOT and c != symbolic.ROOT) == S * N
