@@ -163,8 +163,11 @@ bmpc_status bmpc_solve(bmpc_plan plan, const double* b, double* x);
  *     max_iters + 1 residuals (tol = c * 2^-53 with c of order 10 asks for the backward
  *     stability of an FP64 solve).
  * Needs the factor of the same D, E, C, R.  x on entry is ignored.  The stop test runs
- * on the device (later launches of a converged loop return at once), so the launch
- * sequence is fixed and capturable.  max_iters in 0..100. */
+ * on the device (later launches of a converged loop return at once), so under stream
+ * capture the launch sequence is fixed and capturable.  Outside capture the host also
+ * reads the stop flag after each test (a synchronization of the plan's stream) and
+ * issues nothing more once it holds, so the call returns after the work is done.
+ * max_iters in 0..100. */
 bmpc_status bmpc_refine(bmpc_plan plan, const double* D, const double* E,
                         const double* C, const double* R, const double* b, double* x,
                         double tol, int32_t max_iters);

@@ -33,7 +33,7 @@ struct Timing {
   hipEvent_t a, b;
 };
 
-int nmax_for(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 32); }
+int nmax_for(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : (n <= 32 ? 32 : 64)); }
 
 double potrf_flops(double n) { return n * n * n / 3.0 + n * n / 2.0 + n / 6.0; }
 double trsm_flops(double n) { return n * n * n; }
@@ -45,7 +45,7 @@ double gemm_flops(double n) { return 2.0 * n * n * n; }
 // serial walk of each window, which sets the pass time once the chains are short or
 // few; 3 (FP64) and 4 (FP32) were fastest or within a few percent of it throughout.
 int default_window_depth(bool fp64, int nmax) {
-  (void)nmax;
+  if (nmax > 32) return 1;  // blocks of 33..64: one level per pass (factor64.hip)
   return fp64 ? 3 : 4;
 }
 
@@ -230,6 +230,7 @@ struct bmpc_plan_s {
   double* kroot = nullptr;
   double* crow = nullptr;
   int kper = 0;  // residual workgroups per system
+  int* hflag = nullptr;  // pinned host copy of the refinement's stop flag
   std::vector<void*> allocs;
   double workspace_bytes = 0;
   bool factored = false;
@@ -289,7 +290,7 @@ void collect_timings(bmpc_plan p) {
 constexpr int kMaxPlanRhs = 4096;
 
 bool dims_ok(const bmpc_dims* d, int B = 1) {
-  return d && d->S >= 1 && d->N >= 1 && d->n >= 1 && d->n <= 32 && d->nrhs >= 1 &&
+  return d && d->S >= 1 && d->N >= 1 && d->n >= 1 && d->n <= 64 && d->nrhs >= 1 &&
          d->nrhs <= kMaxPlanRhs && B >= 1 && (double)B * d->S * d->N * d->n < 2.0e9 &&
          (double)B * d->S * d->N < 2.0e9 / 64 &&
          (double)B * d->nrhs * ((double)d->S * d->N + 1) * d->n < 4.0e9;
@@ -303,6 +304,8 @@ int systems_of(const bmpc_options* o) { return (o && o->num_systems > 0) ? o->nu
 void free_plan_memory(bmpc_plan p) {
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
+  if (p->hflag) (void)hipHostFree(p->hflag);
+  p->hflag = nullptr;
   for (const Timing& t : p->timings) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -329,6 +332,7 @@ bool dalloc(bmpc_plan p, void** ptr, size_t bytes) {
 // The LDS of a pass includes the right-hand-side slots of the fused forward
 // substitution for one chunk of the plan's right-hand sides, so that path always fits.
 int pick_window_depth(bool fp64, int nmax, int nrhs, const bmpc_options* o) {
+  if (nmax > 32) return 1;
   int Tw = (o && o->window_depth > 0) ? o->window_depth : default_window_depth(fp64, nmax);
   Tw = std::min(Tw, kMaxWindowDepth);
   const int q = std::min(nrhs, rhs_chunk(nmax));
@@ -481,6 +485,11 @@ void enqueue_solve(bmpc_plan p, const double* b, double* x, int first_chunk = 0)
 template <typename T>
 void enqueue_factor_solve(bmpc_plan p, const double* D, const double* E, const double* C,
                           const double* R, const double* b, double* x) {
+  if (p->nmax > 32) {  // no forward substitution inside the n > 32 factor passes
+    enqueue_factor<T>(p, D, E, C, R);
+    enqueue_solve<T>(p, b, x);
+    return;
+  }
   enqueue_factor<T>(p, D, E, C, R, b, chunk_rhs(p, 0));
   enqueue_solve_back<T>(p, solve_args(p, b, x, 0, chunk_rhs(p, 0)));
   enqueue_solve<T>(p, b, x, 1);
@@ -617,6 +626,11 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
             dalloc(p, (void**)&p->kpart, S * res_chunks * 8) &&
             dalloc(p, (void**)&p->kroot, (size_t)B * 8) &&
             dalloc(p, (void**)&p->crow, S * n * 8);
+  if (ok && hipHostMalloc((void**)&p->hflag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    p->hflag = nullptr;
+    (void)hipGetLastError();
+    ok = false;
+  }
   if (ok && npass > 1) {
     for (int set = 0; set < 2 && ok; ++set) {
       for (int b = 0; b < 3 && ok; ++b)
@@ -672,6 +686,26 @@ bmpc_status bmpc_solve(bmpc_plan p, const double* b, double* x) {
   else
     enqueue_solve<float>(p, b, x);
   return last_error_status();
+}
+
+// Whether the refinement's stop test already holds, read on the host.  Outside stream
+// capture the loop stops issuing launches once it holds (the device-side flag would
+// make them return at once, but each still costs a launch); under capture the launch
+// sequence stays fixed and the flag alone decides.
+bool stop_reached(bmpc_plan p) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(p->stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (cs != hipStreamCaptureStatusNone) return false;
+  if (hipMemcpyAsync(p->hflag, p->flags, sizeof(int), hipMemcpyDeviceToHost, p->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return p->hflag[0] != 0;
 }
 
 // x = K^{-1} b by refinement (see bmpc_refine); with fused, the factor is issued here
@@ -750,6 +784,7 @@ static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, co
     else
       enqueue_solve<float>(p, p->rbuf, x, 0, mod);
   };
+  bool stopped = false;  // the host saw the stop test hold
   for (int it = 0; it < max_iters; ++it) {
     residual(be && it == 0);
     if (be) {
@@ -759,6 +794,7 @@ static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, co
                                p->kper, p->kroot, p->knorm, p->bnorm, tol, 1, p->flags,
                                p->relcorr, rnorm, st);
       });
+      if ((stopped = stop_reached(p))) break;
     } else {
       timed(p, KC_REFINE_MISC, [&] {
         launch_maxabs(p->rbuf, segs, len, p->npart, rnorm, p->flags, st);
@@ -770,9 +806,10 @@ static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, co
         launch_refine_check(p->rbuf, x, segs, len, p->npart, tol, p->flags, p->relcorr, dnorm,
                             xnorm, st);
       });
+      if (it + 1 < max_iters && (stopped = stop_reached(p))) break;
     }
   }
-  if (be) {
+  if (be && !stopped) {
     // the returned x is certified by its own residual
     residual(max_iters == 0);
     timed(p, KC_REFINE_MISC, [&] {

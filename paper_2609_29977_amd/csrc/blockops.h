@@ -279,12 +279,12 @@ __device__ __attribute__((always_inline)) inline void wave_lds_fence() {
 // The leaves do two 16-row factorizations instead of one 32-row one, which halves
 // their per-lane state and cuts the scalar broadcasts; the rest runs on the matrix
 // cores.  One wave.  Returns the 0-based row of the first non-positive pivot, or -1.
-template <typename T, int NMAX>
+template <typename T, int NMAX, int LD = Lay<NMAX>::LD>
 __device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
+  static_assert(NMAX <= 32, "one wave per block up to 32 x 32");
   if constexpr (NMAX < 32) {
-    return wave_potrf_inv_leaf<T, NMAX>(A);
+    return wave_potrf_inv_leaf<T, NMAX, LD>(A);
   } else {
-    constexpr int LD = Lay<NMAX>::LD;
     typedef typename Mfma<T>::acc_t acc_t;
     const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
     T* A21 = A + 16 * LD;

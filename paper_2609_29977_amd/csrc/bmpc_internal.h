@@ -32,7 +32,7 @@ constexpr int kSolveThreads = 64;
 // residual's LDS holds fewer vectors); a plan's nrhs has no such limit.
 constexpr int kMaxRhs = 8;
 constexpr int kMaxRhs64 = 4;
-inline __host__ __device__ int rhs_chunk(int nmax) { return nmax > 32 ? kMaxRhs64 : kMaxRhs; }
+constexpr __host__ __device__ int rhs_chunk(int nmax) { return nmax > 32 ? kMaxRhs64 : kMaxRhs; }
 
 // Blocks per chain in the G_l and G_r arrays: the N-1 blocks of the positions 1..N-1,
 // padded to N so that every factor array (L^{-1} has N) shares one chain stride; the
@@ -171,6 +171,10 @@ struct GradArgs {
 // launchers (defined next to their kernels)
 template <typename T>
 void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st);
+// block sizes 33..64: window depth 1, no fused forward substitution (factor64.hip)
+template <typename T>
+void launch_factor_pass64(const FactorPassArgs& a, hipStream_t st);
+size_t factor64_lds_bytes(bool fp64);
 void launch_factor_init(unsigned long long* info, hipStream_t st);
 // part[sys][g] = sum of U over the scenarios of group g of system sys (B systems of S)
 void launch_root_reduce(const double* U, double* part, int B, int S, int n, int groups,
@@ -194,6 +198,13 @@ void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t
 // chain, one wave per position, top level first); only where bwd_top_level says so.
 template <typename T>
 void launch_solve_bwd_top(const SolveArgs& a, int level_lo, hipStream_t st);
+
+// block sizes 33..64 (solve64.hip): one level of either sweep, the x_1 forward step
+// (fwd) or root propagation + x_1 backward step
+template <typename T>
+void launch_solve64_level(const SolveArgs& a, int level, bool fwd, hipStream_t st);
+template <typename T>
+void launch_solve64_x(const SolveArgs& a, bool fwd, hipStream_t st);
 
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st);
 void launch_grad_blocks(const GradArgs& a, hipStream_t st);

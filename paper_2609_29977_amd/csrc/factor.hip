@@ -860,21 +860,18 @@ __global__ void __launch_bounds__(1024) root_reduce_kernel(const double* __restr
   const int per = (S + groups - 1) / groups;
   const int s0 = g * per, s1 = min(S, s0 + per);
   const double* Us = U + (size_t)sys * S * nn;
-  const int e = threadIdx.x;
-  if (e >= nn || s0 >= s1) {
-    if (e < nn) part[((size_t)sys * groups + g) * nn + e] = 0.0;
-    return;
-  }
-  constexpr int B = 16;
-  double acc = 0.0;
-  for (int s = s0; s < s1; s += B) {
-    double t[B];
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    constexpr int B = 16;
+    double acc = 0.0;
+    for (int s = s0; s < s1; s += B) {
+      double t[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) t[u] = Us[(size_t)min(s + u, s1 - 1) * nn + e];
+      for (int u = 0; u < B; ++u) t[u] = Us[(size_t)min(s + u, s1 - 1) * nn + e];
 #pragma unroll
-    for (int u = 0; u < B; ++u) acc = (s + u < s1) ? acc + t[u] : acc;
+      for (int u = 0; u < B; ++u) acc = (s + u < s1) ? acc + t[u] : acc;
+    }
+    part[((size_t)sys * groups + g) * nn + e] = acc;  // 0 for an empty group
   }
-  part[((size_t)sys * groups + g) * nn + e] = acc;
 }
 
 // R~ = R - sum_g part[g] (group order), L_R = chol(R~) in FP64 (Algorithm 1, root
@@ -896,9 +893,8 @@ __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restri
   part += (size_t)sys * groups * n * n;
   LR += (size_t)sys * n * n;
   const unsigned long long row_base = sys * sys_rows + root_row;
-  const int e = threadIdx.x;
-  const int r = e / NMAX, c = e % NMAX;
-  if (e < NMAX * NMAX) {
+  for (int e = threadIdx.x; e < NMAX * NMAX; e += blockDim.x) {
+    const int r = e / NMAX, c = e % NMAX;
     double v = (r == c) ? 1.0 : 0.0;  // identity padding
     if (r < n && c < n) {
       constexpr int B = 32;
@@ -922,7 +918,10 @@ __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restri
     if (fail >= 0 && fail < n && threadIdx.x == 0) atomicMin(info, row_base + fail + 1);
   }
   __syncthreads();
-  if (e < NMAX * NMAX && r < n && c < n) LR[r * n + c] = A[r * LD + c];
+  for (int e = threadIdx.x; e < NMAX * NMAX; e += blockDim.x) {
+    const int r = e / NMAX, c = e % NMAX;
+    if (r < n && c < n) LR[r * n + c] = A[r * LD + c];
+  }
 }
 
 // Block slots, plus (fused forward substitution) Tw + 5 right-hand-side slots.
@@ -973,6 +972,7 @@ void launch_pass_t(const FactorPassArgs& a, hipStream_t st) {
 }  // namespace
 
 size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw, int nrhs_fused) {
+  if (nmax > 32) return Tw == 1 && nrhs_fused == 0 ? factor64_lds_bytes(fp64) : ~(size_t)0;
   if (fp64) {
     if (nmax <= 8) return pass_lds_bytes<double, 8>(Tw, nrhs_fused);
     if (nmax <= 16) return pass_lds_bytes<double, 16>(Tw, nrhs_fused);
@@ -989,8 +989,10 @@ void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st) {
     launch_pass_t<T, 8>(a, st);
   else if (nmax <= 16)
     launch_pass_t<T, 16>(a, st);
-  else
+  else if (nmax <= 32)
     launch_pass_t<T, 32>(a, st);
+  else
+    launch_factor_pass64<T>(a, st);
 }
 template void launch_factor_pass<double>(const FactorPassArgs&, int, hipStream_t);
 template void launch_factor_pass<float>(const FactorPassArgs&, int, hipStream_t);
@@ -1011,8 +1013,11 @@ void launch_root_potrf(const double* R, const double* part, int B, int groups, i
   if (n <= 16)
     hipLaunchKernelGGL(root_potrf_kernel<16>, dim3(B), dim3(1024), 0, st, R, part, groups, n,
                        LR, (unsigned long long)sys_rows, (unsigned long long)root_row, info);
-  else
+  else if (n <= 32)
     hipLaunchKernelGGL(root_potrf_kernel<32>, dim3(B), dim3(1024), 0, st, R, part, groups, n,
+                       LR, (unsigned long long)sys_rows, (unsigned long long)root_row, info);
+  else
+    hipLaunchKernelGGL(root_potrf_kernel<64>, dim3(B), dim3(1024), 0, st, R, part, groups, n,
                        LR, (unsigned long long)sys_rows, (unsigned long long)root_row, info);
 }
 

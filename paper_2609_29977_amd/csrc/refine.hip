@@ -45,7 +45,7 @@ inline size_t residual_lds_bytes(int nrhs) {
 template <int NMAX, bool FULL>
 struct StageFetch {
   static constexpr int PER = (NMAX * NMAX + RES_T - 1) / RES_T;
-  static constexpr int VPER = (kMaxRhs * NMAX + RES_T - 1) / RES_T;
+  static constexpr int VPER = (rhs_chunk(NMAX) * NMAX + RES_T - 1) / RES_T;
   double d[PER], e[PER], xv[VPER], bv[VPER];
 
   // A block that does not exist (exists = false) is read as zero without a memory
@@ -258,25 +258,29 @@ __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chu
   }
 }
 
+// One workgroup per system; thread (g, i) sums element i of the products C_s x_{s,0}
+// over the scenarios s = g mod G (G = 1024 / NMAX groups), the groups in order.
+template <int NMAX>
 __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
   if (a.done && *a.done) return;
-  __shared__ double part[32][33];
+  constexpr int G = 1024 / NMAX;
+  __shared__ double part[G][NMAX + 1];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
   const int sys = blockIdx.x;  // one workgroup per system
   const size_t len = ((size_t)S * N + 1) * n;
   const size_t root = (size_t)sys * a.vsys + (size_t)S * N * n;
   const double* w = a.w + (size_t)sys * S * nrhs * n;
   const double* R = a.R + (size_t)sys * n * n;
-  const int t = threadIdx.x, i = t & 31, g = t >> 5;
+  const int t = threadIdx.x, i = t % NMAX, g = t / NMAX;
   for (int q = 0; q < nrhs; ++q) {
     double acc = 0.0;
     if (i < n) {
       constexpr int B = 8;
-      for (int s0 = g; s0 < S; s0 += 32 * B) {
+      for (int s0 = g; s0 < S; s0 += G * B) {
         double v[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-          const int sc = s0 + 32 * u;
+          const int sc = s0 + G * u;
           v[u] = sc < S ? w[((size_t)sc * nrhs + q) * n + i] : 0.0;
         }
 #pragma unroll
@@ -288,7 +292,7 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
     if (t < n) {
       const int row = t;
       double sum = 0.0;
-      for (int gg = 0; gg < 32; ++gg) sum += part[gg][row];
+      for (int gg = 0; gg < G; ++gg) sum += part[gg][row];
       double rx = 0.0;
       for (int c = 0; c < n; ++c) {
         const double rv = (row >= c) ? R[row * n + c] : R[c * n + row];
@@ -480,12 +484,23 @@ void launch_refine_be_check(const double* r, const double* x, int B, int nrhs, s
 
 template <int NMAX>
 static void launch_residual_t(const ResidualArgs& a, dim3 grid, int chunks, hipStream_t st) {
+  const size_t lds = residual_lds_bytes<NMAX>(a.nrhs);
+  if (NMAX > 32) {  // beyond the default 64 KB of dynamic LDS
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel<NMAX, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)residual_lds_bytes<NMAX>(rhs_chunk(NMAX)));
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&residual_kernel<NMAX, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)residual_lds_bytes<NMAX>(rhs_chunk(NMAX)));
+      attr_set = true;
+    }
+  }
   if (a.n == NMAX)
-    hipLaunchKernelGGL((residual_kernel<NMAX, true>), grid, dim3(RES_T),
-                       residual_lds_bytes<NMAX>(a.nrhs), st, a, chunks);
+    hipLaunchKernelGGL((residual_kernel<NMAX, true>), grid, dim3(RES_T), lds, st, a, chunks);
   else
-    hipLaunchKernelGGL((residual_kernel<NMAX, false>), grid, dim3(RES_T),
-                       residual_lds_bytes<NMAX>(a.nrhs), st, a, chunks);
+    hipLaunchKernelGGL((residual_kernel<NMAX, false>), grid, dim3(RES_T), lds, st, a, chunks);
 }
 
 void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
@@ -495,12 +510,17 @@ void launch_residual(const ResidualArgs& a, int nmax, hipStream_t st) {
     launch_residual_t<8>(a, grid, chunks, st);
   else if (nmax <= 16)
     launch_residual_t<16>(a, grid, chunks, st);
-  else
+  else if (nmax <= 32)
     launch_residual_t<32>(a, grid, chunks, st);
+  else
+    launch_residual_t<64>(a, grid, chunks, st);
 }
 
 void launch_residual_root(const ResidualArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(residual_root_kernel, dim3(a.B), dim3(1024), 0, st, a);
+  if (a.n > 32)
+    hipLaunchKernelGGL(residual_root_kernel<64>, dim3(a.B), dim3(1024), 0, st, a);
+  else
+    hipLaunchKernelGGL(residual_root_kernel<32>, dim3(a.B), dim3(1024), 0, st, a);
 }
 
 void launch_maxabs(const double* v, int nrhs, size_t len, double* partial, double* out,

@@ -37,7 +37,7 @@ __device__ inline float buf_load_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
 
 template <typename T, int NMAX, int WAVES = 1>
 struct RegBlock {
-  static_assert(NMAX == 8 || NMAX == 16 || NMAX == 32, "block size bound");
+  static_assert(NMAX == 8 || NMAX == 16 || NMAX == 32 || NMAX == 64, "block size bound");
   static_assert(WAVES == 1 || WAVES == 2 || WAVES == 4, "waves per block");
   static constexpr int RPW = NMAX / WAVES;
   static constexpr int LPR = 64 / RPW;

@@ -19,24 +19,13 @@
 #include "bmpc_internal.h"
 #include "blockops.h"
 #include "regblock.h"
+#include "solve_common.h"
 
 namespace bmpc {
 
 namespace {
 
 constexpr int NT = kSolveThreads;
-
-// Vectors b, x, r are [B][nrhs][len], len = (S*N+1)*n: system sys, right-hand side q
-// of the launch's chunk starts at sys*vsys + q*len (the pointers are offset to the
-// chunk), its tails in stage order, its root last.  Chain g of the batch
-// (0 <= g < B*S) is scenario g % S of system g / S.  vec_off gives the offset of
-// (chain g, q = 0, stage); seg_of the first norm index of g's system in the chunk.
-__device__ inline size_t vec_len(const SolveArgs& a) { return ((size_t)a.S * a.N + 1) * a.n; }
-__device__ inline size_t vec_off(const SolveArgs& a, int g, int stage) {
-  const int sys = g / a.S, sl = g - sys * a.S;
-  return (size_t)sys * a.vsys + ((size_t)sl * a.N + stage) * a.n;
-}
-__device__ inline int seg_of(const SolveArgs& a, int g) { return (g / a.S) * a.seg_sys; }
 
 // Gathered right-hand side of a position: dst[q][i] = b[off + q*len + i] / rnorm, zero
 // padded to NMAX (seg0 = norm index of q = 0).
@@ -141,18 +130,6 @@ struct SolveSmem {
   T vbuf[2][kMaxRhs][NMAX];
   T rhs[kMaxRhs][NMAX];
 };
-
-// x[off + q*len] = d  or  x += rnorm * d with rnorm * d kept in dstore.
-__device__ inline void scatter_value(const SolveArgs& a, int q, size_t off, int seg0, double d) {
-  const size_t idx = (size_t)q * vec_len(a) + off;
-  if (a.accumulate) {
-    const double dd = a.rnorm[seg0 + q] * d;
-    a.x[idx] += dd;
-    a.dstore[idx] = dd;
-  } else {
-    a.x[idx] = d;
-  }
-}
 
 // Level kernels of both sweeps.  A position applies its own L_jj^{-1} after
 // subtracting the products of the factor blocks it pulls, each with the vector of a
@@ -809,35 +786,38 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
 
 // Root step in FP64 (Algorithm 2, root step).  One workgroup of 1024 threads per
 // system of the batch:
-// r~_0 = r_0 - sum_s w_s with thread (g, i) summing the scenarios s = g mod 32 of
-// element i and the 32 group partials combined in order; then the two triangular
-// solves with L_R in LDS, one wave per right-hand side, lane i owning row i.
+// r~_0 = r_0 - sum_s w_s with thread (g, i) summing the scenarios s = g mod G of
+// element i (G = 1024 / NMAX groups) and the G group partials combined in order; then
+// the two triangular solves with L_R in LDS, one wave per right-hand side, lane i
+// owning row i.
+template <int NMAX>
 __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
   if (a.done && *a.done) return;
-  __shared__ double part[32][33];
-  __shared__ double L[32 * 33];
-  __shared__ double r0[kMaxRhs][32];
+  constexpr int G = 1024 / NMAX, LD = NMAX + 1;
+  __shared__ double part[G][LD];
+  __shared__ double L[NMAX * LD];
+  __shared__ double r0[kMaxRhs][NMAX];
   const int n = a.n, S = a.S, nrhs = a.nrhs;
   const int sys = blockIdx.x;
   const size_t len = vec_len(a);
   const size_t root_off = (size_t)sys * a.vsys + (size_t)S * a.N * n;
   const int seg0 = sys * a.seg_sys;
   const double* w = a.w + (size_t)sys * S * nrhs * n;  // this system's chains
-  const int t = threadIdx.x, i = t & 31, g = t >> 5;
-  {
-    const int r = t / 32, c = t % 32;
-    L[r * 33 + c] = (r < n && c < n) ? a.LR[(size_t)sys * n * n + r * n + c]
+  const int t = threadIdx.x, i = t % NMAX, g = t / NMAX;
+  for (int e = t; e < NMAX * NMAX; e += 1024) {
+    const int r = e / NMAX, c = e % NMAX;
+    L[r * LD + c] = (r < n && c < n) ? a.LR[(size_t)sys * n * n + r * n + c]
                                      : (r == c ? 1.0 : 0.0);  // identity padding
   }
   for (int q = 0; q < nrhs; ++q) {
     double acc = 0.0;
     if (i < n) {
       constexpr int B = 8;
-      for (int s0 = g; s0 < S; s0 += 32 * B) {
+      for (int s0 = g; s0 < S; s0 += G * B) {
         double v[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-          const int sc = s0 + 32 * u;
+          const int sc = s0 + G * u;
           v[u] = sc < S ? w[((size_t)sc * nrhs + q) * n + i] : 0.0;
         }
 #pragma unroll
@@ -848,7 +828,7 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
     __syncthreads();
     if (t < n) {
       double sum = 0.0;
-      for (int gg = 0; gg < 32; ++gg) sum += part[gg][t];
+      for (int gg = 0; gg < G; ++gg) sum += part[gg][t];
       double bv = a.b[(size_t)q * len + root_off + t];
       if (a.rnorm) {
         const double rn = a.rnorm[seg0 + q];
@@ -859,26 +839,26 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
     __syncthreads();
   }
   // L_R y = r, then L_R^T x = y: wave q handles right-hand side q, lane k row k.  L is
-  // identity padded to 32 x 32, so both sweeps run 32 unrolled steps (the padded
+  // identity padded to NMAX x NMAX, so both sweeps run NMAX unrolled steps (the padded
   // unknowns stay 0); each lane holds the row (forward) or column (backward) of L it
   // updates with, and 1 / L[k][k] is formed once per lane and broadcast with x_k.
   const int wv = t >> 6, lane = t & 63;
   if (wv < nrhs) {
-    const int row = lane < 32 ? lane : 31;
+    const int row = lane < NMAX ? lane : NMAX - 1;
     double v = (lane < n) ? r0[wv][lane] : 0.0;
-    const double rd = 1.0 / L[row * 33 + row];
-    double lk[32];
+    const double rd = 1.0 / L[row * LD + row];
+    double lk[NMAX];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) lk[k] = L[row * 33 + k];
+    for (int k = 0; k < NMAX; ++k) lk[k] = L[row * LD + k];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
+    for (int k = 0; k < NMAX; ++k) {
       const double xk = wave_bcast(v, k) * wave_bcast(rd, k);
       v = (lane == k) ? xk : (lane > k ? v - lk[k] * xk : v);
     }
 #pragma unroll
-    for (int k = 0; k < 32; ++k) lk[k] = L[k * 33 + row];
+    for (int k = 0; k < NMAX; ++k) lk[k] = L[k * LD + row];
 #pragma unroll
-    for (int k = 31; k >= 0; --k) {
+    for (int k = NMAX - 1; k >= 0; --k) {
       const double xk = wave_bcast(v, k) * wave_bcast(rd, k);
       v = (lane == k) ? xk : (lane < k ? v - lk[k] * xk : v);
     }
@@ -1005,10 +985,12 @@ void x_bwd_t(const SolveArgs& a, hipStream_t st) {
 
 template <typename T>
 void launch_solve_fwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st) {
+  if (nmax > 32) return launch_solve64_level<T>(a, level, true, st);
   BMPC_DISPATCH_NMAX(nmax, fwd_level_t, a, level, st);
 }
 template <typename T>
 void launch_solve_bwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st) {
+  if (nmax > 32) return launch_solve64_level<T>(a, level, false, st);
   BMPC_DISPATCH_NMAX(nmax, bwd_level_t, a, level, st);
 }
 template <typename T>
@@ -1025,14 +1007,19 @@ void launch_solve_bwd_top(const SolveArgs& a, int level_lo, hipStream_t st) {
 }
 template <typename T>
 void launch_solve_x_fwd(const SolveArgs& a, int nmax, hipStream_t st) {
+  if (nmax > 32) return launch_solve64_x<T>(a, true, st);
   BMPC_DISPATCH_NMAX(nmax, x_fwd_t, a, st);
 }
 template <typename T>
 void launch_solve_x_bwd(const SolveArgs& a, int nmax, hipStream_t st) {
+  if (nmax > 32) return launch_solve64_x<T>(a, false, st);
   BMPC_DISPATCH_NMAX(nmax, x_bwd_t, a, st);
 }
 void launch_solve_root(const SolveArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(solve_root_kernel, dim3(a.B), dim3(1024), 0, st, a);
+  if (a.n > 32)
+    hipLaunchKernelGGL(solve_root_kernel<64>, dim3(a.B), dim3(1024), 0, st, a);
+  else
+    hipLaunchKernelGGL(solve_root_kernel<32>, dim3(a.B), dim3(1024), 0, st, a);
 }
 
 template void launch_solve_fwd_level<double>(const SolveArgs&, int, int, hipStream_t);

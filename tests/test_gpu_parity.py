@@ -183,7 +183,7 @@ def test_state_and_argument_errors():
     assert e.value.status == bm.ERR_INVALID
     plan.close()
     with pytest.raises(bm.BmpcError) as e:
-        bm.Plan(2, 4, 40, 1)
+        bm.Plan(2, 4, 65, 1)
     assert e.value.status == bm.ERR_INVALID
 
 

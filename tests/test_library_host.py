@@ -72,8 +72,8 @@ def test_metric_workload_counts():
     assert c.factor_bytes == pytest.approx(4.29e9, rel=1e-3)
 
 
-@pytest.mark.parametrize("dims", [(0, 4, 4, 1), (4, 0, 4, 1), (4, 4, 0, 1), (4, 4, 33, 1),
-                                  (4, 4, 4, 0), (4, 4, 4, 5000)])
+@pytest.mark.parametrize("dims", [(0, 4, 4, 1), (4, 0, 4, 1), (4, 4, 0, 1),
+                                  (4, 4, 4, 0), (4, 4, 4, 5000), (4, 4, 65, 1)])
 def test_cost_model_rejects_bad_dims(dims):
     with pytest.raises(bmpc.BmpcError) as e:
         bmpc.cost_model(*dims)
