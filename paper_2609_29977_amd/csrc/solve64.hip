@@ -77,6 +77,7 @@ __global__ void __launch_bounds__(T64) solve64_level_kernel(SolveArgs a, int lev
   const size_t off = vec_off(a, s, N - j);
   const int seg0 = seg_of(a, s);
   stage_rhs64<T, FWD>(a, rhs, off, seg0, yj);
+  __syncthreads();  // rhs is complete before any lane updates it (also with no pulls)
   T part[kMaxRhs64];
 #pragma unroll
   for (int q = 0; q < kMaxRhs64; ++q) part[q] = T(0);
@@ -147,6 +148,7 @@ __global__ void __launch_bounds__(T64) solve64_x_fwd_kernel(SolveArgs a) {
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* y = reinterpret_cast<T*>(a.y) + (size_t)s * N * nrhs * n;
   stage_rhs64<T, true>(a, rhs, vec_off(a, s, 0), seg_of(a, s), nullptr);
+  __syncthreads();  // rhs is complete before any lane updates it (also with no pulls)
   T part[kMaxRhs64];
 #pragma unroll
   for (int q = 0; q < kMaxRhs64; ++q) part[q] = T(0);
