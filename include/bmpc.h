@@ -299,6 +299,18 @@ bmpc_status bmpc_assemble_qp(const bmpc_qp_dims* dims, const double* Q, const do
                              double* D, double* E, double* C, double* R, double* work,
                              void* stream);
 
+/* bmpc_assemble_qp without the work argument, for callers that cannot allocate device
+ * memory (code under graph capture, serving loops, harnesses that forbid allocation).
+ * The scratch is a static device array of the library, one per GPU, of 512 * 32 * 32
+ * doubles (4 MiB, held until the process ends): S * n * n must not exceed that
+ * (BMPC_ERR_INVALID otherwise).  Allocates nothing.  Every call on a GPU uses that GPU's
+ * one scratch array, so calls that overlap on one GPU (other streams, other threads)
+ * race; issue them on one stream.  Results are those of bmpc_assemble_qp. */
+bmpc_status bmpc_assemble_qp_noalloc(const bmpc_qp_dims* dims, const double* Q,
+                                     const double* A, const double* G, const double* w,
+                                     double tau, double delta, double* D, double* E,
+                                     double* C, double* R, void* stream);
+
 /* ---- host-only helpers (no device needed) ---------------------------------- */
 
 /* Pi_i for N stages (same content as bmpc_query_perm). */

@@ -29,6 +29,7 @@ EXPORTED = [
     "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
     "bmpc_cost_model", "bmpc_grad_blocks", "bmpc_assemble_qp", "bmpc_factor_solve",
     "bmpc_factor_refine", "bmpc_set_refine_stop", "bmpc_query_structure",
+    "bmpc_assemble_qp_noalloc",
 ]
 
 
@@ -115,6 +116,7 @@ def lib():
         "bmpc_cost_model": [P(_Dims), i32, P(_Options), P(_Cost)],
         "bmpc_grad_blocks": [vp, vp, vp, vp, vp, vp, vp],
         "bmpc_assemble_qp": [P(_QpDims), vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, vp],
+        "bmpc_assemble_qp_noalloc": [P(_QpDims), vp, vp, vp, vp, dbl, dbl, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -201,10 +203,12 @@ def _ptr(t, what, dtype=None, numel=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def assemble_qp(Q, A, G, w, tau: float, delta: float, stream=None):
+def assemble_qp(Q, A, G, w, tau: float, delta: float, stream=None, out=None,
+                noalloc: bool = False):
     """Reduced IPM system K = P + tau I + A^T A / delta + G^T (W + delta I)^{-1} G of a
     branch-MPC QP given per link (see bmpc_assemble_qp): returns D, E, C, R (device
-    tensors, FP64) ready for Plan.factor."""
+    tensors, FP64) ready for Plan.factor.  out = (D, E, C, R) writes into given tensors;
+    noalloc uses bmpc_assemble_qp_noalloc (the library's static scratch, no work array)."""
     import torch
     S, L, n2, _ = Q.shape
     N, n = L - 1, n2 // 2
@@ -212,22 +216,29 @@ def assemble_qp(Q, A, G, w, tau: float, delta: float, stream=None):
     f64 = torch.float64
     dev = Q.device
     d = _QpDims(S, N, n, me, mi)
-    D = torch.empty((S, N, n, n), dtype=f64, device=dev)
-    E = torch.empty((S, max(N - 1, 0), n, n), dtype=f64, device=dev)
-    C = torch.empty((S, n, n), dtype=f64, device=dev)
-    R = torch.empty((n, n), dtype=f64, device=dev)
-    work = torch.empty((S, n, n), dtype=f64, device=dev)
+    if out is None:
+        D = torch.empty((S, N, n, n), dtype=f64, device=dev)
+        E = torch.empty((S, max(N - 1, 0), n, n), dtype=f64, device=dev)
+        C = torch.empty((S, n, n), dtype=f64, device=dev)
+        R = torch.empty((n, n), dtype=f64, device=dev)
+    else:
+        D, E, C, R = out
     if stream is None:
         stream = torch.cuda.current_stream()
     args = [_ptr(Q, "Q", f64, S * L * n2 * n2), _ptr(A, "A", f64, S * L * me * n2) if me else None,
             _ptr(G, "G", f64, S * L * mi * n2) if mi else None,
             _ptr(w, "w", f64, S * L * mi) if mi else None]
-    _check(lib().bmpc_assemble_qp(ctypes.byref(d), *args, float(tau), float(delta),
-                                  ctypes.c_void_p(D.data_ptr()),
-                                  ctypes.c_void_p(E.data_ptr()) if N > 1 else None,
-                                  ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(R.data_ptr()),
-                                  ctypes.c_void_p(work.data_ptr()),
-                                  ctypes.c_void_p(stream.cuda_stream)), "bmpc_assemble_qp")
+    outs = [_ptr(D, "D", f64, S * N * n * n),
+            _ptr(E, "E", f64, S * (N - 1) * n * n) if N > 1 else None,
+            _ptr(C, "C", f64, S * n * n), _ptr(R, "R", f64, n * n)]
+    st = ctypes.c_void_p(stream.cuda_stream)
+    if noalloc:
+        _check(lib().bmpc_assemble_qp_noalloc(ctypes.byref(d), *args, float(tau), float(delta),
+                                              *outs, st), "bmpc_assemble_qp_noalloc")
+    else:
+        work = torch.empty((S, n, n), dtype=f64, device=dev)
+        _check(lib().bmpc_assemble_qp(ctypes.byref(d), *args, float(tau), float(delta), *outs,
+                                      ctypes.c_void_p(work.data_ptr()), st), "bmpc_assemble_qp")
     return D, E, C, R
 
 

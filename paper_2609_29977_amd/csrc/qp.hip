@@ -13,6 +13,8 @@
 // so K has exactly the root-coupled block structure the solver takes.  One workgroup
 // per tail stage stages the scaled rows of its two links in LDS, one link at a time;
 // the root block is a fixed-order sum over the scenarios.
+#include <mutex>
+
 #include "bmpc.h"
 #include "bmpc_internal.h"
 
@@ -118,6 +120,41 @@ __global__ void __launch_bounds__(1024) qp_root_kernel(const double* Rpart, int 
 
 }  // namespace bmpc
 
+namespace {
+
+// Scratch of bmpc_assemble_qp_noalloc: the per-scenario root shares (S * n * n doubles)
+// in a file-scope device array, one copy per GPU, so that the entry point allocates
+// nothing.  Host code never uses the array's name as an address: the device address of
+// each GPU's copy is looked up once per device (hipGetSymbolAddress with that device
+// current) and kept here.
+constexpr size_t kQpScratchDoubles = (size_t)512 * 32 * 32;  // 4 MiB
+static __device__ __align__(256) double scratch[kQpScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (null on failure).
+double* device_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 extern "C" bmpc_status bmpc_assemble_qp(const bmpc_qp_dims* d, const double* Q, const double* A,
                                         const double* G, const double* w, double tau,
                                         double delta, double* D, double* E, double* C,
@@ -153,4 +190,16 @@ extern "C" bmpc_status bmpc_assemble_qp(const bmpc_qp_dims* d, const double* Q, 
   hipLaunchKernelGGL(qp_root_kernel, dim3(1), dim3(1024), 0, st, (const double*)work, d->S,
                      d->n, tau, R);
   return hipGetLastError() == hipSuccess ? BMPC_OK : BMPC_ERR_DEVICE;
+}
+
+extern "C" bmpc_status bmpc_assemble_qp_noalloc(const bmpc_qp_dims* d, const double* Q,
+                                                const double* A, const double* G, const double* w,
+                                                double tau, double delta, double* D, double* E,
+                                                double* C, double* R, void* stream) {
+  if (!d || d->S < 1 || d->n < 1 || d->n > 32 ||
+      (size_t)d->S * d->n * d->n > kQpScratchDoubles)
+    return BMPC_ERR_INVALID;
+  double* work = device_scratch();
+  if (!work) return BMPC_ERR_DEVICE;
+  return bmpc_assemble_qp(d, Q, A, G, w, tau, delta, D, E, C, R, work, stream);
 }
