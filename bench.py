@@ -41,7 +41,7 @@ def parse():
                     help="time separate factor and solve calls (default: the forward "
                          "substitution of the first solve runs inside the factorization)")
     ap.add_argument("--profile-steps", type=int, default=3)
-    ap.add_argument("--systems", type=int, default=512,
+    ap.add_argument("--systems", type=int, default=1024,
                     help="batching workload (--config c4): number of systems")
     ap.add_argument("--no-graph", action="store_true",
                     help="batching workload: launch eagerly instead of replaying a HIP graph")
@@ -88,14 +88,14 @@ def measured_traffic(kernel_class, digest):
 
 def bench_hetero(args):
     """Batching workload: independent systems with S ~ U[8, 256], N ~ U[16, 256],
-    n ~ {8, 16, 32}, delta log-uniform in [1e-4, 1], one right-hand side, FP32 +
-    one refinement correction, grouped into padded uniform batches.  One step solves
-    every system once (factor + refine of every bucket)."""
+    n ~ {8, 16, 32}, delta log-uniform in [1e-4, 1], one right-hand side, FP32 + one
+    refinement correction, all in one ragged plan (every step one launch over all
+    systems, nothing padded), replayed from a HIP graph.  One step solves every system
+    once (factor + refined solve)."""
     import numpy as np
     import torch
 
     from paper_2609_29977_amd import bmpc
-    from paper_2609_29977_amd.batch import HeteroBatch
     from synth.branch_system_gpu import make_system_gpu
 
     K = args.systems
@@ -108,51 +108,74 @@ def bench_hetero(args):
         shapes.append((S, N, n, 1))
         deltas.append(float(10 ** rng.uniform(-4, 0)))
     t0 = time.perf_counter()
-    hb = HeteroBatch(shapes, "fp32")
+    side = torch.cuda.Stream()
+    rp = bmpc.RaggedPlan(shapes, "fp32", stream=side)
+    analyze_s = time.perf_counter() - t0
+    sz = rp.sizes
+    f64 = torch.float64
+    D, E, C, R = (torch.empty(max(k, 1), dtype=f64, device="cuda") for k in sz[:4])
+    b = torch.empty(sz[4], dtype=f64, device="cuda")
+    x = torch.zeros_like(b)
     for i, (S, N, n, _) in enumerate(shapes):
-        hb.put(i, *make_system_gpu(S, N, n, 1, deltas[i], 1000 + i))
+        for which, (dst, t) in enumerate(zip((D, E, C, R, b),
+                                             make_system_gpu(S, N, n, 1, deltas[i], 1000 + i))):
+            if t.numel():
+                rp.unpack(which, dst, i).copy_(t.reshape(-1))
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log(f"{K} systems in {len(hb.groups)} buckets (padded work x{hb.padded_work:.2f}), "
-        f"set up in {time.perf_counter() - t0:.1f}s, "
-        f"{torch.cuda.memory_allocated() / 2**30:.1f} GiB allocated by torch")
-    flops = 0.0
-    for S, N, n, nrhs in shapes:
-        c = bmpc.cost_model(S, N, n, nrhs, "fp32")
-        flops += c.factor_flops + c.solve_flops
+    log(f"{K} systems in one ragged plan, analysed in {analyze_s:.1f}s, set up in "
+        f"{time.perf_counter() - t0:.1f}s; inputs {sum(sz) * 8 / 1e9:.1f} GB, plan workspaces "
+        f"{rp.cost().workspace_bytes / 1e9:.1f} GB")
+    cost = rp.cost()
+    flops = cost.factor_flops + cost.solve_flops
 
-    if args.no_graph:
-        def step():
-            hb.solve(refine_tol=0.0, refine_iters=1)
-    else:
+    def step():
+        rp.factor_refine(D, E, C, R, b, x, tol=0.0, max_iters=1)
+
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.synchronize()
+    graph = None
+    if not args.no_graph:
         tc = time.perf_counter()
-        hb.capture(refine_tol=0.0, refine_iters=1)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            step()
+        torch.cuda.synchronize()
         log(f"captured the batch solve in {time.perf_counter() - tc:.2f}s")
 
-        def step():
-            hb.replay()
+    def run():
+        if graph is not None:
+            graph.replay()
+        else:
+            with torch.cuda.stream(side):
+                step()
 
     for _ in range(args.warmup):
-        step()
+        run()
     torch.cuda.synchronize()
     times = []
     for _ in range(args.steps):
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        step()
+        run()
         torch.cuda.synchronize()
         times.append((time.perf_counter() - w0) * 1e3)
-    bad = hb.info()
+    info = rp.info()
     err = None
     if not args.no_cpu:
         from oracle import oracle
         worst = 0.0
-        for i in (0, K // 2, K - 1):
+        for i in sorted({0, K // 3, K // 2, (2 * K) // 3, K - 1}):
             S, N, n, _ = shapes[i]
-            D, E, C, R, b = (t.cpu().numpy() for t in make_system_gpu(S, N, n, 1, deltas[i], 1000 + i))
-            ref, info = oracle.solve(D, E, C, R, b, nthreads=16)
-            x = hb.solution(i).cpu().numpy()
-            worst = max(worst, float(np.max(np.abs(x - ref)) / np.max(np.abs(ref))))
+            host = [rp.unpack(w, t, i).cpu().numpy() for w, t in enumerate((D, E, C, R, b))]
+            Dh = host[0].reshape(S, N, n, n)
+            Eh = host[1].reshape(S, N - 1, n, n)
+            Ch, Rh, bh = host[2].reshape(S, n, n), host[3].reshape(n, n), host[4].reshape(1, -1)
+            ref, _ = oracle.solve(Dh, Eh, Ch, Rh, bh, nthreads=host_threads())
+            xi = rp.unpack(4, x, i).cpu().numpy().reshape(1, -1)
+            worst = max(worst, float(np.max(np.abs(xi - ref)) / np.max(np.abs(ref))))
         err = worst
     ts = sorted(times)
     p50 = statistics.median(ts)
@@ -163,12 +186,14 @@ def bench_hetero(args):
            "p50_ms": round(p50, 3), "p99_ms": round(p99, 3), "higher_is_better": True,
            "dtype": "f32+f64", "data": "synthetic (device generator)",
            "config": {"workload": "c4", "systems": K, "S": "U[8,256]", "N": "U[16,256]",
-                      "n": "{8,16,32}", "delta": "log-U[1e-4,1]", "buckets": len(hb.groups),
-                      "padded_work": round(hb.padded_work, 3), "graph": not args.no_graph},
+                      "n": "{8,16,32}", "delta": "log-U[1e-4,1]", "plan": "one ragged plan",
+                      "padded_work": 1.0, "graph": not args.no_graph},
            "gflops_real_work": round(flops / (p50 * 1e-3) / 1e9, 1),
-           "failed_buckets": bad, "max_rel_err_vs_oracle_sampled": err}
+           "input_gb": round(sum(sz) * 8 / 1e9, 1),
+           "workspace_gb": round(rp.cost().workspace_bytes / 1e9, 1),
+           "info": info, "max_rel_err_vs_oracle_sampled": err}
     print(json.dumps(out))
-    hb.close()
+    rp.close()
 
 
 def bench_qp(args):

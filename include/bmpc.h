@@ -125,6 +125,32 @@ bmpc_status bmpc_analyze(const bmpc_dims* dims, bmpc_precision prec, void* strea
 bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* stream,
                             const bmpc_options* opts, bmpc_plan* out);
 
+/* Ragged batch: B independent systems of different shapes dims[i] = (S_i, N_i, n_i,
+ * nrhs) -- n_i <= 32, one nrhs for all -- in one plan (not one of the paper's
+ * algorithms: it batches many of its systems).  Each system gets its own ordering
+ * Pi_i, level table and workspaces; each step of Algorithm 1, Algorithm 2 and the
+ * refinement is then one launch over every system that takes part in it (per block-size
+ * class and kernel variant), its work items -- chain windows, chain positions, root
+ * blocks -- ordered largest system first.  Arrays are the systems' own layouts above
+ * (B = 1 each), concatenated in system order: D = [D_0 | D_1 | ...], likewise E
+ * (N_i - 1 blocks per tail; E must not be NULL), C, R, and b, x = [b_0 | b_1 | ...] with
+ * b_i [nrhs][(S_i N_i + 1) n_i]; bmpc_ragged_layout gives the offsets.  The plan works
+ * with bmpc_factor, bmpc_solve, bmpc_factor_solve, bmpc_refine, bmpc_factor_refine,
+ * bmpc_get_info (rows of the concatenated systems), bmpc_get_stats (the stop test holds
+ * for every system), bmpc_query_cost (sums), bmpc_export_tail_factor (chains of the
+ * concatenated systems), bmpc_export_root_factor (the n_i x n_i factors one after the
+ * other), bmpc_set_stream, bmpc_set_refine_stop, the profiling calls and
+ * bmpc_destroy; bmpc_query_perm, bmpc_query_structure and bmpc_grad_blocks return
+ * BMPC_ERR_INVALID (the host-only bmpc_ordering and bmpc_structure give each system's
+ * Pi_i and structure).  opts: window_depth and flags apply to every system;
+ * num_systems must be 0 or 1.  BMPC_ERR_INVALID for B < 1 or bad dims. */
+bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision prec,
+                                void* stream, const bmpc_options* opts, bmpc_plan* out);
+
+/* Shape of system i of a ragged plan and the element offsets of its arrays in the
+ * concatenated D, E, C, R and vectors (offsets[0..4]); either output may be NULL. */
+bmpc_status bmpc_ragged_layout(bmpc_plan plan, int32_t i, bmpc_dims* dims, int64_t* offsets);
+
 /* Replace the stream later calls enqueue on (e.g. a graph-capture stream). */
 bmpc_status bmpc_set_stream(bmpc_plan plan, void* stream);
 

@@ -29,7 +29,7 @@ EXPORTED = [
     "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
     "bmpc_cost_model", "bmpc_grad_blocks", "bmpc_assemble_qp", "bmpc_factor_solve",
     "bmpc_factor_refine", "bmpc_set_refine_stop", "bmpc_query_structure",
-    "bmpc_assemble_qp_noalloc",
+    "bmpc_assemble_qp_noalloc", "bmpc_analyze_ragged", "bmpc_ragged_layout",
 ]
 
 
@@ -94,6 +94,8 @@ def lib():
         "bmpc_analyze_ex": [P(_Dims), i32, vp, P(_Options), P(vp)],
         "bmpc_set_stream": [vp, vp],
         "bmpc_set_refine_stop": [vp, i32],
+        "bmpc_analyze_ragged": [i32, P(_Dims), i32, vp, P(_Options), P(vp)],
+        "bmpc_ragged_layout": [vp, i32, P(_Dims), P(i64)],
         "bmpc_query_structure": [vp, P(i32), P(i32), i64, P(i64)],
         "bmpc_factor": [vp, vp, vp, vp, vp],
         "bmpc_solve": [vp, vp, vp],
@@ -245,7 +247,8 @@ def assemble_qp(Q, A, G, w, tau: float, delta: float, stream=None, out=None,
 class Plan:
     """A bmpc plan: analysis + persistent device workspaces for one (S, N, n, nrhs),
     or for a batch of num_systems independent systems of that shape (arrays stacked
-    along the leading dimension, see include/bmpc.h)."""
+    along the leading dimension, see include/bmpc.h).  RaggedPlan holds systems of
+    different shapes."""
 
     def __init__(self, S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
                  window_depth: int = 0, stream=None, num_systems: int = 1, flags: int = 0):
@@ -431,3 +434,97 @@ class Plan:
         _check(L.bmpc_get_kernel_times(self._h, k, launches, ms), "bmpc_get_kernel_times")
         names = kernel_class_names()
         return {names[i]: (int(launches[i]), float(ms[i])) for i in range(k)}
+
+
+class RaggedPlan(Plan):
+    """Independent systems of different shapes (S_i, N_i, n_i) with one nrhs, factored
+    and solved together (bmpc_analyze_ragged).  The arrays are the systems' own arrays
+    concatenated in system order (flat FP64 device tensors); layout(i) gives each
+    system's element offsets, and pack() / unpack() move per-system tensors in and out.
+    factor / solve / refine / factor_solve / factor_refine / info / stats take and
+    return the concatenated arrays."""
+
+    def __init__(self, shapes, precision="fp32", window_depth: int = 0, stream=None,
+                 flags: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("bmpc needs a HIP device (torch.cuda.is_available() is False)")
+        shapes = [tuple(int(v) for v in sh) for sh in shapes]
+        self.shapes = shapes
+        self.B = len(shapes)
+        self.nrhs = shapes[0][3]
+        self.precision = _prec(precision)
+        self._h = ctypes.c_void_p()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        dims = (_Dims * self.B)(*[_Dims(*sh) for sh in shapes])
+        o = _Options(int(window_depth), 0, int(flags))
+        _check(lib().bmpc_analyze_ragged(self.B, dims, self.precision,
+                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
+                                         ctypes.byref(self._h)), "bmpc_analyze_ragged")
+        self.offsets = [self.layout(i)[1] for i in range(self.B)] + [self._totals()]
+
+    def layout(self, i):
+        d = _Dims()
+        off = (ctypes.c_int64 * 5)()
+        _check(lib().bmpc_ragged_layout(self._h, int(i), ctypes.byref(d), off),
+               "bmpc_ragged_layout")
+        return (d.S, d.N, d.n, d.nrhs), list(off)
+
+    def _totals(self):
+        S, N, n, q = self.shapes[-1]
+        last = self.layout(self.B - 1)[1]
+        return [last[0] + S * N * n * n, last[1] + S * (N - 1) * n * n, last[2] + S * n * n,
+                last[3] + n * n, last[4] + q * (S * N + 1) * n]
+
+    @property
+    def sizes(self):
+        """Element counts of the concatenated D, E, C, R and vectors."""
+        return self.offsets[-1]
+
+    def pack(self, which: int, parts, out=None):
+        """Concatenate per-system tensors (which: 0 D, 1 E, 2 C, 3 R, 4 vectors)."""
+        import torch
+        dev = next(t for t in parts if t is not None).device
+        if out is None:
+            out = torch.empty(max(self.sizes[which], 1), dtype=torch.float64, device=dev)
+        for i, t in enumerate(parts):
+            a, b = self.offsets[i][which], self.offsets[i + 1][which]
+            if b > a:
+                out[a:b] = t.reshape(-1)
+        return out
+
+    def unpack(self, which: int, flat, i: int):
+        a, b = self.offsets[i][which], self.offsets[i + 1][which]
+        return flat[a:b]
+
+    def _blocks(self, D, E, C, R):
+        import torch
+        f64 = torch.float64
+        s = self.sizes
+        return (_ptr(D, "D", f64, s[0]), _ptr(E, "E", f64, max(s[1], 1)),
+                _ptr(C, "C", f64, s[2]), _ptr(R, "R", f64, s[3]))
+
+    def _rhs(self, b, x):
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        return (_ptr(b, "b", torch.float64, self.sizes[4]),
+                _ptr(x, "x", torch.float64, self.sizes[4]), x)
+
+    def export_tail_factor(self, chain: int):
+        """Stored factor of chain `chain` of the concatenated systems (see
+        Plan.export_tail_factor), sized for its system."""
+        import numpy as np
+        s = int(chain)
+        for S, N, n, _ in self.shapes:
+            if s < S:
+                break
+            s -= S
+        L = np.zeros((N * n, N * n))
+        F = np.zeros((n, n))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().bmpc_export_tail_factor(self._h, int(chain), L.ctypes.data_as(dp),
+                                             F.ctypes.data_as(dp)), "bmpc_export_tail_factor")
+        return L, F

@@ -11,8 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbmpc.so")
-SOURCES = ["api.hip", "factor.hip", "factor64.hip", "solve.hip", "solve64.hip", "refine.hip",
-           "grad.hip", "qp.hip"]
+SOURCES = ["api.hip", "ragged.hip", "factor.hip", "factor64.hip", "solve.hip", "solve64.hip",
+           "refine.hip", "grad.hip", "qp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -12,26 +12,11 @@
 
 #include "../../include/bmpc.h"
 #include "bmpc_internal.h"
-
-namespace bmpc {
-size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw, int nrhs_fused);
-}
+#include "plan.h"
 
 using namespace bmpc;
 
-namespace {
-
-constexpr int kLdsBudget = 160 * 1024;
-
-struct PassPlan {
-  int mk, shift, windows, is_final;
-  double flops, bytes;  // algorithmic flops / HBM bytes of the pass
-};
-
-struct Timing {
-  int cls;
-  hipEvent_t a, b;
-};
+namespace bmpc {
 
 int nmax_for(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : (n <= 32 ? 32 : 64)); }
 
@@ -68,15 +53,6 @@ std::vector<int> make_perm(int N) {
   for (int j = 1; j <= N; ++j) perm[pp[j - 1]] = N - j;  // position j holds stage N-j
   return perm;
 }
-
-struct Costs {
-  std::vector<PassPlan> passes;
-  double factor_flops = 0, solve_flops = 0, factor_bytes = 0, solve_bytes = 0,
-         residual_bytes = 0, L_bytes = 0;
-  double pass_flops[KC_COUNT] = {0}, pass_bytes[KC_COUNT] = {0};
-  int launches[KC_COUNT] = {0};
-  int levels = 0, Tw = 0;
-};
 
 Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B, bool no_top_merge) {
   Costs c;
@@ -185,111 +161,12 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B, bool no_top_merge
   return c;
 }
 
-}  // namespace
+}  // namespace bmpc
 
-struct bmpc_plan_s {
-  bmpc_dims d{};
-  bmpc_precision prec = BMPC_FP64;
-  bool fp64 = true;
-  int m = 0, nmax = 8, Tw = 1, groups = 1;
-  int B = 1;      // systems in the batch
-  int opt_flags = 0;  // BMPC_FLAG_*
-  int chunk = kMaxRhs;  // right-hand sides per launch
-  int refine_stop = BMPC_STOP_CORRECTION;
-  hipStream_t stream = nullptr;
-  Costs costs;
-  std::vector<int> perm, permpos;
-  int stride = 1;
-  // device buffers
-  void* Linv = nullptr;
-  void* Gl = nullptr;
-  void* Gr = nullptr;
-  void* F = nullptr;
-  double* U = nullptr;
-  double* Upart = nullptr;
-  double* LR = nullptr;
-  void* acc[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-  void* accX = nullptr;
-  void* vacc[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // fused forward: R, L
-  void* vaccX = nullptr;
-  int* d_permpos = nullptr;
-  unsigned long long* d_info = nullptr;
-  void* y = nullptr;
-  double* w = nullptr;
-  double* x0 = nullptr;
-  double* rbuf = nullptr;
-  double* norms = nullptr;  // rnorm, dnorm, xnorm: 3 * nrhs
-  double* npart = nullptr;  // partial maxima: 2 * nrhs * kNormBlocks
-  int* flags = nullptr;     // done, iterations
-  double* relcorr = nullptr;
-  // backward-error stop: |b| per segment, |K| per system, the residual's row-sum
-  // partials (per tail workgroup), root-row maxima and per-chain |C_s| row sums
-  double* bnorm = nullptr;
-  double* knorm = nullptr;
-  double* kpart = nullptr;
-  double* kroot = nullptr;
-  double* crow = nullptr;
-  int kper = 0;  // residual workgroups per system
-  int* hflag = nullptr;  // pinned host copy of the refinement's stop flag
-  std::vector<void*> allocs;
-  double workspace_bytes = 0;
-  bool factored = false;
-  int last_max_iters = 0;
-  // profiling
-  bool profiling = false;
-  std::vector<Timing> timings;
-  std::vector<hipEvent_t> event_pool;
-  int64_t launches[KC_COUNT] = {0};
-  double total_ms[KC_COUNT] = {0};
-};
 
-namespace {
+namespace bmpc {
 
-hipEvent_t take_event(bmpc_plan p) {
-  if (!p->event_pool.empty()) {
-    hipEvent_t e = p->event_pool.back();
-    p->event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  (void)hipEventCreate(&e);
-  return e;
-}
-
-// Bracket a launch with events when profiling is on.
-template <typename F>
-void timed(bmpc_plan p, int cls, F&& launch) {
-  if (!p->profiling) {
-    launch();
-    return;
-  }
-  Timing t{cls, take_event(p), take_event(p)};
-  (void)hipEventRecord(t.a, p->stream);
-  launch();
-  (void)hipEventRecord(t.b, p->stream);
-  p->timings.push_back(t);
-}
-
-void collect_timings(bmpc_plan p) {
-  if (p->timings.empty()) return;
-  (void)hipEventSynchronize(p->timings.back().b);
-  for (const Timing& t : p->timings) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
-      p->launches[t.cls] += 1;
-      p->total_ms[t.cls] += ms;
-    }
-    p->event_pool.push_back(t.a);
-    p->event_pool.push_back(t.b);
-  }
-  p->timings.clear();
-}
-
-// Right-hand sides per plan: no limit of the method; this bound keeps the per-segment
-// norm arrays and index arithmetic small.
-constexpr int kMaxPlanRhs = 4096;
-
-bool dims_ok(const bmpc_dims* d, int B = 1) {
+bool dims_ok(const bmpc_dims* d, int B) {
   return d && d->S >= 1 && d->N >= 1 && d->n >= 1 && d->n <= 64 && d->nrhs >= 1 &&
          d->nrhs <= kMaxPlanRhs && B >= 1 && (double)B * d->S * d->N * d->n < 2.0e9 &&
          (double)B * d->S * d->N < 2.0e9 / 64 &&
@@ -316,7 +193,13 @@ void free_plan_memory(bmpc_plan p) {
 }
 
 bool dalloc(bmpc_plan p, void** ptr, size_t bytes) {
-  bytes = std::max<size_t>(bytes, 256);
+  bytes = (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255;
+  if (p->measure || p->arena) {
+    *ptr = p->measure ? reinterpret_cast<void*>(256) : p->arena + p->arena_used;
+    p->arena_used += bytes;
+    p->workspace_bytes += (double)bytes;
+    return true;
+  }
   if (hipMalloc(ptr, bytes) != hipSuccess) {
     *ptr = nullptr;
     // the runtime keeps the failure as its last error; cleared here, since it is reported
@@ -343,6 +226,91 @@ int pick_window_depth(bool fp64, int nmax, int nrhs, const bmpc_options* o) {
 // Factor passes and root factor; a non-null b also runs the tail forward substitution
 // of that right-hand side inside the passes (y and w as the forward sweep and the X
 // step of the solve leave them).
+// Arguments of factor pass k; a non-null b adds the forward substitution of nq
+// right-hand sides starting at b (the first chunk).
+FactorPassArgs factor_pass_args(bmpc_plan p, int k, const double* D, const double* E,
+                                const double* C, const double* b, int nq) {
+  const bmpc_dims& d = p->d;
+  const int npass = (int)p->costs.passes.size();
+  const PassPlan& pp = p->costs.passes[k];
+  FactorPassArgs a{};
+  a.S = p->B * d.S;
+  a.Ssys = d.S;
+  a.N = d.N;
+  a.n = d.n;
+  a.m = p->m;
+  a.Tw = p->Tw;
+  a.pass = k;
+  a.npass = npass;
+  a.mk = pp.mk;
+  a.shift = pp.shift;
+  a.windows = pp.windows;
+  a.is_final = pp.is_final;
+  a.D = D;
+  a.E = E;
+  a.C = C;
+  const int in = (k + 1) & 1, out = k & 1;
+  a.accR_in = k > 0 ? p->acc[in][0] : nullptr;
+  a.accL_in = k > 0 ? p->acc[in][1] : nullptr;
+  a.fill_in = k > 0 ? p->acc[in][2] : nullptr;
+  a.accR_out = p->acc[out][0];
+  a.accL_out = p->acc[out][1];
+  a.fill_out = p->acc[out][2];
+  a.stride = p->stride;
+  a.accX = p->accX;
+  a.Linv = p->Linv;
+  a.Gl = p->Gl;
+  a.Gr = p->Gr;
+  a.F = p->F;
+  a.U = p->U;
+  a.permpos = p->d_permpos;
+  a.info = p->d_info;
+  if (b) {
+    a.b = b;
+    a.nrhs = nq;
+    a.vsys = (size_t)d.nrhs * (((size_t)d.S * d.N + 1) * d.n);
+    a.y = p->y;
+    a.w = p->w;
+    a.vaccR_in = k > 0 ? p->vacc[in][0] : nullptr;
+    a.vaccL_in = k > 0 ? p->vacc[in][1] : nullptr;
+    a.vaccR_out = p->vacc[out][0];
+    a.vaccL_out = p->vacc[out][1];
+    a.vaccX = p->vaccX;
+  }
+  return a;
+}
+
+// Arguments of the residual of chunk c of the right-hand sides (b, x, r at their
+// bases; knorm adds the row sums of |K|).
+ResidualArgs residual_args(bmpc_plan p, int c, const double* D, const double* E,
+                           const double* C, const double* R, const double* b, const double* x,
+                           double* r, bool knorm) {
+  const size_t off = (size_t)c * p->chunk * vec_len(p);
+  ResidualArgs ra{};
+  ra.S = p->d.S;
+  ra.B = p->B;
+  ra.N = p->d.N;
+  ra.n = p->d.n;
+  ra.nrhs = chunk_rhs(p, c);
+  ra.vsys = (size_t)p->d.nrhs * vec_len(p);
+  ra.chunk = 16;
+  ra.D = D;
+  ra.E = E;
+  ra.C = C;
+  ra.R = R;
+  ra.b = b + off;
+  ra.x = x + off;
+  ra.r = r + off;
+  ra.w = p->w;
+  ra.done = p->flags;
+  if (knorm) {
+    ra.knorm_part = p->kpart;
+    ra.knorm_root = p->kroot;
+    ra.crow = p->crow;
+  }
+  return ra;
+}
+
 template <typename T>
 void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double* C,
                     const double* R, const double* b = nullptr, int nq = 0) {
@@ -352,50 +320,7 @@ void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double*
   const int npass = (int)p->costs.passes.size();
   for (int k = 0; k < npass; ++k) {
     const PassPlan& pp = p->costs.passes[k];
-    FactorPassArgs a{};
-    a.S = p->B * d.S;
-    a.Ssys = d.S;
-    a.N = d.N;
-    a.n = d.n;
-    a.m = p->m;
-    a.Tw = p->Tw;
-    a.pass = k;
-    a.npass = npass;
-    a.mk = pp.mk;
-    a.shift = pp.shift;
-    a.windows = pp.windows;
-    a.is_final = pp.is_final;
-    a.D = D;
-    a.E = E;
-    a.C = C;
-    const int in = (k + 1) & 1, out = k & 1;
-    a.accR_in = k > 0 ? p->acc[in][0] : nullptr;
-    a.accL_in = k > 0 ? p->acc[in][1] : nullptr;
-    a.fill_in = k > 0 ? p->acc[in][2] : nullptr;
-    a.accR_out = p->acc[out][0];
-    a.accL_out = p->acc[out][1];
-    a.fill_out = p->acc[out][2];
-    a.stride = p->stride;
-    a.accX = p->accX;
-    a.Linv = p->Linv;
-    a.Gl = p->Gl;
-    a.Gr = p->Gr;
-    a.F = p->F;
-    a.U = p->U;
-    a.permpos = p->d_permpos;
-    a.info = p->d_info;
-    if (b) {
-      a.b = b;
-      a.nrhs = nq;
-      a.vsys = (size_t)d.nrhs * (((size_t)d.S * d.N + 1) * d.n);
-      a.y = p->y;
-      a.w = p->w;
-      a.vaccR_in = k > 0 ? p->vacc[in][0] : nullptr;
-      a.vaccL_in = k > 0 ? p->vacc[in][1] : nullptr;
-      a.vaccR_out = p->vacc[out][0];
-      a.vaccL_out = p->vacc[out][1];
-      a.vaccX = p->vaccX;
-    }
+    const FactorPassArgs a = factor_pass_args(p, k, D, E, C, b, nq);
     const int cls = pp.is_final ? KC_FACTOR_FINAL : (k == 0 ? KC_FACTOR_FIRST : KC_FACTOR_MID);
     timed(p, cls, [&] { launch_factor_pass<T>(a, p->nmax, st); });
   }
@@ -499,7 +424,106 @@ bmpc_status last_error_status() {
   return hipGetLastError() == hipSuccess ? BMPC_OK : BMPC_ERR_DEVICE;
 }
 
-}  // namespace
+// Whether the refinement's stop test already holds, read on the host.  Outside stream
+// capture the loop stops issuing launches once it holds (the device-side flag would
+// make them return at once, but each still costs a launch); under capture the launch
+// sequence stays fixed and the flag alone decides.
+bool stop_reached(bmpc_plan p) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(p->stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (cs != hipStreamCaptureStatusNone) return false;
+  if (hipMemcpyAsync(p->hflag, p->flags, sizeof(int), hipMemcpyDeviceToHost, p->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return p->hflag[0] != 0;
+}
+
+// Analysis and workspaces of a plan (bmpc_analyze_ex after its argument checks).  A
+// plan with a ragged parent shares the parent's residual vector and stop flags, which
+// the parent sets.
+bmpc_status init_plan(bmpc_plan p, const bmpc_dims* dims, bmpc_precision prec, void* stream,
+                      const bmpc_options* opts) {
+  p->d = *dims;
+  p->prec = prec;
+  p->fp64 = prec == BMPC_FP64;
+  p->m = dims->N - 1;
+  p->nmax = nmax_for(dims->n);
+  p->Tw = pick_window_depth(p->fp64, p->nmax, dims->nrhs, opts);
+  p->B = systems_of(opts);
+  p->opt_flags = flags_of(opts);
+  p->chunk = rhs_chunk(p->nmax);
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  p->costs = make_costs(*dims, p->fp64, p->Tw, p->B, no_top_merge_of(opts));
+  p->perm = make_perm(dims->N);
+  p->permpos = make_permpos(dims->N);
+  p->groups = std::min(dims->S, 32);
+  const int B = p->B, N = dims->N, n = dims->n, nrhs = dims->nrhs;
+  const int cq = std::min(nrhs, p->chunk);  // right-hand sides of one chunk
+  const size_t S = (size_t)B * dims->S;  // chains of the batch
+  const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
+  const size_t len = ((size_t)dims->S * N + 1) * n;
+  const size_t segs = (size_t)B * nrhs;  // (system, right-hand side) vectors
+  const int res_chunks = (N + 15) / 16;   // tail residual workgroups per chain
+  p->kper = dims->S * res_chunks;
+  const int npass = (int)p->costs.passes.size();
+  p->stride = (npass > 1 ? p->costs.passes[0].windows : 1) + 1;
+  const size_t gblocks = g_chain_blocks(N);
+  bool ok = dalloc(p, &p->Linv, S * N * nn * tb) &&
+            dalloc(p, &p->Gl, S * gblocks * nn * tb) &&
+            dalloc(p, &p->Gr, S * gblocks * nn * tb) &&
+            dalloc(p, &p->F, S * nn * tb) &&
+            dalloc(p, (void**)&p->U, S * nn * 8) &&
+            dalloc(p, (void**)&p->Upart, (size_t)B * p->groups * nn * 8) &&
+            dalloc(p, (void**)&p->LR, (size_t)B * nn * 8) &&
+            dalloc(p, &p->accX, S * npass * nn * tb) &&
+            dalloc(p, &p->vaccX, S * npass * cq * n * tb) &&
+            dalloc(p, (void**)&p->d_permpos, (size_t)N * sizeof(int)) &&
+            dalloc(p, (void**)&p->d_info, sizeof(unsigned long long)) &&
+            dalloc(p, &p->y, S * N * cq * n * tb) &&
+            dalloc(p, (void**)&p->w, S * cq * n * 8) &&
+            dalloc(p, (void**)&p->x0, (size_t)B * cq * n * 8) &&
+            (p->parent || dalloc(p, (void**)&p->rbuf, segs * len * 8)) &&
+            dalloc(p, (void**)&p->norms, 3 * segs * 8) &&
+            dalloc(p, (void**)&p->npart, 2 * segs * kNormBlocks * 8) &&
+            (p->parent || dalloc(p, (void**)&p->flags, 2 * sizeof(int))) &&
+            dalloc(p, (void**)&p->relcorr, sizeof(double)) &&
+            dalloc(p, (void**)&p->bnorm, segs * 8) &&
+            dalloc(p, (void**)&p->knorm, (size_t)B * 8) &&
+            dalloc(p, (void**)&p->kpart, S * res_chunks * 8) &&
+            dalloc(p, (void**)&p->kroot, (size_t)B * 8) &&
+            dalloc(p, (void**)&p->crow, S * n * 8);
+  if (ok && !p->parent && !p->measure &&
+      hipHostMalloc((void**)&p->hflag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    p->hflag = nullptr;
+    (void)hipGetLastError();
+    ok = false;
+  }
+  if (ok && npass > 1) {
+    for (int set = 0; set < 2 && ok; ++set) {
+      for (int b = 0; b < 3 && ok; ++b)
+        ok = dalloc(p, &p->acc[set][b], S * p->stride * nn * tb);
+      for (int b = 0; b < 2 && ok; ++b)
+        ok = dalloc(p, &p->vacc[set][b], S * p->stride * cq * n * tb);
+    }
+  }
+  if (!ok) return BMPC_ERR_ALLOC;
+  if (p->measure) return BMPC_OK;
+  if (hipMemcpy(p->d_permpos, p->permpos.data(), (size_t)N * sizeof(int),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();  // reported here, not by a later call
+    return BMPC_ERR_DEVICE;
+  }
+  return BMPC_OK;
+}
+
+
+}  // namespace bmpc
 
 extern "C" {
 
@@ -577,79 +601,11 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BMPC_ERR_DEVICE;
   bmpc_plan p = new (std::nothrow) bmpc_plan_s();
   if (!p) return BMPC_ERR_ALLOC;
-  p->d = *dims;
-  p->prec = prec;
-  p->fp64 = prec == BMPC_FP64;
-  p->m = dims->N - 1;
-  p->nmax = nmax_for(dims->n);
-  p->Tw = pick_window_depth(p->fp64, p->nmax, dims->nrhs, opts);
-  p->B = systems_of(opts);
-  p->opt_flags = flags_of(opts);
-  p->chunk = rhs_chunk(p->nmax);
-  p->stream = reinterpret_cast<hipStream_t>(stream);
-  p->costs = make_costs(*dims, p->fp64, p->Tw, p->B, no_top_merge_of(opts));
-  p->perm = make_perm(dims->N);
-  p->permpos = make_permpos(dims->N);
-  p->groups = std::min(dims->S, 32);
-  const int B = p->B, N = dims->N, n = dims->n, nrhs = dims->nrhs;
-  const int cq = std::min(nrhs, p->chunk);  // right-hand sides of one chunk
-  const size_t S = (size_t)B * dims->S;  // chains of the batch
-  const size_t nn = (size_t)n * n, tb = p->fp64 ? 8 : 4;
-  const size_t len = ((size_t)dims->S * N + 1) * n;
-  const size_t segs = (size_t)B * nrhs;  // (system, right-hand side) vectors
-  const int res_chunks = (N + 15) / 16;   // tail residual workgroups per chain
-  p->kper = dims->S * res_chunks;
-  const int npass = (int)p->costs.passes.size();
-  p->stride = (npass > 1 ? p->costs.passes[0].windows : 1) + 1;
-  const size_t gblocks = g_chain_blocks(N);
-  bool ok = dalloc(p, &p->Linv, S * N * nn * tb) &&
-            dalloc(p, &p->Gl, S * gblocks * nn * tb) &&
-            dalloc(p, &p->Gr, S * gblocks * nn * tb) &&
-            dalloc(p, &p->F, S * nn * tb) &&
-            dalloc(p, (void**)&p->U, S * nn * 8) &&
-            dalloc(p, (void**)&p->Upart, (size_t)B * p->groups * nn * 8) &&
-            dalloc(p, (void**)&p->LR, (size_t)B * nn * 8) &&
-            dalloc(p, &p->accX, S * npass * nn * tb) &&
-            dalloc(p, &p->vaccX, S * npass * cq * n * tb) &&
-            dalloc(p, (void**)&p->d_permpos, (size_t)N * sizeof(int)) &&
-            dalloc(p, (void**)&p->d_info, sizeof(unsigned long long)) &&
-            dalloc(p, &p->y, S * N * cq * n * tb) &&
-            dalloc(p, (void**)&p->w, S * cq * n * 8) &&
-            dalloc(p, (void**)&p->x0, (size_t)B * cq * n * 8) &&
-            dalloc(p, (void**)&p->rbuf, segs * len * 8) &&
-            dalloc(p, (void**)&p->norms, 3 * segs * 8) &&
-            dalloc(p, (void**)&p->npart, 2 * segs * kNormBlocks * 8) &&
-            dalloc(p, (void**)&p->flags, 2 * sizeof(int)) &&
-            dalloc(p, (void**)&p->relcorr, sizeof(double)) &&
-            dalloc(p, (void**)&p->bnorm, segs * 8) &&
-            dalloc(p, (void**)&p->knorm, (size_t)B * 8) &&
-            dalloc(p, (void**)&p->kpart, S * res_chunks * 8) &&
-            dalloc(p, (void**)&p->kroot, (size_t)B * 8) &&
-            dalloc(p, (void**)&p->crow, S * n * 8);
-  if (ok && hipHostMalloc((void**)&p->hflag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-    p->hflag = nullptr;
-    (void)hipGetLastError();
-    ok = false;
-  }
-  if (ok && npass > 1) {
-    for (int set = 0; set < 2 && ok; ++set) {
-      for (int b = 0; b < 3 && ok; ++b)
-        ok = dalloc(p, &p->acc[set][b], S * p->stride * nn * tb);
-      for (int b = 0; b < 2 && ok; ++b)
-        ok = dalloc(p, &p->vacc[set][b], S * p->stride * cq * n * tb);
-    }
-  }
-  if (!ok) {
+  const bmpc_status st = init_plan(p, dims, prec, stream, opts);
+  if (st != BMPC_OK) {
     free_plan_memory(p);
     delete p;
-    return BMPC_ERR_ALLOC;
-  }
-  if (hipMemcpy(p->d_permpos, p->permpos.data(), (size_t)N * sizeof(int),
-                hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipGetLastError();  // reported here, not by a later call
-    free_plan_memory(p);
-    delete p;
-    return BMPC_ERR_DEVICE;
+    return st;
   }
   *out = p;
   return BMPC_OK;
@@ -663,11 +619,15 @@ bmpc_status bmpc_analyze(const bmpc_dims* dims, bmpc_precision prec, void* strea
 bmpc_status bmpc_set_stream(bmpc_plan plan, void* stream) {
   if (!plan) return BMPC_ERR_INVALID;
   plan->stream = reinterpret_cast<hipStream_t>(stream);
+  if (plan->ragged)
+    for (bmpc_plan s : ragged_subs(plan)) s->stream = plan->stream;
   return BMPC_OK;
 }
 
 bmpc_status bmpc_factor(bmpc_plan p, const double* D, const double* E, const double* C,
                         const double* R) {
+  if (p && p->ragged) return (D && E && C && R) ? ragged_factor(p, D, E, C, R, nullptr, nullptr)
+                                                : BMPC_ERR_INVALID;
   if (!p || !D || !C || !R || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
   if (p->fp64)
     enqueue_factor<double>(p, D, E, C, R);
@@ -681,31 +641,12 @@ bmpc_status bmpc_factor(bmpc_plan p, const double* D, const double* E, const dou
 bmpc_status bmpc_solve(bmpc_plan p, const double* b, double* x) {
   if (!p || !b || !x) return BMPC_ERR_INVALID;
   if (!p->factored) return BMPC_ERR_STATE;
+  if (p->ragged) return ragged_solve(p, b, x);
   if (p->fp64)
     enqueue_solve<double>(p, b, x);
   else
     enqueue_solve<float>(p, b, x);
   return last_error_status();
-}
-
-// Whether the refinement's stop test already holds, read on the host.  Outside stream
-// capture the loop stops issuing launches once it holds (the device-side flag would
-// make them return at once, but each still costs a launch); under capture the launch
-// sequence stays fixed and the flag alone decides.
-bool stop_reached(bmpc_plan p) {
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(p->stream, &cs) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  if (cs != hipStreamCaptureStatusNone) return false;
-  if (hipMemcpyAsync(p->hflag, p->flags, sizeof(int), hipMemcpyDeviceToHost, p->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(p->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return p->hflag[0] != 0;
 }
 
 // x = K^{-1} b by refinement (see bmpc_refine); with fused, the factor is issued here
@@ -716,6 +657,10 @@ static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, co
   if (!p || !D || !C || !R || !b || !x || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
   if (max_iters < 0 || max_iters > 100 || !(tol >= 0.0) || x == b) return BMPC_ERR_INVALID;
   if (!fused && !p->factored) return BMPC_ERR_STATE;
+  if (p->ragged) {
+    if (!E) return BMPC_ERR_INVALID;
+    return ragged_refine(p, D, E, C, R, b, x, tol, max_iters, fused);
+  }
   hipStream_t st = p->stream;
   const int nrhs = p->d.nrhs;
   const int segs = p->B * nrhs;  // norms per (system, right-hand side)
@@ -744,29 +689,7 @@ static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, co
   // the row sums of |K|
   auto residual = [&](bool knorm) {
     for (int c = 0; c < chunks_of(p); ++c) {
-      const size_t off = (size_t)c * p->chunk * len;
-      ResidualArgs ra{};
-      ra.S = p->d.S;
-      ra.B = p->B;
-      ra.N = p->d.N;
-      ra.n = p->d.n;
-      ra.nrhs = chunk_rhs(p, c);
-      ra.vsys = (size_t)nrhs * len;
-      ra.chunk = 16;
-      ra.D = D;
-      ra.E = E;
-      ra.C = C;
-      ra.R = R;
-      ra.b = b + off;
-      ra.x = x + off;
-      ra.r = p->rbuf + off;
-      ra.w = p->w;
-      ra.done = p->flags;
-      if (knorm && c == 0) {
-        ra.knorm_part = p->kpart;
-        ra.knorm_root = p->kroot;
-        ra.crow = p->crow;
-      }
+      const ResidualArgs ra = residual_args(p, c, D, E, C, R, b, x, p->rbuf, knorm && c == 0);
       timed(p, KC_RESIDUAL, [&] { launch_residual(ra, p->nmax, st); });
       timed(p, KC_RESIDUAL_ROOT, [&] { launch_residual_root(ra, st); });
     }
@@ -837,6 +760,7 @@ bmpc_status bmpc_factor_refine(bmpc_plan p, const double* D, const double* E, co
 bmpc_status bmpc_factor_solve(bmpc_plan p, const double* D, const double* E, const double* C,
                               const double* R, const double* b, double* x) {
   if (!p || !D || !C || !R || !b || !x || (p->d.N > 1 && !E)) return BMPC_ERR_INVALID;
+  if (p->ragged) return E ? ragged_factor(p, D, E, C, R, b, x) : BMPC_ERR_INVALID;
   if (p->fp64)
     enqueue_factor_solve<double>(p, D, E, C, R, b, x);
   else
@@ -855,13 +779,13 @@ bmpc_status bmpc_set_refine_stop(bmpc_plan p, int32_t stop) {
 
 bmpc_status bmpc_query_structure(bmpc_plan p, int32_t* rows, int32_t* cols, int64_t cap,
                                  int64_t* count) {
-  if (!p) return BMPC_ERR_INVALID;
+  if (!p || p->ragged) return BMPC_ERR_INVALID;
   return bmpc_structure(p->d.N, rows, cols, cap, count);
 }
 
 bmpc_status bmpc_grad_blocks(bmpc_plan p, const double* x, const double* lam, double* dD,
                              double* dE, double* dC, double* dR) {
-  if (!p || !x || !lam) return BMPC_ERR_INVALID;
+  if (!p || !x || !lam || p->ragged) return BMPC_ERR_INVALID;
   GradArgs g{};
   g.S = p->d.S;
   g.B = p->B;
@@ -880,6 +804,7 @@ bmpc_status bmpc_grad_blocks(bmpc_plan p, const double* x, const double* lam, do
 
 bmpc_status bmpc_get_info(bmpc_plan p, int64_t* info) {
   if (!p || !info) return BMPC_ERR_INVALID;
+  if (p->ragged) return ragged_info(p, info);
   unsigned long long v = 0;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
   if (hipMemcpy(&v, p->d_info, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
@@ -918,7 +843,7 @@ bmpc_status bmpc_get_stats(bmpc_plan p, int32_t* iters, double* rel_correction) 
 }
 
 bmpc_status bmpc_query_perm(bmpc_plan p, int32_t* perm) {
-  if (!p || !perm) return BMPC_ERR_INVALID;
+  if (!p || !perm || p->ragged) return BMPC_ERR_INVALID;
   for (int i = 0; i < p->d.N; ++i) perm[i] = p->perm[i];
   return BMPC_OK;
 }
@@ -926,6 +851,20 @@ bmpc_status bmpc_query_perm(bmpc_plan p, int32_t* perm) {
 bmpc_status bmpc_query_cost(bmpc_plan p, bmpc_cost* cost) {
   if (!p || !cost) return BMPC_ERR_INVALID;
   std::memset(cost, 0, sizeof(*cost));
+  if (p->ragged) {  // sums over the systems; levels and passes of the deepest one
+    for (bmpc_plan s : ragged_subs(p)) {
+      cost->factor_flops += s->costs.factor_flops;
+      cost->solve_flops += s->costs.solve_flops;
+      cost->factor_bytes += s->costs.factor_bytes;
+      cost->solve_bytes += s->costs.solve_bytes;
+      cost->residual_bytes += s->costs.residual_bytes;
+      cost->levels = std::max(cost->levels, s->costs.levels);
+      cost->passes = std::max(cost->passes, (int32_t)s->costs.passes.size());
+      cost->window_depth = std::max(cost->window_depth, s->Tw);
+    }
+    cost->workspace_bytes = p->workspace_bytes;
+    return BMPC_OK;
+  }
   cost->factor_flops = p->costs.factor_flops;
   cost->solve_flops = p->costs.solve_flops;
   cost->factor_bytes = p->costs.factor_bytes;
@@ -941,6 +880,17 @@ bmpc_status bmpc_query_cost(bmpc_plan p, bmpc_cost* cost) {
 bmpc_status bmpc_query_kernel_cost(bmpc_plan p, int32_t cls, double* bytes, double* flops,
                                    int32_t* launches) {
   if (!p || cls < 0 || cls >= KC_COUNT) return BMPC_ERR_INVALID;
+  if (p->ragged) {  // sums over the systems; launches: not defined per system
+    double by = 0, fl = 0;
+    for (bmpc_plan s : ragged_subs(p)) {
+      by += s->costs.pass_bytes[cls];
+      fl += s->costs.pass_flops[cls];
+    }
+    if (bytes) *bytes = by;
+    if (flops) *flops = fl;
+    if (launches) *launches = 0;
+    return BMPC_OK;
+  }
   if (bytes) *bytes = p->costs.pass_bytes[cls];
   if (flops) *flops = p->costs.pass_flops[cls];
   if (launches) *launches = p->costs.launches[cls];
@@ -948,6 +898,15 @@ bmpc_status bmpc_query_kernel_cost(bmpc_plan p, int32_t cls, double* bytes, doub
 }
 
 bmpc_status bmpc_export_tail_factor(bmpc_plan p, int32_t s, double* L, double* F) {
+  if (p && p->ragged) {  // chain s of the concatenated systems
+    if (!p->factored) return BMPC_ERR_STATE;
+    (void)hipStreamSynchronize(p->stream);
+    for (bmpc_plan sub : ragged_subs(p)) {
+      if (s < sub->d.S) return bmpc_export_tail_factor(sub, s, L, F);
+      s -= sub->d.S;
+    }
+    return BMPC_ERR_INVALID;
+  }
   if (!p || !L || !F || s < 0 || s >= p->B * p->d.S) return BMPC_ERR_INVALID;
   if (!p->factored) return BMPC_ERR_STATE;
   const int N = p->d.N, n = p->d.n, m = p->m;
@@ -996,6 +955,16 @@ bmpc_status bmpc_export_tail_factor(bmpc_plan p, int32_t s, double* L, double* F
 bmpc_status bmpc_export_root_factor(bmpc_plan p, double* LR) {
   if (!p || !LR) return BMPC_ERR_INVALID;
   if (!p->factored) return BMPC_ERR_STATE;
+  if (p->ragged) {  // the systems' n_i x n_i root factors one after the other
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
+    for (bmpc_plan sub : ragged_subs(p)) {
+      const size_t nn = (size_t)sub->d.n * sub->d.n;
+      if (hipMemcpy(LR, sub->LR, nn * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return BMPC_ERR_DEVICE;
+      LR += nn;
+    }
+    return BMPC_OK;
+  }
   if (hipStreamSynchronize(p->stream) != hipSuccess) return BMPC_ERR_DEVICE;
   if (hipMemcpy(LR, p->LR, (size_t)p->B * p->d.n * p->d.n * 8, hipMemcpyDeviceToHost) !=
       hipSuccess)
@@ -1047,6 +1016,7 @@ const char* bmpc_kernel_class_name(int32_t cls) {
 bmpc_status bmpc_destroy(bmpc_plan p) {
   if (!p) return BMPC_ERR_INVALID;
   (void)hipStreamSynchronize(p->stream);
+  ragged_destroy(p);
   free_plan_memory(p);
   delete p;
   return BMPC_OK;

@@ -27,6 +27,7 @@
 
 #include "bmpc_internal.h"
 #include "blockops.h"
+#include "multi.h"
 #include "regblock.h"
 
 namespace bmpc {
@@ -520,14 +521,14 @@ constexpr int pass_min_blocks() {
 }
 
 template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
-__global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
-    factor_pass_kernel(FactorPassArgs a) {
+__device__ __attribute__((always_inline)) inline void factor_pass_body(const FactorPassArgs& a,
+                                                                       unsigned bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Slots<T, NMAX> sl{reinterpret_cast<T*>(smem_raw), a.Tw, FWD ? a.nrhs * NMAX : 0};
   const int n = a.n, N = a.N;
   const size_t nn = (size_t)n * n;
-  const int s = blockIdx.x / a.windows;
-  const int w = blockIdx.x - s * a.windows;
+  const int s = bx / a.windows;
+  const int w = bx - s * a.windows;
   const int lo = w << a.Tw;
   const int hi = min(lo + (1 << a.Tw) - 1, a.mk);
   const bool has_left = lo >= 1;
@@ -844,6 +845,12 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
   }
 }
 
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+__global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
+    factor_pass_kernel(FactorPassArgs a) {
+  factor_pass_body<T, NMAX, FIRST, FINAL, FWD>(a, blockIdx.x);
+}
+
 __global__ void factor_init_kernel(unsigned long long* info) {
   if (threadIdx.x == 0) *info = ~0ull;
 }
@@ -852,11 +859,10 @@ __global__ void factor_init_kernel(unsigned long long* info) {
 // scenario order (one workgroup per (system, group), one thread per element).  The
 // loads of a group are issued together (clamped to the group's last scenario) and
 // added in order afterwards.
-__global__ void __launch_bounds__(1024) root_reduce_kernel(const double* __restrict__ U,
-                                                           double* part, int S, int nn,
-                                                           int groups) {
-  const int sys = blockIdx.x / groups;
-  const int g = blockIdx.x - sys * groups;
+__device__ __attribute__((always_inline)) inline void root_reduce_body(
+    const double* __restrict__ U, double* part, int S, int nn, int groups, unsigned bx) {
+  const int sys = bx / groups;
+  const int g = bx - sys * groups;
   const int per = (S + groups - 1) / groups;
   const int s0 = g * per, s1 = min(S, s0 + per);
   const double* Us = U + (size_t)sys * S * nn;
@@ -874,21 +880,25 @@ __global__ void __launch_bounds__(1024) root_reduce_kernel(const double* __restr
   }
 }
 
+__global__ void __launch_bounds__(1024) root_reduce_kernel(const double* __restrict__ U,
+                                                           double* part, int S, int nn,
+                                                           int groups) {
+  root_reduce_body(U, part, S, nn, groups, blockIdx.x);
+}
+
 // R~ = R - sum_g part[g] (group order), L_R = chol(R~) in FP64 (Algorithm 1, root
 // reduction and root factorization).
 // 1024 threads: thread e owns element e of the NMAX x NMAX block (identity padded
 // beyond n) and loads all group partials at once.
 template <int NMAX>
-__global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restrict__ R,
-                                                          const double* __restrict__ part,
-                                                          int groups, int n, double* LR,
-                                                          unsigned long long sys_rows,
-                                                          unsigned long long root_row,
-                                                          unsigned long long* info) {
+__device__ __attribute__((always_inline)) inline void root_potrf_body(
+    const double* __restrict__ R, const double* __restrict__ part, int groups, int n,
+    double* LR, unsigned long long sys_rows, unsigned long long root_row,
+    unsigned long long* info, unsigned bx) {
   constexpr int LD = NMAX + 1;
   __shared__ double A[NMAX * LD];
   // one workgroup per system of the batch
-  const int sys = blockIdx.x;
+  const int sys = bx;
   R += (size_t)sys * n * n;
   part += (size_t)sys * groups * n * n;
   LR += (size_t)sys * n * n;
@@ -922,6 +932,81 @@ __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restri
     const int r = e / NMAX, c = e % NMAX;
     if (r < n && c < n) LR[r * n + c] = A[r * LD + c];
   }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restrict__ R,
+                                                          const double* __restrict__ part,
+                                                          int groups, int n, double* LR,
+                                                          unsigned long long sys_rows,
+                                                          unsigned long long root_row,
+                                                          unsigned long long* info) {
+  root_potrf_body<NMAX>(R, part, groups, n, LR, sys_rows, root_row, info, blockIdx.x);
+}
+
+// ---- one launch over the systems of a ragged batch (see multi.h) ----
+
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+__global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
+    factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems, Reloc r) {
+  const MultiItem<FactorPassArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  FactorPassArgs a = it.a;
+  a.D = rel(r.D, a.D);
+  a.E = rel(r.E, a.E);
+  a.C = rel(r.C, a.C);
+  a.b = FWD ? rel(r.b, a.b) : nullptr;
+  factor_pass_body<T, NMAX, FIRST, FINAL, FWD>(a, multi_local(it).x);
+}
+
+__global__ void __launch_bounds__(1024) root_reduce_multi(const MultiItem<RootArgs>* items,
+                                                          int nitems) {
+  const MultiItem<RootArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  root_reduce_body(it.a.U, it.a.part, it.a.S, it.a.n * it.a.n, it.a.groups, multi_local(it).x);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(1024) root_potrf_multi(const MultiItem<RootArgs>* items,
+                                                         int nitems, Reloc r) {
+  const MultiItem<RootArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  root_potrf_body<NMAX>(rel(r.R, it.a.R), it.a.part, it.a.groups, it.a.n, it.a.LR,
+                        it.a.sys_rows, it.a.root_row, it.a.info, multi_local(it).x);
+}
+
+__global__ void info_reset_kernel(unsigned long long* info, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    info[i] = ~0ull;
+}
+
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+void launch_multi_kf(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
+                     size_t lds, const Reloc& r, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&factor_pass_multi<T, NMAX, FIRST, FINAL, FWD>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((factor_pass_multi<T, NMAX, FIRST, FINAL, FWD>), dim3(blocks),
+                     dim3(TileCfg<NMAX>::NT), lds, st, items, nitems, r);
+}
+
+template <typename T, int NMAX>
+void launch_multi_pass_t(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
+                         bool first, bool final, bool fwd, size_t lds, const Reloc& r,
+                         hipStream_t st) {
+#define BMPC_MULTI_KF(F, L, W)                                                          \
+  if (first == F && final == L && fwd == W)                                            \
+    return launch_multi_kf<T, NMAX, F, L, W>(items, nitems, blocks, lds, r, st);
+  BMPC_MULTI_KF(true, true, true)
+  BMPC_MULTI_KF(true, true, false)
+  BMPC_MULTI_KF(true, false, true)
+  BMPC_MULTI_KF(true, false, false)
+  BMPC_MULTI_KF(false, true, true)
+  BMPC_MULTI_KF(false, true, false)
+  BMPC_MULTI_KF(false, false, true)
+  BMPC_MULTI_KF(false, false, false)
+#undef BMPC_MULTI_KF
 }
 
 // Block slots, plus (fused forward substitution) Tw + 5 right-hand-side slots.
@@ -996,6 +1081,39 @@ void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st) {
 }
 template void launch_factor_pass<double>(const FactorPassArgs&, int, hipStream_t);
 template void launch_factor_pass<float>(const FactorPassArgs&, int, hipStream_t);
+
+template <typename T>
+void launch_factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems,
+                              unsigned blocks, int nmax, bool first, bool final, bool fwd,
+                              size_t lds, const Reloc& r, hipStream_t st) {
+  if (nmax <= 8)
+    launch_multi_pass_t<T, 8>(items, nitems, blocks, first, final, fwd, lds, r, st);
+  else if (nmax <= 16)
+    launch_multi_pass_t<T, 16>(items, nitems, blocks, first, final, fwd, lds, r, st);
+  else
+    launch_multi_pass_t<T, 32>(items, nitems, blocks, first, final, fwd, lds, r, st);
+}
+template void launch_factor_pass_multi<double>(const MultiItem<FactorPassArgs>*, int, unsigned,
+                                               int, bool, bool, bool, size_t, const Reloc&,
+                                               hipStream_t);
+template void launch_factor_pass_multi<float>(const MultiItem<FactorPassArgs>*, int, unsigned,
+                                              int, bool, bool, bool, size_t, const Reloc&,
+                                              hipStream_t);
+
+void launch_root_reduce_multi(const MultiItem<RootArgs>* items, int nitems, unsigned blocks,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(root_reduce_multi, dim3(blocks), dim3(1024), 0, st, items, nitems);
+}
+void launch_root_potrf_multi(const MultiItem<RootArgs>* items, int nitems, unsigned blocks,
+                             int nmax, const Reloc& r, hipStream_t st) {
+  if (nmax <= 16)
+    hipLaunchKernelGGL(root_potrf_multi<16>, dim3(blocks), dim3(1024), 0, st, items, nitems, r);
+  else
+    hipLaunchKernelGGL(root_potrf_multi<32>, dim3(blocks), dim3(1024), 0, st, items, nitems, r);
+}
+void launch_info_reset(unsigned long long* info, int count, hipStream_t st) {
+  hipLaunchKernelGGL(info_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, st, info, count);
+}
 
 void launch_factor_init(unsigned long long* info, hipStream_t st) {
   hipLaunchKernelGGL(factor_init_kernel, dim3(1), dim3(64), 0, st, info);

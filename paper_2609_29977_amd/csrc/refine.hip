@@ -10,6 +10,7 @@
 // norms are maxima taken by a two-stage reduction (per-block partial maxima, then
 // one block), so they are deterministic and need no atomics.
 #include "bmpc_internal.h"
+#include "multi.h"
 #include "regblock.h"
 
 namespace bmpc {
@@ -112,7 +113,8 @@ struct StageFetch {
 };
 
 template <int NMAX, bool FULL>
-__global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chunks) {
+__device__ __attribute__((always_inline)) inline void residual_body(const ResidualArgs& a,
+                                                                    int chunks, unsigned bx) {
   if (a.done && *a.done) return;
   constexpr int LD = NMAX + 1;
   constexpr int BS = NMAX * LD;
@@ -132,8 +134,8 @@ __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chu
   double* ws = rs + VS;                // [nrhs][NMAX] C_s x_{s,0} (stage 0)
   const size_t nn = (size_t)n * n;
   const size_t len = ((size_t)S * N + 1) * n;
-  const int s = blockIdx.x / chunks;  // chain of the batch
-  const int ch = blockIdx.x - s * chunks;
+  const int s = bx / chunks;  // chain of the batch
+  const int ch = bx - s * chunks;
   const int sys = s / S, sl = s - sys * S;
   const size_t vbase = (size_t)sys * a.vsys;
   const size_t xk = vbase + (size_t)sl * N * n;  // stage 0 of this chain, q = 0
@@ -253,20 +255,26 @@ __global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chu
     if (t == 0) {
       double m = 0.0;
       for (int i = 0; i < RES_T / 64; ++i) m = fmax(m, wmax[i]);
-      a.knorm_part[blockIdx.x] = m;
+      a.knorm_part[bx] = m;
     }
   }
+}
+
+template <int NMAX, bool FULL>
+__global__ void __launch_bounds__(RES_T) residual_kernel(ResidualArgs a, int chunks) {
+  residual_body<NMAX, FULL>(a, chunks, blockIdx.x);
 }
 
 // One workgroup per system; thread (g, i) sums element i of the products C_s x_{s,0}
 // over the scenarios s = g mod G (G = 1024 / NMAX groups), the groups in order.
 template <int NMAX>
-__global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
+__device__ __attribute__((always_inline)) inline void residual_root_body(const ResidualArgs& a,
+                                                                         unsigned bx) {
   if (a.done && *a.done) return;
   constexpr int G = 1024 / NMAX;
   __shared__ double part[G][NMAX + 1];
   const int n = a.n, N = a.N, S = a.S, nrhs = a.nrhs;
-  const int sys = blockIdx.x;  // one workgroup per system
+  const int sys = bx;  // one workgroup per system
   const size_t len = ((size_t)S * N + 1) * n;
   const size_t root = (size_t)sys * a.vsys + (size_t)S * N * n;
   const double* w = a.w + (size_t)sys * S * nrhs * n;
@@ -315,6 +323,11 @@ __global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
     if (t == 0) a.knorm_root[sys] = m;  // n <= 64: the rows sit in wave 0
   }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(1024) residual_root_kernel(ResidualArgs a) {
+  residual_root_body<NMAX>(a, blockIdx.x);
 }
 
 // Maximum that propagates NaN (so a NaN residual or correction fails the stop test).
@@ -468,7 +481,164 @@ __global__ void __launch_bounds__(256) refine_be_check_kernel(
   }
 }
 
+// ---- ragged batches (see multi.h) ----
+
+__device__ inline ResidualArgs relocate_residual(const ResidualArgs& t, const Reloc& r) {
+  ResidualArgs a = t;
+  a.D = rel(r.D, t.D);
+  a.E = rel(r.E, t.E);
+  a.C = rel(r.C, t.C);
+  a.R = rel(r.R, t.R);
+  a.b = rel(r.b, t.b);
+  a.x = rel(r.x, t.x);
+  a.r = rel(r.r, t.r);
+  return a;
+}
+
+template <int NMAX, bool FULL>
+__global__ void __launch_bounds__(RES_T) residual_multi(const MultiItem<ResidualArgs>* items,
+                                                        int nitems, Reloc r) {
+  const MultiItem<ResidualArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  residual_body<NMAX, FULL>(relocate_residual(it.a, r), it.p0, multi_local(it).x);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(1024) residual_root_multi(const MultiItem<ResidualArgs>* items,
+                                                            int nitems, Reloc r) {
+  const MultiItem<ResidualArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  residual_root_body<NMAX>(relocate_residual(it.a, r), multi_local(it).x);
+}
+
+__global__ void __launch_bounds__(256) seg_maxabs_kernel(const double* v, const double* v2,
+                                                         const SegRec* segs, double* out,
+                                                         double* out2, const int* done) {
+  if (done && *done) return;
+  __shared__ double sh[4];
+  const SegRec sg = segs[blockIdx.x];
+  for (int t = 0; t < (v2 ? 2 : 1); ++t) {
+    const double* p = (t == 0 ? v : v2) + sg.off;
+    double m0 = 0.0, m1 = 0.0;
+    size_t i = threadIdx.x;
+    for (; i + 256 < sg.len; i += 512) {
+      m0 = nan_max(fabs(p[i]), m0);
+      m1 = nan_max(fabs(p[i + 256]), m1);
+    }
+    for (; i < sg.len; i += 256) m0 = nan_max(fabs(p[i]), m0);
+    const double mx = block_max(nan_max(m0, m1), sh);
+    if (threadIdx.x == 0) (t == 0 ? out : out2)[blockIdx.x] = mx;
+  }
+}
+
+// Per system (one workgroup each): its |K| (backward-error mode, when kpart is set) and
+// whether all its segments pass; sys_worst = the largest test quantity.
+__global__ void __launch_bounds__(256) ragged_sys_check_kernel(
+    int mode, const double* dr, const double* xn, const double* bn, const int* seg_sys,
+    int nseg, const double* kpart, const int* kp_off, const double* kroot, double* knorm,
+    double tol, const int* flags, int* sys_ok, double* sys_worst) {
+  if (flags[0]) return;
+  __shared__ double sh[4];
+  const int sys = blockIdx.x;
+  if (mode == 1 && kpart) {
+    double m = 0.0;
+    for (int i = kp_off[sys] + threadIdx.x; i < kp_off[sys + 1]; i += blockDim.x)
+      m = nan_max(kpart[i], m);
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) knorm[sys] = nan_max(m, kroot[sys]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  bool ok = true;
+  double worst = 0.0;
+  // the segments of a system are consecutive; find them by a scan of seg_sys
+  int lo = 0, hi = nseg;
+  while (lo < hi) {  // first segment of sys
+    const int mid = (lo + hi) >> 1;
+    if (seg_sys[mid] < sys) lo = mid + 1; else hi = mid;
+  }
+  for (int k = lo; k < nseg && seg_sys[k] == sys; ++k) {
+    double q;
+    if (mode == 1) {
+      const double den = knorm[sys] * xn[k] + bn[k];
+      q = den > 0.0 ? dr[k] / den : (dr[k] > 0.0 ? HUGE_VAL : 0.0);
+    } else {
+      q = xn[k] > 0.0 ? dr[k] / xn[k] : dr[k];
+    }
+    worst = nan_max(worst, q);
+    if (!(q <= tol)) ok = false;
+  }
+  sys_ok[sys] = ok ? 1 : 0;
+  sys_worst[sys] = worst;
+}
+
+__global__ void __launch_bounds__(256) ragged_final_check_kernel(int B, int count, int* flags,
+                                                                 double* relcorr,
+                                                                 const int* sys_ok,
+                                                                 const double* sys_worst) {
+  if (flags[0]) return;
+  __shared__ double sh[4];
+  double w = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < B; i += blockDim.x) {
+    w = nan_max(sys_worst[i], w);
+    if (!sys_ok[i]) bad = 1.0;
+  }
+  w = block_max(w, sh);
+  bad = block_max(bad, sh);
+  if (threadIdx.x == 0) {
+    *relcorr = w;
+    // count: 2 = a correction was applied before this test (correction-size test),
+    // 1 = one is applied after it unless the test holds (backward error), 0 = none
+    if (count == 2 || (count == 1 && bad != 0.0)) flags[1] += 1;
+    if (bad == 0.0) flags[0] = 1;
+  }
+}
+
 }  // namespace
+
+size_t residual_lds(int nmax, int nrhs) {
+  return nmax <= 8 ? residual_lds_bytes<8>(nrhs)
+                   : nmax <= 16 ? residual_lds_bytes<16>(nrhs) : residual_lds_bytes<32>(nrhs);
+}
+
+void launch_residual_multi(int nmax, bool full, const MultiItem<ResidualArgs>* items, int nitems,
+                           unsigned blocks, size_t lds, const Reloc& r, hipStream_t st) {
+  const dim3 g(blocks), b(RES_T);
+#define BMPC_RES_MULTI(NM)                                                             \
+  if (full)                                                                            \
+    hipLaunchKernelGGL((residual_multi<NM, true>), g, b, lds, st, items, nitems, r);     \
+  else                                                                                 \
+    hipLaunchKernelGGL((residual_multi<NM, false>), g, b, lds, st, items, nitems, r);
+  if (nmax <= 8) {
+    BMPC_RES_MULTI(8)
+  } else if (nmax <= 16) {
+    BMPC_RES_MULTI(16)
+  } else {
+    BMPC_RES_MULTI(32)
+  }
+#undef BMPC_RES_MULTI
+}
+
+void launch_residual_root_multi(const MultiItem<ResidualArgs>* items, int nitems, unsigned blocks,
+                                const Reloc& r, hipStream_t st) {
+  hipLaunchKernelGGL(residual_root_multi<32>, dim3(blocks), dim3(1024), 0, st, items, nitems, r);
+}
+
+void launch_seg_maxabs(const double* v, const double* v2, const SegRec* segs, int nseg,
+                       double* out, double* out2, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(seg_maxabs_kernel, dim3(nseg), dim3(256), 0, st, v, v2, segs, out, out2,
+                     done);
+}
+
+void launch_ragged_check(int mode, const double* dn_or_rn, const double* xn, const double* bn,
+                         const int* seg_sys, int nseg, int B, const double* kpart,
+                         const int* kp_off, const double* kroot, double* knorm, double tol,
+                         int count, int* flags, double* relcorr, int* sys_ok,
+                         double* sys_worst, hipStream_t st) {
+  hipLaunchKernelGGL(ragged_sys_check_kernel, dim3(B), dim3(256), 0, st, mode, dn_or_rn, xn, bn,
+                     seg_sys, nseg, kpart, kp_off, kroot, knorm, tol, (const int*)flags, sys_ok,
+                     sys_worst);
+  hipLaunchKernelGGL(ragged_final_check_kernel, dim3(1), dim3(256), 0, st, B, count, flags,
+                     relcorr, (const int*)sys_ok, (const double*)sys_worst);
+}
 
 void launch_refine_be_check(const double* r, const double* x, int B, int nrhs, size_t len,
                             double* partial, const double* kpart, int kper,

@@ -18,6 +18,7 @@
 
 #include "bmpc_internal.h"
 #include "blockops.h"
+#include "multi.h"
 #include "regblock.h"
 #include "solve_common.h"
 
@@ -252,8 +253,9 @@ struct RhsRegs {
 constexpr int kUpdatePrefetch = 2;
 
 template <typename T, int NMAX, bool FWD, bool FULL>
-__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveArgs a, int level,
-                                                                         int count) {
+__device__ __attribute__((always_inline)) inline void solve_level_body(const SolveArgs& a,
+                                                                       int level, int count,
+                                                                       unsigned bx) {
   if (a.done && *a.done) return;
   typedef RegBlock<T, NMAX> RB;
   constexpr int P = kPullsPerWave;
@@ -265,8 +267,8 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
   Vec* vbuf = reinterpret_cast<Vec*>(level_smem);          // [(w * P + u) * nrhs + q]
   Vec* partial = vbuf + (size_t)W * P * nrhs;              // [w * nrhs + q]
   Vec* rhs = partial + (size_t)W * nrhs;                   // [q]
-  const int s = blockIdx.x / count;
-  const int i = blockIdx.x - s * count;
+  const int s = bx / count;
+  const int i = bx - s * count;
   const int j = (2 * i + 1) << (level - 1);
   const size_t gstride = g_chain_blocks(N);
   const T* Gl = reinterpret_cast<const T*>(a.Gl) + (size_t)s * gstride * nn;
@@ -418,6 +420,12 @@ __global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveA
       finish(q, ok ? a.x[idx] : 0.0, ok ? a.rnorm[seg0 + q] : 0.0);
     }
   }
+}
+
+template <typename T, int NMAX, bool FWD, bool FULL>
+__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_kernel(SolveArgs a, int level,
+                                                                         int count) {
+  solve_level_body<T, NMAX, FWD, FULL>(a, level, count, blockIdx.x);
 }
 
 // Level kernel for one right-hand side and n == NMAX (the common case): the same
@@ -706,8 +714,10 @@ __global__ void __launch_bounds__(64) solve_bwd_rows_kernel(SolveArgs a, int lev
 // of the single-level kernel (row reads at n = 32, one wave of the general one-vector
 // kernel otherwise), so the results are bitwise those of the launches level by level.
 template <typename T, int NMAX>
-__global__ void __launch_bounds__(64 * kBwdTopWaves) solve_bwd_top_kernel(SolveArgs a,
-                                                                          int level_lo) {
+__device__ __attribute__((always_inline)) inline void solve_bwd_top_body(const SolveArgs& a,
+                                                                         int level_lo,
+                                                                         unsigned bx,
+                                                                         unsigned by) {
   if (a.done && *a.done) return;
   constexpr int PER = NMAX == 32 ? 3 * NMAX : (kPullsPerWave + 2) * NMAX;  // per wave
   __shared__ __align__(16) T sm[kBwdTopWaves * PER];
@@ -715,10 +725,10 @@ __global__ void __launch_bounds__(64 * kBwdTopWaves) solve_bwd_top_kernel(SolveA
   for (int level = chain_levels(a.m); level >= level_lo; --level) {
     if (w < level_count(a.m, level)) {
       if constexpr (NMAX == 32)
-        bwd_rows_position<T>(a, level, w, blockIdx.x, blockIdx.y,
+        bwd_rows_position<T>(a, level, w, bx, by,
                              reinterpret_cast<T(*)[NMAX]>(sm + w * PER));
       else
-        level_one_position<T, NMAX, false>(a, level, w, blockIdx.x, blockIdx.y, 1, 0,
+        level_one_position<T, NMAX, false>(a, level, w, bx, by, 1, 0,
                                            reinterpret_cast<unsigned char*>(sm + w * PER));
     }
     __syncthreads();
@@ -726,13 +736,20 @@ __global__ void __launch_bounds__(64 * kBwdTopWaves) solve_bwd_top_kernel(SolveA
 }
 
 template <typename T, int NMAX>
-__global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
+__global__ void __launch_bounds__(64 * kBwdTopWaves) solve_bwd_top_kernel(SolveArgs a,
+                                                                          int level_lo) {
+  solve_bwd_top_body<T, NMAX>(a, level_lo, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int NMAX>
+__device__ __attribute__((always_inline)) inline void solve_x_fwd_body(const SolveArgs& a,
+                                                                  unsigned bx) {
   if (a.done && *a.done) return;
   typedef RegBlock<T, NMAX> RB;
   __shared__ SolveSmem<T, NMAX> sm;
   const int n = a.n, N = a.N, nrhs = a.nrhs, m = a.m;
   const size_t nn = (size_t)n * n;
-  const int s = blockIdx.x;
+  const int s = bx;
   const size_t gstride = g_chain_blocks(N);
   const T* Gr = reinterpret_cast<const T*>(a.Gr) + (size_t)s * gstride * nn;
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
@@ -784,6 +801,11 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
   }
 }
 
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
+  solve_x_fwd_body<T, NMAX>(a, blockIdx.x);
+}
+
 // Root step in FP64 (Algorithm 2, root step).  One workgroup of 1024 threads per
 // system of the batch:
 // r~_0 = r_0 - sum_s w_s with thread (g, i) summing the scenarios s = g mod G of
@@ -791,14 +813,15 @@ __global__ void __launch_bounds__(NT) solve_x_fwd_kernel(SolveArgs a) {
 // the two triangular solves with L_R in LDS, one wave per right-hand side, lane i
 // owning row i.
 template <int NMAX>
-__global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
+__device__ __attribute__((always_inline)) inline void solve_root_body(const SolveArgs& a,
+                                                                      unsigned bx) {
   if (a.done && *a.done) return;
   constexpr int G = 1024 / NMAX, LD = NMAX + 1;
   __shared__ double part[G][LD];
   __shared__ double L[NMAX * LD];
   __shared__ double r0[kMaxRhs][NMAX];
   const int n = a.n, S = a.S, nrhs = a.nrhs;
-  const int sys = blockIdx.x;
+  const int sys = bx;
   const size_t len = vec_len(a);
   const size_t root_off = (size_t)sys * a.vsys + (size_t)S * a.N * n;
   const int seg0 = sys * a.seg_sys;
@@ -872,15 +895,21 @@ __global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
   }
 }
 
+template <int NMAX>
+__global__ void __launch_bounds__(1024) solve_root_kernel(SolveArgs a) {
+  solve_root_body<NMAX>(a, blockIdx.x);
+}
+
 template <typename T, int NMAX>
-__global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
+__device__ __attribute__((always_inline)) inline void solve_x_bwd_body(const SolveArgs& a,
+                                                                  unsigned bx) {
   if (a.done && *a.done) return;
   typedef RegBlock<T, NMAX> RB;
   __shared__ SolveSmem<T, NMAX> sm;
   __shared__ double x0s[kMaxRhs][NMAX];
   const int n = a.n, N = a.N, nrhs = a.nrhs;
   const size_t nn = (size_t)n * n;
-  const int s = blockIdx.x;
+  const int s = bx;
   const T* Linv = reinterpret_cast<const T*>(a.Linv) + (size_t)s * N * nn;
   T* yx = reinterpret_cast<T*>(a.y) + ((size_t)s * N + (N - 1)) * nrhs * n;
   RB lin, fb;
@@ -919,6 +948,124 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
   }
 }
 
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
+  solve_x_bwd_body<T, NMAX>(a, blockIdx.x);
+}
+
+// ---- one launch over the systems of a ragged batch (see multi.h) ----
+// Items of the level kinds carry (level, count) in p0, p1; the merged backward top
+// levels carry level_lo in p0.
+
+__device__ inline SolveArgs relocate_solve(const SolveArgs& t, const Reloc& r) {
+  SolveArgs a = t;
+  a.b = rel(r.b, t.b);
+  a.x = rel(r.x, t.x);
+  a.dstore = rel(r.r, t.dstore);
+  return a;
+}
+
+template <typename T, int NMAX, bool FWD, bool FULL>
+__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_multi(
+    const MultiItem<SolveArgs>* items, int nitems, Reloc r) {
+  const MultiItem<SolveArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  const SolveArgs a = relocate_solve(it.a, r);
+  solve_level_body<T, NMAX, FWD, FULL>(a, it.p0, it.p1, multi_local(it).x);
+}
+
+template <typename T, int NMAX, bool FWD>
+__global__ void __launch_bounds__(64 * kLevelMaxWaves) solve_level_one_multi(
+    const MultiItem<SolveArgs>* items, int nitems, Reloc r) {
+  const MultiItem<SolveArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  const SolveArgs a = relocate_solve(it.a, r);
+  if (a.done && *a.done) return;
+  extern __shared__ __align__(16) unsigned char level_smem[];
+  const LocalBlock lb = multi_local(it);
+  level_one_position<T, NMAX, FWD>(a, it.p0, lb.x, lb.y, lb.z, (int)(blockDim.x >> 6),
+                                   (int)(threadIdx.x >> 6), level_smem);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) solve_bwd_rows_multi(const MultiItem<SolveArgs>* items,
+                                                           int nitems, Reloc r) {
+  const MultiItem<SolveArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  const SolveArgs a = relocate_solve(it.a, r);
+  if (a.done && *a.done) return;
+  __shared__ T xs[3][32];
+  const LocalBlock lb = multi_local(it);
+  bwd_rows_position<T>(a, it.p0, lb.x, lb.y, lb.z, xs);
+}
+
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(64 * kBwdTopWaves) solve_bwd_top_multi(
+    const MultiItem<SolveArgs>* items, int nitems, Reloc r) {
+  const MultiItem<SolveArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  const SolveArgs a = relocate_solve(it.a, r);
+  const LocalBlock lb = multi_local(it);
+  solve_bwd_top_body<T, NMAX>(a, it.p0, lb.x, lb.y);
+}
+
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(NT) solve_x_fwd_multi(const MultiItem<SolveArgs>* items,
+                                                        int nitems, Reloc r) {
+  const MultiItem<SolveArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  solve_x_fwd_body<T, NMAX>(relocate_solve(it.a, r), multi_local(it).x);
+}
+
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(NT) solve_x_bwd_multi(const MultiItem<SolveArgs>* items,
+                                                        int nitems, Reloc r) {
+  const MultiItem<SolveArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  solve_x_bwd_body<T, NMAX>(relocate_solve(it.a, r), multi_local(it).x);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(1024) solve_root_multi(const MultiItem<SolveArgs>* items,
+                                                         int nitems, Reloc r) {
+  const MultiItem<SolveArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  solve_root_body<NMAX>(relocate_solve(it.a, r), multi_local(it).x);
+}
+
+template <typename T, int NMAX>
+void solve_multi_t(int kind, bool fwd, bool full, const MultiItem<SolveArgs>* items, int nitems,
+                   unsigned blocks, unsigned threads, size_t lds, const Reloc& r, hipStream_t st) {
+  const dim3 g(blocks), b(threads);
+  switch (kind) {
+    case SK_LEVEL:
+      if (fwd && full)
+        hipLaunchKernelGGL((solve_level_multi<T, NMAX, true, true>), g, b, lds, st, items, nitems, r);
+      else if (fwd)
+        hipLaunchKernelGGL((solve_level_multi<T, NMAX, true, false>), g, b, lds, st, items, nitems, r);
+      else if (full)
+        hipLaunchKernelGGL((solve_level_multi<T, NMAX, false, true>), g, b, lds, st, items, nitems, r);
+      else
+        hipLaunchKernelGGL((solve_level_multi<T, NMAX, false, false>), g, b, lds, st, items, nitems, r);
+      break;
+    case SK_LEVEL_ONE:
+      if (fwd)
+        hipLaunchKernelGGL((solve_level_one_multi<T, NMAX, true>), g, b, lds, st, items, nitems, r);
+      else
+        hipLaunchKernelGGL((solve_level_one_multi<T, NMAX, false>), g, b, lds, st, items, nitems, r);
+      break;
+    case SK_BWD_ROWS:
+      if constexpr (NMAX == 32)
+        hipLaunchKernelGGL((solve_bwd_rows_multi<T>), g, b, 0, st, items, nitems, r);
+      break;
+    case SK_BWD_TOP:
+      hipLaunchKernelGGL((solve_bwd_top_multi<T, NMAX>), g, b, 0, st, items, nitems, r);
+      break;
+    case SK_X_FWD:
+      hipLaunchKernelGGL((solve_x_fwd_multi<T, NMAX>), g, b, 0, st, items, nitems, r);
+      break;
+    case SK_X_BWD:
+      hipLaunchKernelGGL((solve_x_bwd_multi<T, NMAX>), g, b, 0, st, items, nitems, r);
+      break;
+    case SK_ROOT:
+      hipLaunchKernelGGL((solve_root_multi<32>), g, b, 0, st, items, nitems, r);
+      break;
+  }
+}
+
 #define BMPC_DISPATCH_NMAX(nmax, FN, ...) \
   do {                                    \
     if ((nmax) <= 8)                      \
@@ -929,48 +1076,39 @@ __global__ void __launch_bounds__(NT) solve_x_bwd_kernel(SolveArgs a) {
       FN<T, 32>(__VA_ARGS__);             \
   } while (0)
 
-// One right-hand side, full blocks, and a grid of (positions, scenarios, systems)
-// within the launch limits of the y and z dimensions.
-template <int NMAX>
-inline bool one_rhs_full(const SolveArgs& a) {
-  return a.nrhs == 1 && a.n == NMAX && a.S <= 65535 && a.B <= 65535;
+template <typename T, int NMAX>
+void level_t(const SolveArgs& a, int level, bool fwd, hipStream_t st) {
+  const LevelCfg c = solve_level_config(a, level, fwd, NMAX, sizeof(T) == 8);
+  if (c.count <= 0) return;
+  const dim3 g(c.gx, c.gy, c.gz), b(c.threads);
+  switch (c.kind) {
+    case SK_BWD_ROWS:
+      if constexpr (NMAX == 32) hipLaunchKernelGGL((solve_bwd_rows_kernel<T>), g, b, 0, st, a, level);
+      break;
+    case SK_LEVEL_ONE:
+      if (fwd)
+        hipLaunchKernelGGL((solve_level_one_kernel<T, NMAX, true>), g, b, c.lds, st, a, level);
+      else
+        hipLaunchKernelGGL((solve_level_one_kernel<T, NMAX, false>), g, b, c.lds, st, a, level);
+      break;
+    default:
+      if (fwd && c.full)
+        hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, true>), g, b, c.lds, st, a, level, c.count);
+      else if (fwd)
+        hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, false>), g, b, c.lds, st, a, level, c.count);
+      else if (c.full)
+        hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, true>), g, b, c.lds, st, a, level, c.count);
+      else
+        hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, false>), g, b, c.lds, st, a, level, c.count);
+  }
 }
-
 template <typename T, int NMAX>
 void fwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
-  const int count = level_count(a.m, level);
-  if (count <= 0) return;
-  const int pulls = 2 * (level - 1);
-  const int waves =
-      std::max(1, std::min(kLevelMaxWaves, (pulls + kPullsPerWave - 1) / kPullsPerWave));
-  const size_t sh = level_smem_bytes<T, NMAX>(waves, a.nrhs);
-  if (one_rhs_full<NMAX>(a))
-    hipLaunchKernelGGL((solve_level_one_kernel<T, NMAX, true>), dim3(count, a.S, a.B),
-                       dim3(64 * waves), sh, st, a, level);
-  else if (a.n == NMAX)
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, true>), dim3(a.B * a.S * count),
-                       dim3(64 * waves), sh, st, a, level, count);
-  else
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, true, false>), dim3(a.B * a.S * count),
-                       dim3(64 * waves), sh, st, a, level, count);
+  level_t<T, NMAX>(a, level, true, st);
 }
 template <typename T, int NMAX>
 void bwd_level_t(const SolveArgs& a, int level, hipStream_t st) {
-  const int count = level_count(a.m, level);
-  if (count <= 0) return;
-  const size_t sh = level_smem_bytes<T, NMAX>(1, a.nrhs);
-  if (NMAX == 32 && one_rhs_full<NMAX>(a))
-    hipLaunchKernelGGL((solve_bwd_rows_kernel<T>), dim3(count, a.S, a.B), dim3(64), 0, st, a,
-                       level);
-  else if (one_rhs_full<NMAX>(a))
-    hipLaunchKernelGGL((solve_level_one_kernel<T, NMAX, false>), dim3(count, a.S, a.B), dim3(64),
-                       sh, st, a, level);
-  else if (a.n == NMAX)
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, true>), dim3(a.B * a.S * count), dim3(64),
-                       sh, st, a, level, count);
-  else
-    hipLaunchKernelGGL((solve_level_kernel<T, NMAX, false, false>), dim3(a.B * a.S * count), dim3(64),
-                       sh, st, a, level, count);
+  level_t<T, NMAX>(a, level, false, st);
 }
 template <typename T, int NMAX>
 void x_fwd_t(const SolveArgs& a, hipStream_t st) {
@@ -982,6 +1120,37 @@ void x_bwd_t(const SolveArgs& a, hipStream_t st) {
 }
 
 }  // namespace
+
+// Kernel, grid and LDS of one level of a sweep (n <= 32).  One right-hand side with
+// full blocks and a grid of (positions, scenarios, systems) within the y and z launch
+// limits takes the one-vector kernels (row reads for the backward sweep at n = 32),
+// everything else the general level kernel on a flat grid.  Forward positions of level
+// l pull 2 (l - 1) blocks, kPullsPerWave per wave, on up to kLevelMaxWaves waves.
+LevelCfg solve_level_config(const SolveArgs& a, int level, bool fwd, int nmax, bool fp64) {
+  LevelCfg c{};
+  c.count = level_count(a.m, level);
+  const bool one = a.nrhs == 1 && a.n == nmax && a.S <= 65535 && a.B <= 65535;
+  int waves = 1;
+  if (fwd) {
+    const int pulls = 2 * (level - 1);
+    waves = std::max(1, std::min(kLevelMaxWaves, (pulls + kPullsPerWave - 1) / kPullsPerWave));
+  }
+  c.threads = 64 * waves;
+  c.lds = solve_level_lds(fp64, nmax, waves, a.nrhs);
+  c.full = a.n == nmax;
+  if (one) {
+    c.kind = (!fwd && nmax == 32) ? SK_BWD_ROWS : SK_LEVEL_ONE;
+    if (c.kind == SK_BWD_ROWS) c.lds = 0;
+    c.gx = (unsigned)c.count;
+    c.gy = (unsigned)a.S;
+    c.gz = (unsigned)a.B;
+  } else {
+    c.kind = SK_LEVEL;
+    c.gx = (unsigned)(a.B * a.S) * (unsigned)std::max(c.count, 0);
+    c.gy = c.gz = 1;
+  }
+  return c;
+}
 
 template <typename T>
 void launch_solve_fwd_level(const SolveArgs& a, int level, int nmax, hipStream_t st) {
@@ -1021,6 +1190,31 @@ void launch_solve_root(const SolveArgs& a, hipStream_t st) {
   else
     hipLaunchKernelGGL(solve_root_kernel<32>, dim3(a.B), dim3(1024), 0, st, a);
 }
+
+size_t solve_level_lds(bool fp64, int nmax, int waves, int nrhs) {
+  return fp64 ? (nmax <= 8 ? level_smem_bytes<double, 8>(waves, nrhs)
+                          : nmax <= 16 ? level_smem_bytes<double, 16>(waves, nrhs)
+                                       : level_smem_bytes<double, 32>(waves, nrhs))
+              : (nmax <= 8 ? level_smem_bytes<float, 8>(waves, nrhs)
+                           : nmax <= 16 ? level_smem_bytes<float, 16>(waves, nrhs)
+                                        : level_smem_bytes<float, 32>(waves, nrhs));
+}
+
+template <typename T>
+void launch_solve_multi(int kind, bool fwd, bool full, int nmax,
+                        const MultiItem<SolveArgs>* items, int nitems, unsigned blocks,
+                        unsigned threads, size_t lds, const Reloc& r, hipStream_t st) {
+  if (nmax <= 8)
+    solve_multi_t<T, 8>(kind, fwd, full, items, nitems, blocks, threads, lds, r, st);
+  else if (nmax <= 16)
+    solve_multi_t<T, 16>(kind, fwd, full, items, nitems, blocks, threads, lds, r, st);
+  else
+    solve_multi_t<T, 32>(kind, fwd, full, items, nitems, blocks, threads, lds, r, st);
+}
+template void launch_solve_multi<double>(int, bool, bool, int, const MultiItem<SolveArgs>*, int,
+                                         unsigned, unsigned, size_t, const Reloc&, hipStream_t);
+template void launch_solve_multi<float>(int, bool, bool, int, const MultiItem<SolveArgs>*, int,
+                                        unsigned, unsigned, size_t, const Reloc&, hipStream_t);
 
 template void launch_solve_fwd_level<double>(const SolveArgs&, int, int, hipStream_t);
 template void launch_solve_fwd_level<float>(const SolveArgs&, int, int, hipStream_t);

@@ -1,4 +1,4 @@
-"""GPU: systems of different shapes through bucketed batches (paper_2609_29977_amd.batch)
+"""GPU: systems of different shapes through paper_2609_29977_amd.batch (one ragged plan)
 against the FP64 oracle, per system (1e-11 FP64, 1e-10 FP32 + refinement)."""
 import numpy as np
 import pytest
@@ -23,7 +23,7 @@ def test_hetero_batch_against_oracle(precision):
         systems.append(make_system(S, N, n, 1, delta, 200 + i))
         shapes.append((S, N, n, 1))
     hb = HeteroBatch(shapes, precision)
-    assert hb.padded_work >= 1.0
+    assert hb.padded_work == 1.0
     for i, s in enumerate(systems):
         hb.put(i, s.D, s.E, s.C, s.R, s.b)
     if precision == "fp64":
@@ -31,7 +31,7 @@ def test_hetero_batch_against_oracle(precision):
     else:
         hb.solve(refine_tol=1e-13, refine_iters=10)
     torch.cuda.synchronize()
-    assert hb.info() == []
+    assert hb.info() == 0
     bar = 1e-11 if precision == "fp64" else 1e-10
     for i, s in enumerate(systems):
         ref, _ = oracle.solve(s.D, s.E, s.C, s.R, s.b)
@@ -66,8 +66,7 @@ def test_graph_replays_match_eager():
     eager = [hb.solution(i).cpu().numpy() for i in range(len(shapes))]
     hb.capture(refine_tol=0.0, refine_iters=1)
     for rep in range(3):
-        for g in hb.groups.values():
-            g.x.zero_()
+        hb.x.zero_()
         junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
         torch.cuda.synchronize()
         hb.replay()
