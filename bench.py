@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--systems", type=int, default=1024,
                     help="batching workload (--config c4): number of systems")
+    ap.add_argument("--tune", action="store_true",
+                    help="batching workload: autotune the launch configuration per shape class")
     ap.add_argument("--no-graph", action="store_true",
                     help="batching workload: launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -107,9 +109,27 @@ def bench_hetero(args):
         n = int(rng.choice([8, 16, 32]))
         shapes.append((S, N, n, 1))
         deltas.append(float(10 ** rng.uniform(-4, 0)))
+    # Autotuned mapping: one bmpc_autotune run per shape class (block size x stage
+    # range), on a representative shape of the class; its choice goes to every system of
+    # the class.
+    tuned = {}
+    options = None
+    if args.tune:
+        t0 = time.perf_counter()
+        classes = [(n, lo, hi) for n in (8, 16, 32) for lo, hi in ((16, 64), (65, 128), (129, 256))]
+        for n, lo, hi in classes:
+            wd, flags, ms, cand = bmpc.autotune(128, hi, n, 1, "fp32", reps=3)
+            tuned[f"n={n} N={lo}..{hi}"] = {"window_depth": wd, "flags": flags,
+                                           "best_ms_at_S128_Nmax": round(ms, 4),
+                                           "candidate_ms": [round(c, 4) for c in cand]}
+        def cls(n, N):
+            return next(v for k, v in tuned.items() if k.startswith(f"n={n} ") and
+                        int(k.split("N=")[1].split("..")[0]) <= N <= int(k.split("..")[1]))
+        options = [(cls(n, N)["window_depth"], cls(n, N)["flags"]) for S, N, n, _ in shapes]
+        log(f"autotuned {len(classes)} shape classes in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     side = torch.cuda.Stream()
-    rp = bmpc.RaggedPlan(shapes, "fp32", stream=side)
+    rp = bmpc.RaggedPlan(shapes, "fp32", stream=side, options=options)
     analyze_s = time.perf_counter() - t0
     sz = rp.sizes
     f64 = torch.float64
@@ -187,8 +207,10 @@ def bench_hetero(args):
            "dtype": "f32+f64", "data": "synthetic (device generator)",
            "config": {"workload": "c4", "systems": K, "S": "U[8,256]", "N": "U[16,256]",
                       "n": "{8,16,32}", "delta": "log-U[1e-4,1]", "plan": "one ragged plan",
+                      "mapping": "autotuned per shape class" if args.tune else "defaults",
                       "padded_work": 1.0, "graph": not args.no_graph},
            "gflops_real_work": round(flops / (p50 * 1e-3) / 1e9, 1),
+           "autotuned": tuned or None,
            "input_gb": round(sum(sz) * 8 / 1e9, 1),
            "workspace_gb": round(rp.cost().workspace_bytes / 1e9, 1),
            "info": info, "max_rel_err_vs_oracle_sampled": err}

@@ -78,8 +78,11 @@ typedef struct {
 } bmpc_dims;
 
 /* bmpc_options.flags */
-#define BMPC_FLAG_NO_BWD_TOP_MERGE 0x1 /* backward sweep: one launch per level even where
-                                          the top levels could share one launch */
+#define BMPC_FLAG_NO_BWD_TOP_MERGE 0x1 /* backward sweep: one launch per level (one wave
+                                          per position) even where the top levels could
+                                          share one launch (one workgroup per chain) */
+#define BMPC_FLAG_FWD_ONE_WAVE 0x2     /* forward sweep: one wave per position instead of
+                                          up to four sharing its pulls */
 
 typedef struct {
   int32_t window_depth; /* 0 = automatic; else levels eliminated per factor pass
@@ -142,14 +145,30 @@ bmpc_status bmpc_analyze_ex(const bmpc_dims* dims, bmpc_precision prec, void* st
  * other), bmpc_set_stream, bmpc_set_refine_stop, the profiling calls and
  * bmpc_destroy; bmpc_query_perm, bmpc_query_structure and bmpc_grad_blocks return
  * BMPC_ERR_INVALID (the host-only bmpc_ordering and bmpc_structure give each system's
- * Pi_i and structure).  opts: window_depth and flags apply to every system;
- * num_systems must be 0 or 1.  BMPC_ERR_INVALID for B < 1 or bad dims. */
+ * Pi_i and structure).  opts: NULL (defaults) or B option structs, one per system
+ * (window_depth, flags; num_systems 0 or 1), e.g. from bmpc_autotune per shape class.
+ * BMPC_ERR_INVALID for B < 1 or bad dims. */
 bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision prec,
                                 void* stream, const bmpc_options* opts, bmpc_plan* out);
 
 /* Shape of system i of a ragged plan and the element offsets of its arrays in the
  * concatenated D, E, C, R and vectors (offsets[0..4]); either output may be NULL. */
 bmpc_status bmpc_ragged_layout(bmpc_plan plan, int32_t i, bmpc_dims* dims, int64_t* offsets);
+
+/* Autotuner: for the shape dims and precision, builds a plan for every candidate
+ * launch configuration -- window_depth from 1 to the largest the shared memory allows,
+ * crossed with BMPC_FLAG_NO_BWD_TOP_MERGE (the backward sweep's top levels in one launch,
+ * one workgroup per chain, or one launch per level, one wave per position) and
+ * BMPC_FLAG_FWD_ONE_WAVE (forward positions on up to four waves or on one) -- times the
+ * plan's step (FP64: bmpc_factor_solve; FP32: bmpc_factor_refine with one correction) on
+ * synthetic SPD data of that shape in device memory (allocated here and freed), the
+ * median of reps runs (1..100) after one warm-up, and writes the fastest configuration
+ * to *best (num_systems 0) and its time to *best_ms.  times (cap entries, may be NULL
+ * with cap = 0) receives each candidate's median in the order tried, *count the number
+ * tried.  Synchronizes the stream; not capturable. */
+bmpc_status bmpc_autotune(const bmpc_dims* dims, bmpc_precision prec, void* stream,
+                          int32_t reps, bmpc_options* best, double* best_ms, double* times,
+                          int32_t cap, int32_t* count);
 
 /* Replace the stream later calls enqueue on (e.g. a graph-capture stream). */
 bmpc_status bmpc_set_stream(bmpc_plan plan, void* stream);

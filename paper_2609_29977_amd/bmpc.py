@@ -17,6 +17,7 @@ OK, ERR_INVALID, ERR_NOT_SPD, ERR_ALLOC, ERR_DEVICE, ERR_STATE, ERR_NOT_CONVERGE
     0, -1, -2, -3, -4, -5, -6
 FP64, FP32_REFINE = 0, 1
 FLAG_NO_BWD_TOP_MERGE = 0x1
+FLAG_FWD_ONE_WAVE = 0x2
 STOP_CORRECTION, STOP_BACKWARD_ERROR = 0, 1
 UNIT_ROUNDOFF = 2.0 ** -53
 
@@ -29,7 +30,7 @@ EXPORTED = [
     "bmpc_destroy", "bmpc_status_string", "bmpc_ordering", "bmpc_structure",
     "bmpc_cost_model", "bmpc_grad_blocks", "bmpc_assemble_qp", "bmpc_factor_solve",
     "bmpc_factor_refine", "bmpc_set_refine_stop", "bmpc_query_structure",
-    "bmpc_assemble_qp_noalloc", "bmpc_analyze_ragged", "bmpc_ragged_layout",
+    "bmpc_assemble_qp_noalloc", "bmpc_analyze_ragged", "bmpc_ragged_layout", "bmpc_autotune",
 ]
 
 
@@ -96,6 +97,7 @@ def lib():
         "bmpc_set_refine_stop": [vp, i32],
         "bmpc_analyze_ragged": [i32, P(_Dims), i32, vp, P(_Options), P(vp)],
         "bmpc_ragged_layout": [vp, i32, P(_Dims), P(i64)],
+        "bmpc_autotune": [P(_Dims), i32, vp, i32, P(_Options), P(dbl), P(dbl), i32, P(i32)],
         "bmpc_query_structure": [vp, P(i32), P(i32), i64, P(i64)],
         "bmpc_factor": [vp, vp, vp, vp, vp],
         "bmpc_solve": [vp, vp, vp],
@@ -181,6 +183,25 @@ def cost_model(S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
     _check(lib().bmpc_cost_model(ctypes.byref(d), _prec(precision), ctypes.byref(o),
                                  ctypes.byref(c)), "bmpc_cost_model")
     return _cost(c)
+
+
+def autotune(S: int, N: int, n: int, nrhs: int = 1, precision="fp32", reps: int = 5,
+             stream=None):
+    """Fastest launch configuration for the shape (bmpc_autotune): returns
+    (window_depth, flags, best_ms, candidate_ms)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    d = _Dims(S, N, n, nrhs)
+    best = _Options()
+    best_ms = ctypes.c_double(0.0)
+    times = (ctypes.c_double * 64)()
+    cnt = ctypes.c_int32(0)
+    _check(lib().bmpc_autotune(ctypes.byref(d), _prec(precision),
+                               ctypes.c_void_p(stream.cuda_stream), int(reps),
+                               ctypes.byref(best), ctypes.byref(best_ms), times, 64,
+                               ctypes.byref(cnt)), "bmpc_autotune")
+    return best.window_depth, best.flags, best_ms.value, list(times[:min(cnt.value, 64)])
 
 
 def kernel_class_names() -> list:
@@ -445,7 +466,7 @@ class RaggedPlan(Plan):
     return the concatenated arrays."""
 
     def __init__(self, shapes, precision="fp32", window_depth: int = 0, stream=None,
-                 flags: int = 0):
+                 flags: int = 0, options=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("bmpc needs a HIP device (torch.cuda.is_available() is False)")
@@ -459,9 +480,11 @@ class RaggedPlan(Plan):
             stream = torch.cuda.current_stream()
         self._stream = stream
         dims = (_Dims * self.B)(*[_Dims(*sh) for sh in shapes])
-        o = _Options(int(window_depth), 0, int(flags))
+        if options is None:
+            options = [(window_depth, flags)] * self.B
+        opts = (_Options * self.B)(*[_Options(int(w), 0, int(f)) for w, f in options])
         _check(lib().bmpc_analyze_ragged(self.B, dims, self.precision,
-                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
+                                         ctypes.c_void_p(stream.cuda_stream), opts,
                                          ctypes.byref(self._h)), "bmpc_analyze_ragged")
         self.offsets = [self.layout(i)[1] for i in range(self.B)] + [self._totals()]
 

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbmpc.so")
 SOURCES = ["api.hip", "ragged.hip", "factor.hip", "factor64.hip", "solve.hip", "solve64.hip",
-           "refine.hip", "grad.hip", "qp.hip"]
+           "refine.hip", "grad.hip", "qp.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

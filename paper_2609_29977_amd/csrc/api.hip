@@ -350,6 +350,7 @@ SolveArgs solve_args(bmpc_plan p, const double* b, double* x, int q0, int nq) {
   a.nrhs = nq;
   a.vsys = (size_t)p->d.nrhs * vec_len(p);
   a.seg_sys = p->d.nrhs;
+  a.fwd_waves = (p->opt_flags & BMPC_FLAG_FWD_ONE_WAVE) ? 1 : 0;
   a.Linv = p->Linv;
   a.Gl = p->Gl;
   a.Gr = p->Gr;

@@ -132,6 +132,7 @@ struct SolveArgs {
   double* dstore;        // refinement: rnorm * d stored here ([nrhs][len], may alias b)
   const int* done;       // refinement stop flag (null outside refinement)
   int accumulate;        // 0: x = d ; 1: x += rnorm * d (refinement update)
+  int fwd_waves;         // forward level positions: at most this many waves (0: 4)
 };
 
 struct ResidualArgs {

@@ -546,11 +546,10 @@ bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision
                                 void* stream, const bmpc_options* opts, bmpc_plan* out) {
   if (!out) return BMPC_ERR_INVALID;
   *out = nullptr;
-  if (B < 1 || !dims || (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE) ||
-      (opts && opts->num_systems > 1))
-    return BMPC_ERR_INVALID;
+  if (B < 1 || !dims || (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE)) return BMPC_ERR_INVALID;
   for (int i = 0; i < B; ++i)
-    if (!dims_ok(&dims[i], 1) || dims[i].n > 32 || dims[i].nrhs != dims[0].nrhs)
+    if (!dims_ok(&dims[i], 1) || dims[i].n > 32 || dims[i].nrhs != dims[0].nrhs ||
+        (opts && opts[i].num_systems > 1))
       return BMPC_ERR_INVALID;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BMPC_ERR_DEVICE;
@@ -571,13 +570,16 @@ bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision
   p->prec = prec;
   p->fp64 = prec == BMPC_FP64;
   p->stream = reinterpret_cast<hipStream_t>(stream);
-  p->opt_flags = opts ? opts->flags : 0;
+  p->opt_flags = opts ? opts[0].flags : 0;
   p->B = B;
   p->d = dims[0];
   R.nrhs = dims[0].nrhs;
-  bmpc_options so{};
-  if (opts) so = *opts;
-  so.num_systems = 1;
+  auto sys_opts = [&](int i) {
+    bmpc_options so{};
+    if (opts) so = opts[i];
+    so.num_systems = 1;
+    return so;
+  };
   // per-system plans: sizes first, then one allocation carved in system order
   size_t total = 0;
   std::vector<size_t> base(B);
@@ -587,6 +589,7 @@ bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision
     R.subs.push_back(s);
     s->parent = p;
     s->measure = true;
+    const bmpc_options so = sys_opts(i);
     if (init_plan(s, &dims[i], prec, stream, &so) != BMPC_OK) return fail(BMPC_ERR_INVALID);
     base[i] = total;
     total += (s->arena_used + 255) & ~(size_t)255;
@@ -598,6 +601,7 @@ bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision
     s->arena = R.arena + base[i];
     s->arena_used = 0;
     s->workspace_bytes = 0;
+    const bmpc_options so = sys_opts(i);
     const bmpc_status st = init_plan(s, &dims[i], prec, stream, &so);
     if (st != BMPC_OK) return fail(st);
     p->workspace_bytes += s->workspace_bytes;
@@ -699,7 +703,6 @@ bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision
     (void)hipGetLastError();
     return fail(BMPC_ERR_DEVICE);
   }
-  for (size_t k = 0; k < R.allocs.size(); ++k) p->workspace_bytes += 0.0;
   *out = p;
   return BMPC_OK;
 }

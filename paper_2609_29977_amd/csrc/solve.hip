@@ -1125,7 +1125,8 @@ void x_bwd_t(const SolveArgs& a, hipStream_t st) {
 // full blocks and a grid of (positions, scenarios, systems) within the y and z launch
 // limits takes the one-vector kernels (row reads for the backward sweep at n = 32),
 // everything else the general level kernel on a flat grid.  Forward positions of level
-// l pull 2 (l - 1) blocks, kPullsPerWave per wave, on up to kLevelMaxWaves waves.
+// l pull 2 (l - 1) blocks, kPullsPerWave per wave, on up to kLevelMaxWaves waves (or
+// a.fwd_waves: one wave per position when the plan asks for it).
 LevelCfg solve_level_config(const SolveArgs& a, int level, bool fwd, int nmax, bool fp64) {
   LevelCfg c{};
   c.count = level_count(a.m, level);
@@ -1133,7 +1134,8 @@ LevelCfg solve_level_config(const SolveArgs& a, int level, bool fwd, int nmax, b
   int waves = 1;
   if (fwd) {
     const int pulls = 2 * (level - 1);
-    waves = std::max(1, std::min(kLevelMaxWaves, (pulls + kPullsPerWave - 1) / kPullsPerWave));
+    const int cap = a.fwd_waves > 0 ? std::min(a.fwd_waves, kLevelMaxWaves) : kLevelMaxWaves;
+    waves = std::max(1, std::min(cap, (pulls + kPullsPerWave - 1) / kPullsPerWave));
   }
   c.threads = 64 * waves;
   c.lds = solve_level_lds(fp64, nmax, waves, a.nrhs);
