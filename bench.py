@@ -110,23 +110,32 @@ def bench_hetero(args):
         shapes.append((S, N, n, 1))
         deltas.append(float(10 ** rng.uniform(-4, 0)))
     # Autotuned mapping: one bmpc_autotune run per shape class (block size x stage
-    # range), on a representative shape of the class; its choice goes to every system of
-    # the class.
+    # range), timed on a batch of the class's mean shape with as many systems as the
+    # class holds (capped at 16 GB of input), so that the tuner sees the class at the
+    # load it runs under; its choice goes to every system of the class.
     tuned = {}
     options = None
     if args.tune:
         t0 = time.perf_counter()
         classes = [(n, lo, hi) for n in (8, 16, 32) for lo, hi in ((16, 64), (65, 128), (129, 256))]
         for n, lo, hi in classes:
-            wd, flags, ms, cand = bmpc.autotune(128, hi, n, 1, "fp32", reps=3)
+            members = [(S, N) for S, N, nn, _ in shapes if nn == n and lo <= N <= hi]
+            if not members:
+                continue
+            S_m = int(round(np.mean([m[0] for m in members])))
+            N_m = int(round(np.mean([m[1] for m in members])))
+            per_sys = S_m * (2 * N_m + 1) * n * n * 8
+            B = max(1, min(len(members), int(16e9 // per_sys)))
+            wd, flags, ms, cand = bmpc.autotune(S_m, N_m, n, 1, "fp32", reps=3, num_systems=B)
             tuned[f"n={n} N={lo}..{hi}"] = {"window_depth": wd, "flags": flags,
-                                           "best_ms_at_S128_Nmax": round(ms, 4),
+                                           "tuned_on": {"S": S_m, "N": N_m, "systems": B},
+                                           "best_ms": round(ms, 4),
                                            "candidate_ms": [round(c, 4) for c in cand]}
         def cls(n, N):
             return next(v for k, v in tuned.items() if k.startswith(f"n={n} ") and
                         int(k.split("N=")[1].split("..")[0]) <= N <= int(k.split("..")[1]))
         options = [(cls(n, N)["window_depth"], cls(n, N)["flags"]) for S, N, n, _ in shapes]
-        log(f"autotuned {len(classes)} shape classes in {time.perf_counter() - t0:.1f}s")
+        log(f"autotuned {len(tuned)} shape classes in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     side = torch.cuda.Stream()
     rp = bmpc.RaggedPlan(shapes, "fp32", stream=side, options=options)

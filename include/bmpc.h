@@ -90,7 +90,11 @@ typedef struct {
   int32_t num_systems;  /* 0 or 1: one system; B > 1: a batch of B independent
                            systems of the same dims (layouts: see "Batches") */
   int32_t flags;        /* BMPC_FLAG_* bits, 0 = defaults */
-  int32_t reserved[5];
+  int32_t later_depth;  /* levels per factor pass after the first: 0 = automatic,
+                           else 1..6 (bounded like window_depth).  The reduced chains
+                           of the later passes are 2^window_depth times shorter; a
+                           smaller depth there gives each chain more workgroups */
+  int32_t reserved[4];
 } bmpc_options;
 
 /* Stop tests of bmpc_refine / bmpc_factor_refine (bmpc_set_refine_stop). */
@@ -109,8 +113,8 @@ typedef struct {
   double residual_bytes;  /* algorithmic bytes of one FP64 residual b - K x */
   int32_t levels;         /* elimination levels of one tail, x_1 included */
   int32_t passes;         /* factor passes (kernel launches over the chains) */
-  int32_t window_depth;   /* levels per factor pass actually used */
-  int32_t reserved;
+  int32_t window_depth;   /* levels of the first factor pass actually used */
+  int32_t later_depth;    /* levels of each later factor pass */
   double workspace_bytes; /* device memory owned by the plan */
 } bmpc_cost;
 
@@ -155,20 +159,24 @@ bmpc_status bmpc_analyze_ragged(int32_t B, const bmpc_dims* dims, bmpc_precision
  * concatenated D, E, C, R and vectors (offsets[0..4]); either output may be NULL. */
 bmpc_status bmpc_ragged_layout(bmpc_plan plan, int32_t i, bmpc_dims* dims, int64_t* offsets);
 
-/* Autotuner: for the shape dims and precision, builds a plan for every candidate
- * launch configuration -- window_depth from 1 to the largest the shared memory allows,
- * crossed with BMPC_FLAG_NO_BWD_TOP_MERGE (the backward sweep's top levels in one launch,
- * one workgroup per chain, or one launch per level, one wave per position) and
+/* Autotuner: for the shape dims, a batch of num_systems such systems (0 or 1: one) and
+ * the precision, builds a plan for every candidate launch configuration --
+ * window_depth from 1 to the largest the shared memory allows, crossed with
+ * BMPC_FLAG_NO_BWD_TOP_MERGE (the backward sweep's top levels in one launch, one
+ * workgroup per chain, or one launch per level, one wave per position) and
  * BMPC_FLAG_FWD_ONE_WAVE (forward positions on up to four waves or on one) -- times the
  * plan's step (FP64: bmpc_factor_solve; FP32: bmpc_factor_refine with one correction) on
- * synthetic SPD data of that shape in device memory (allocated here and freed), the
- * median of reps runs (1..100) after one warm-up, and writes the fastest configuration
- * to *best (num_systems 0) and its time to *best_ms.  times (cap entries, may be NULL
- * with cap = 0) receives each candidate's median in the order tried, *count the number
- * tried.  Synchronizes the stream; not capturable. */
-bmpc_status bmpc_autotune(const bmpc_dims* dims, bmpc_precision prec, void* stream,
-                          int32_t reps, bmpc_options* best, double* best_ms, double* times,
-                          int32_t cap, int32_t* count);
+ * synthetic SPD data in device memory (allocated here and freed), the median of reps
+ * runs (1..100) after one warm-up, and writes the fastest configuration to *best
+ * (num_systems 0) and its time to *best_ms.  One small system measures latency; a batch
+ * that fills the GPU measures throughput, the right criterion for a system that shares
+ * the GPU with many others (a ragged batch).  times (cap entries, may be NULL with
+ * cap = 0) receives each candidate's median in the order tried, *count the number
+ * tried.  Synchronizes the stream; not capturable.  BMPC_ERR_ALLOC if no candidate
+ * fits in device memory. */
+bmpc_status bmpc_autotune(const bmpc_dims* dims, int32_t num_systems, bmpc_precision prec,
+                          void* stream, int32_t reps, bmpc_options* best, double* best_ms,
+                          double* times, int32_t cap, int32_t* count);
 
 /* Replace the stream later calls enqueue on (e.g. a graph-capture stream). */
 bmpc_status bmpc_set_stream(bmpc_plan plan, void* stream);

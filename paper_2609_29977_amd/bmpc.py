@@ -52,7 +52,8 @@ class _QpDims(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("window_depth", ctypes.c_int32), ("num_systems", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("flags", ctypes.c_int32), ("later_depth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class _Cost(ctypes.Structure):
@@ -60,7 +61,7 @@ class _Cost(ctypes.Structure):
                 ("factor_bytes", ctypes.c_double), ("solve_bytes", ctypes.c_double),
                 ("residual_bytes", ctypes.c_double), ("levels", ctypes.c_int32),
                 ("passes", ctypes.c_int32), ("window_depth", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_double)]
+                ("later_depth", ctypes.c_int32), ("workspace_bytes", ctypes.c_double)]
 
 
 @dataclass
@@ -74,6 +75,7 @@ class Cost:
     passes: int
     window_depth: int
     workspace_bytes: float
+    later_depth: int = 0
 
 
 _lib = None
@@ -97,7 +99,8 @@ def lib():
         "bmpc_set_refine_stop": [vp, i32],
         "bmpc_analyze_ragged": [i32, P(_Dims), i32, vp, P(_Options), P(vp)],
         "bmpc_ragged_layout": [vp, i32, P(_Dims), P(i64)],
-        "bmpc_autotune": [P(_Dims), i32, vp, i32, P(_Options), P(dbl), P(dbl), i32, P(i32)],
+        "bmpc_autotune": [P(_Dims), i32, i32, vp, i32, P(_Options), P(dbl), P(dbl), i32,
+                          P(i32)],
         "bmpc_query_structure": [vp, P(i32), P(i32), i64, P(i64)],
         "bmpc_factor": [vp, vp, vp, vp, vp],
         "bmpc_solve": [vp, vp, vp],
@@ -155,7 +158,8 @@ def _prec(precision) -> int:
 
 def _cost(c: _Cost) -> Cost:
     return Cost(c.factor_flops, c.solve_flops, c.factor_bytes, c.solve_bytes,
-                c.residual_bytes, c.levels, c.passes, c.window_depth, c.workspace_bytes)
+                c.residual_bytes, c.levels, c.passes, c.window_depth, c.workspace_bytes,
+                c.later_depth)
 
 
 # ---- host-only helpers -------------------------------------------------------------
@@ -176,9 +180,10 @@ def structure(N: int) -> list:
 
 
 def cost_model(S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
-               window_depth: int = 0, num_systems: int = 1, flags: int = 0) -> Cost:
+               window_depth: int = 0, num_systems: int = 1, flags: int = 0,
+               later_depth: int = 0) -> Cost:
     d = _Dims(S, N, n, nrhs)
-    o = _Options(window_depth, num_systems, flags)
+    o = _Options(window_depth, num_systems, flags, later_depth)
     c = _Cost()
     _check(lib().bmpc_cost_model(ctypes.byref(d), _prec(precision), ctypes.byref(o),
                                  ctypes.byref(c)), "bmpc_cost_model")
@@ -186,9 +191,10 @@ def cost_model(S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
 
 
 def autotune(S: int, N: int, n: int, nrhs: int = 1, precision="fp32", reps: int = 5,
-             stream=None):
-    """Fastest launch configuration for the shape (bmpc_autotune): returns
-    (window_depth, flags, best_ms, candidate_ms)."""
+             stream=None, num_systems: int = 1):
+    """Fastest launch configuration for the shape (bmpc_autotune), timed on one system
+    or on a batch of num_systems of them: returns (window_depth, flags, best_ms,
+    candidate_ms)."""
     import torch
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -197,7 +203,7 @@ def autotune(S: int, N: int, n: int, nrhs: int = 1, precision="fp32", reps: int 
     best_ms = ctypes.c_double(0.0)
     times = (ctypes.c_double * 64)()
     cnt = ctypes.c_int32(0)
-    _check(lib().bmpc_autotune(ctypes.byref(d), _prec(precision),
+    _check(lib().bmpc_autotune(ctypes.byref(d), int(num_systems), _prec(precision),
                                ctypes.c_void_p(stream.cuda_stream), int(reps),
                                ctypes.byref(best), ctypes.byref(best_ms), times, 64,
                                ctypes.byref(cnt)), "bmpc_autotune")
@@ -272,7 +278,8 @@ class Plan:
     different shapes."""
 
     def __init__(self, S: int, N: int, n: int, nrhs: int = 1, precision="fp64",
-                 window_depth: int = 0, stream=None, num_systems: int = 1, flags: int = 0):
+                 window_depth: int = 0, stream=None, num_systems: int = 1, flags: int = 0,
+                 later_depth: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("bmpc needs a HIP device (torch.cuda.is_available() is False)")
@@ -284,7 +291,7 @@ class Plan:
             stream = torch.cuda.current_stream()
         self._stream = stream
         d = _Dims(self.S, self.N, self.n, self.nrhs)
-        o = _Options(int(window_depth), self.B, int(flags))
+        o = _Options(int(window_depth), self.B, int(flags), int(later_depth))
         _check(lib().bmpc_analyze_ex(ctypes.byref(d), self.precision,
                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
                                      ctypes.byref(self._h)), "bmpc_analyze")
@@ -482,7 +489,10 @@ class RaggedPlan(Plan):
         dims = (_Dims * self.B)(*[_Dims(*sh) for sh in shapes])
         if options is None:
             options = [(window_depth, flags)] * self.B
-        opts = (_Options * self.B)(*[_Options(int(w), 0, int(f)) for w, f in options])
+        # (window_depth, flags) or (window_depth, flags, later_depth) per system
+        opts = (_Options * self.B)(*[_Options(int(o[0]), 0, int(o[1]),
+                                              int(o[2]) if len(o) > 2 else 0)
+                                     for o in options])
         _check(lib().bmpc_analyze_ragged(self.B, dims, self.precision,
                                          ctypes.c_void_p(stream.cuda_stream), opts,
                                          ctypes.byref(self._h)), "bmpc_analyze_ragged")

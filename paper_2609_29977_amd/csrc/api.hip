@@ -10,7 +10,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/bmpc.h"
+#include "bmpc.h"
 #include "bmpc_internal.h"
 #include "plan.h"
 
@@ -36,6 +36,12 @@ int default_window_depth(bool fp64, int nmax) {
 
 int ctz_host(unsigned v) { return __builtin_ctz(v); }
 
+int later_depth_default(bool fp64, int Tw, const bmpc_dims& d) {
+  (void)fp64;
+  (void)d;
+  return Tw;
+}
+
 // Permuted position of every chain position (Gamma_{N-1} on the reversed tail,
 // Section IV-A): level-major, positions in increasing order inside a level; X last.
 std::vector<int> make_permpos(int N) {
@@ -54,9 +60,10 @@ std::vector<int> make_perm(int N) {
   return perm;
 }
 
-Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B, bool no_top_merge) {
+Costs make_costs(const bmpc_dims& d, bool fp64, int Tw1, int Tw2, int B, bool no_top_merge) {
   Costs c;
-  c.Tw = Tw;
+  c.Tw = Tw1;
+  c.Tw2 = Tw2;
   const int S = d.S, N = d.N, n = d.n, m = N - 1;
   const double tb = fp64 ? 8.0 : 4.0;
   const double nn = (double)n * n, tri = (double)n * (n + 1) / 2.0;
@@ -65,6 +72,8 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B, bool no_top_merge
   double nG = 0;  // off-diagonal factor blocks per tail
   for (;;) {
     PassPlan p{};
+    const int Tw = shift == 0 ? Tw1 : Tw2;
+    p.tw = Tw;
     p.is_final = mk < (1 << Tw);
     p.windows = p.is_final ? 1 : (mk >> Tw) + 1;
     p.mk = mk;
@@ -223,6 +232,20 @@ int pick_window_depth(bool fp64, int nmax, int nrhs, const bmpc_options* o) {
   return Tw;
 }
 
+// Levels of the passes after the first.  Automatic: the first pass's depth, except
+// where the chain left after the first pass would fill the final pass's one workgroup
+// per chain with a long serial walk; then a smaller depth gives the next pass more
+// workgroups per chain and leaves the final pass a short chain.
+int pick_later_depth(bool fp64, int nmax, int nrhs, int Tw, const bmpc_dims& d,
+                     const bmpc_options* o) {
+  if (nmax > 32) return 1;
+  bmpc_options lo{};
+  if (o) lo = *o;
+  int T2 = (o && o->later_depth > 0) ? o->later_depth : later_depth_default(fp64, Tw, d);
+  lo.window_depth = std::min(T2, kMaxWindowDepth);
+  return pick_window_depth(fp64, nmax, nrhs, &lo);
+}
+
 // Factor passes and root factor; a non-null b also runs the tail forward substitution
 // of that right-hand side inside the passes (y and w as the forward sweep and the X
 // step of the solve leave them).
@@ -239,7 +262,7 @@ FactorPassArgs factor_pass_args(bmpc_plan p, int k, const double* D, const doubl
   a.N = d.N;
   a.n = d.n;
   a.m = p->m;
-  a.Tw = p->Tw;
+  a.Tw = pp.tw;
   a.pass = k;
   a.npass = npass;
   a.mk = pp.mk;
@@ -456,11 +479,12 @@ bmpc_status init_plan(bmpc_plan p, const bmpc_dims* dims, bmpc_precision prec, v
   p->m = dims->N - 1;
   p->nmax = nmax_for(dims->n);
   p->Tw = pick_window_depth(p->fp64, p->nmax, dims->nrhs, opts);
+  p->Tw2 = pick_later_depth(p->fp64, p->nmax, dims->nrhs, p->Tw, *dims, opts);
   p->B = systems_of(opts);
   p->opt_flags = flags_of(opts);
   p->chunk = rhs_chunk(p->nmax);
   p->stream = reinterpret_cast<hipStream_t>(stream);
-  p->costs = make_costs(*dims, p->fp64, p->Tw, p->B, no_top_merge_of(opts));
+  p->costs = make_costs(*dims, p->fp64, p->Tw, p->Tw2, p->B, no_top_merge_of(opts));
   p->perm = make_perm(dims->N);
   p->permpos = make_permpos(dims->N);
   p->groups = std::min(dims->S, 32);
@@ -579,7 +603,8 @@ bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
     return BMPC_ERR_INVALID;
   const bool fp64 = prec == BMPC_FP64;
   const int Tw = pick_window_depth(fp64, nmax_for(dims->n), dims->nrhs, opts);
-  Costs c = make_costs(*dims, fp64, Tw, systems_of(opts), no_top_merge_of(opts));
+  const int Tw2 = pick_later_depth(fp64, nmax_for(dims->n), dims->nrhs, Tw, *dims, opts);
+  Costs c = make_costs(*dims, fp64, Tw, Tw2, systems_of(opts), no_top_merge_of(opts));
   std::memset(cost, 0, sizeof(*cost));
   cost->factor_flops = c.factor_flops;
   cost->solve_flops = c.solve_flops;
@@ -589,6 +614,7 @@ bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
   cost->levels = c.levels;
   cost->passes = (int32_t)c.passes.size();
   cost->window_depth = Tw;
+  cost->later_depth = Tw2;
   return BMPC_OK;
 }
 
@@ -862,6 +888,7 @@ bmpc_status bmpc_query_cost(bmpc_plan p, bmpc_cost* cost) {
       cost->levels = std::max(cost->levels, s->costs.levels);
       cost->passes = std::max(cost->passes, (int32_t)s->costs.passes.size());
       cost->window_depth = std::max(cost->window_depth, s->Tw);
+      cost->later_depth = std::max(cost->later_depth, s->Tw2);
     }
     cost->workspace_bytes = p->workspace_bytes;
     return BMPC_OK;
@@ -874,6 +901,7 @@ bmpc_status bmpc_query_cost(bmpc_plan p, bmpc_cost* cost) {
   cost->levels = p->costs.levels;
   cost->passes = (int32_t)p->costs.passes.size();
   cost->window_depth = p->Tw;
+  cost->later_depth = p->Tw2;
   cost->workspace_bytes = p->workspace_bytes;
   return BMPC_OK;
 }

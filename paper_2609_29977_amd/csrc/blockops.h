@@ -9,6 +9,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace bmpc {
 
 template <int NMAX>
@@ -67,6 +70,10 @@ __device__ inline void lds_store(T* __restrict__ dst, const T* src, int n) {
 
 // ---- wave-uniform broadcast and reciprocal square root ---------------------------
 
+// This wave's index in the workgroup, in a scalar register (the compiler cannot tell
+// that threadIdx.x / 64 is the same on every lane, and would branch on it per lane).
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 __device__ inline float wave_bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -74,6 +81,36 @@ __device__ inline double wave_bcast(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
+}
+
+// v with lane LANE's value replaced by the wave-uniform x (v_writelane with an
+// immediate lane select, so that x is the instruction's one scalar operand).
+template <int LANE>
+__device__ inline int wave_set_lane_b32(int v, int x) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "n"(LANE));
+  return v;
+}
+template <int LANE>
+__device__ inline float wave_set_lane(float v, float x) {
+  return __int_as_float(wave_set_lane_b32<LANE>(__float_as_int(v), __float_as_int(x)));
+}
+template <int LANE>
+__device__ inline double wave_set_lane(double v, double x) {
+  const int lo = wave_set_lane_b32<LANE>(__double2loint(v), __double2loint(x));
+  const int hi = wave_set_lane_b32<LANE>(__double2hiint(v), __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// f(std::integral_constant<int, K>{}) for K = 0 .. N-1 in order (a loop whose index is
+// a constant expression in the body).
+template <typename F, int... Ks>
+__device__ __attribute__((always_inline)) inline void static_for_impl(
+    F&& f, std::integer_sequence<int, Ks...>) {
+  (f(std::integral_constant<int, Ks>{}), ...);
+}
+template <int N, typename F>
+__device__ __attribute__((always_inline)) inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // 1/sqrt(x).  FP32: the hardware reciprocal square root, accurate to about one unit in
@@ -131,13 +168,14 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
 // right-looking Cholesky sweep: step k forms column k of L (L[i][k] on lane i).
 // Lane NMAX + j keeps column j of Z, the inverse being built by the same elimination
 // applied to the identity with unscaled rows: row c of Z loses (L[c][k] / L[k][k])
-// times row k, and row i is divided by L[i][i] at the end.  Both updates of step k
-// are "entry c -= L[c][k] * y" with a per-lane factor y (L[i][k] on a row lane,
-// Z[k][j] / L[k][k] on a column lane), so one readlane broadcast of L[c][k] and one
-// FMA per column c > k serve the factor and the inverse together.  No per-lane
-// branches: row lanes also update entries above the diagonal, which are never read.
-// Blocks smaller than NMAX must be padded with an identity block.  Returns (on
-// every lane) the 0-based row of the first non-positive pivot, or -1.
+// times row k, and row k is divided by L[k][k] once step k has used it.  Both updates
+// of step k are "entry c -= L[c][k] * y" with y = entry k / L[k][k] on every lane
+// (L[i][k] on a row lane, Z[k][j] / L[k][k] on a column lane), so one readlane
+// broadcast of L[c][k] and one FMA per column c > k serve the factor and the inverse
+// together, and entry k keeps y (the finished entry of L^{-1} on a column lane).  No
+// per-lane branches: row lanes also update entries above the diagonal, which are
+// never read.  Blocks smaller than NMAX must be padded with an identity block.
+// Returns (on every lane) the 0-based row of the first non-positive pivot, or -1.
 template <typename T, int NMAX, int LD = Lay<NMAX>::LD>
 __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   static_assert(2 * NMAX <= 64, "two lane groups per wave");
@@ -151,17 +189,20 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
 #pragma unroll
   for (int c = 0; c < NMAX; ++c) v[c] = A[idx * LD + c];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) v[c] = rowl ? v[c] : ((c == idx) ? T(1) : T(0));
+  for (int c = 0; c < NMAX; ++c) v[c] = rowl ? v[c] : T(0);
   int fail = -1;
-  T dinv[NMAX];
-#pragma unroll
-  for (int k = 0; k < NMAX; ++k) {
+  static_for<NMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    // Column lane k's identity entry.  Set here rather than at the start: until step k
+    // it would not change (the entries above a column's diagonal stay zero, so every
+    // earlier step subtracts zero from it), and a per-lane constant per column would
+    // otherwise be kept in a register across the caller's loop.
+    v[k] = wave_set_lane<NMAX + k>(v[k], T(1));
     const T piv = wave_bcast(v[k], k);
     if (fail < 0 && !(piv > T(0))) fail = k;
     const T inv = pivot_rsqrt(piv);
-    dinv[k] = inv;
-    const T lik = v[k] * inv;               // L[i][k] on row lane i (>= k)
-    const T y = rowl ? lik : inv * v[k];    // Z[k][j] / L[k][k] on column lane j
+    const T y = v[k] * inv;  // L[i][k] on row lane i (>= k); Z[k][j] / L[k][k] on column lane j
+    v[k] = y;
     // broadcasts in groups of BG: the scalar reads of a group are issued together
     // (hiding the read-after-write wait) with bounded temporaries
     constexpr int BG = 8;
@@ -170,15 +211,18 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
       T lc[BG];
 #pragma unroll
       for (int u = 0; u < BG; ++u)
-        if (c0 + u < NMAX) lc[u] = wave_bcast(lik, c0 + u);
+        if (c0 + u < NMAX) lc[u] = wave_bcast(y, c0 + u);
 #pragma unroll
       for (int u = 0; u < BG; ++u)
         if (c0 + u < NMAX) v[c0 + u] -= lc[u] * y;
     }
-  }
+  });
+  // Column lane j's entries above the diagonal (i < j) are exact zeros: they start at
+  // zero, and each update subtracts a multiple of y = Z[k][j] / L[k][k] with k < i < j,
+  // itself zero.  So the whole column is stored without a mask.
   if (!rowl && j < NMAX) {
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i) A[i * LD + j] = (i >= j) ? v[i] * dinv[i] : T(0);
+    for (int i = 0; i < NMAX; ++i) A[i * LD + j] = v[i];
   }
   return fail;
 }
@@ -225,7 +269,7 @@ __device__ __attribute__((always_inline)) inline typename Mfma<T>::acc_t mfma_ti
     const T* X, const T* Y) {
   constexpr int LD = Lay<NMAX>::LD;
   constexpr int KS = TileCfg<NMAX>::KSTEPS;
-  const int w = (threadIdx.x >> 6) % (TileCfg<NMAX>::TILES * TileCfg<NMAX>::TILES);
+  const int w = wave_id() % (TileCfg<NMAX>::TILES * TileCfg<NMAX>::TILES);
   const int l = threadIdx.x & 63;
   const int ti = w / TileCfg<NMAX>::TILES, tj = w % TileCfg<NMAX>::TILES;
   const int g = l >> 4, i = l & 15;
@@ -245,12 +289,49 @@ __device__ __attribute__((always_inline)) inline typename Mfma<T>::acc_t mfma_ti
   return acc;
 }
 
+// Row tile ti of op(X) L^T for a lower triangular L (32 x 32 blocks in LDS, L's upper
+// triangle zero): t0 = columns 0..15, which only meet k < 16 (four MFMA steps), t1 =
+// columns 16..31 (eight).  The contraction index of step s is
+// k = 16 (s / 4) + 4 (lane / 16) + s % 4, the same for both tiles, so the first four
+// steps' X operands serve both.  op(X)[r][k] = X[k][r] if TRANSX.  One wave.
+template <typename T, bool TRANSX>
+__device__ __attribute__((always_inline)) inline void mfma_rowtile_lower(
+    const T* X, const T* L, int ti, typename Mfma<T>::acc_t& t0, typename Mfma<T>::acc_t& t1) {
+  constexpr int LD = Lay<32>::LD;
+  const int l = threadIdx.x & 63;
+  const int g = l >> 4, i = l & 15;
+  const int r = ti * 16 + i;
+  t0 = {0, 0, 0, 0};
+  t1 = {0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int k = 16 * (s >> 2) + 4 * g + (s & 3);
+    const T a = TRANSX ? X[k * LD + r] : X[r * LD + k];
+    if (s < 4) t0 = Mfma<T>::mma(a, L[i * LD + k], t0);
+    t1 = Mfma<T>::mma(a, L[(16 + i) * LD + k], t1);
+  }
+}
+
+// out[tile (ti, tj)] = alpha * acc or += alpha * acc for a 32 x 32 block, the tile given.
+template <typename T, bool ACCUMULATE>
+__device__ __attribute__((always_inline)) inline void mfma_tile_store_at(
+    T* out, const typename Mfma<T>::acc_t& acc, T alpha, int ti, int tj) {
+  constexpr int LD = Lay<32>::LD;
+  const int l = threadIdx.x & 63;
+  const int c = tj * 16 + (l & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    T* o = &out[(ti * 16 + Mfma<T>::row(l, v)) * LD + c];
+    *o = ACCUMULATE ? *o + alpha * acc[v] : alpha * acc[v];
+  }
+}
+
 // out[tile] = alpha * acc  or  out[tile] += alpha * acc (NMAX x NMAX blocks)
 template <typename T, int NMAX, bool ACCUMULATE>
 __device__ __attribute__((always_inline)) inline void mfma_tile_store(
     T* out, const typename Mfma<T>::acc_t& acc, T alpha) {
   constexpr int LD = Lay<NMAX>::LD;
-  const int w = (threadIdx.x >> 6) % (TileCfg<NMAX>::TILES * TileCfg<NMAX>::TILES);
+  const int w = wave_id() % (TileCfg<NMAX>::TILES * TileCfg<NMAX>::TILES);
   const int l = threadIdx.x & 63;
   const int ti = w / TileCfg<NMAX>::TILES, tj = w % TileCfg<NMAX>::TILES;
   const int c = tj * 16 + (l & 15);

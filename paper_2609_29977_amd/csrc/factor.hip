@@ -59,7 +59,9 @@ template <int NMAX>
 struct Share {
   static constexpr int NT = TileCfg<NMAX>::NT;
   static constexpr int ELEMS = (NMAX * NMAX + NT - 1) / NT;
-  __device__ static int elem(int j) { return threadIdx.x + j * NT; }
+  // (the mask tells the compiler that the index is below NT, so the loops' range tests
+  // fold away)
+  __device__ static int elem(int j) { return (int)(threadIdx.x & (NT - 1)) + j * NT; }
 };
 
 // Zero an NMAX x NMAX slot (padding included).
@@ -282,7 +284,9 @@ struct FetchOdd {
       const int e = Share<NMAX>::elem(jj);
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
-      li[jj] = (in && c <= r) ? Li[r * (r + 1) / 2 + c] : T(0);
+      // the upper triangle reads the row's diagonal entry (in range) and drops it
+      const T lv = in ? Li[r * (r + 1) / 2 + (c <= r ? c : r)] : T(0);
+      li[jj] = c <= r ? lv : T(0);
       cp[jj] = in ? cpl[r * n + c] : CT(0);
     }
   }
@@ -331,16 +335,19 @@ struct FetchEven {
       accL = reinterpret_cast<const T*>(a.accL_in) + o;
       cpl = reinterpret_cast<const T*>(a.fill_in) + o;
     }
+    // Every element reads its lower-triangle counterpart (D's upper triangle is not
+    // read), so the loads carry no lane mask; the upper half of the slot is never used
+    // before the block is factored.
 #pragma unroll
     for (int jj = 0; jj < EL; ++jj) {
       const int e = Share<NMAX>::elem(jj);
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
-      const bool lower = in && r >= c;
-      d[jj] = lower ? D[r * n + c] : 0.0;
+      const int lo = (r >= c ? r * n + c : c * n + r);
+      d[jj] = in ? D[lo] : 0.0;
       if constexpr (!FIRST) {
-        ar[jj] = lower ? accR[r * n + c] : T(0);
-        al[jj] = lower ? accL[r * n + c] : T(0);
+        ar[jj] = in ? accR[lo] : T(0);
+        al[jj] = in ? accL[lo] : T(0);
       }
       cp[jj] = in ? cpl[r * n + c] : CT(0);
     }
@@ -354,14 +361,12 @@ struct FetchEven {
       if (e >= NMAX * NMAX) continue;
       const int r = e / NMAX, c = e % NMAX;
       const bool in = r < n && c < n;
-      if (in && r >= c) {
-        T v = static_cast<T>(d[jj]);
+      T v = (r == c) ? T(1) : T(0);  // identity padding of diagonal blocks
+      if (in) {
+        v = static_cast<T>(d[jj]);
         if constexpr (!FIRST) v = (v + ar[jj]) + al[jj];
-        A[r * LD + c] = v;
-        A[c * LD + r] = v;
-      } else if (!in) {
-        A[r * LD + c] = (r == c) ? T(1) : T(0);  // identity padding of diagonal blocks
       }
+      A[r * LD + c] = v;
       const T cv = static_cast<T>(cp[jj]);
       if constexpr (FIRST)
         C[c * LD + r] = cv;
@@ -437,17 +442,23 @@ __device__ inline void slot_store(T* __restrict__ dst, const T* src, int n) {
 }
 
 // Lower triangle of an LDS block to global memory, packed by rows: element (r, c),
-// c <= r, at r (r + 1) / 2 + c (the storage of the inverted diagonal blocks).
+// c <= r, at r (r + 1) / 2 + c (the storage of the inverted diagonal blocks).  The
+// threads walk the packed indices, so only the last round has idle lanes: the row of
+// index p is the r with r (r + 1) / 2 <= p < (r + 1) (r + 2) / 2, estimated from the
+// square root and corrected by one where rounding put it off.
 template <typename T, int NMAX>
 __device__ inline void slot_store_packed(T* __restrict__ dst, const T* src, int n) {
   constexpr int LD = Lay<NMAX>::LD;
+  constexpr int NT = TileCfg<NMAX>::NT;
+  const int np = n * (n + 1) / 2;
 #pragma unroll
-  for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
-    const int e = Share<NMAX>::elem(j);
-    if (e < NMAX * NMAX) {
-      const int r = e / NMAX, c = e % NMAX;
-      if (r < n && c <= r) dst[r * (r + 1) / 2 + c] = src[r * LD + c];
-    }
+  for (int p0 = 0; p0 < NMAX * (NMAX + 1) / 2; p0 += NT) {
+    const int p = p0 + (int)threadIdx.x;
+    int r = (int)((__fsqrt_rn(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+    r = (r * (r + 1) / 2 > p) ? r - 1 : r;
+    r = ((r + 1) * (r + 2) / 2 <= p) ? r + 1 : r;
+    const int c = p - r * (r + 1) / 2;
+    if (p < np) dst[p] = src[r * LD + c];
   }
 }
 
@@ -458,7 +469,7 @@ template <typename T, int NMAX>
 __device__ __attribute__((always_inline)) inline void factor_diag(T* A, unsigned long long perm_row0, int n,
                                    unsigned long long* info) {
   constexpr int NW = TileCfg<NMAX>::NT / 64;
-  if ((threadIdx.x >> 6) == (int)(blockIdx.x % NW)) {
+  if (wave_id() == (int)(blockIdx.x % NW)) {
     const int fail = wave_potrf_inv<T, NMAX>(A);
     if (fail >= 0 && fail < n && (threadIdx.x & 63) == 0) atomicMin(info, perm_row0 + fail + 1);
   }
@@ -480,12 +491,31 @@ __device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T*
   typedef typename Mfma<T>::acc_t acc_t;
   if (!have_inverse) factor_diag<T, NMAX>(Aj, perm_row0, n, info);
   const bool left = Cl != nullptr;
-  acc_t gr = mfma_tile_nt<T, NMAX, false>(Cj, Aj);
-  acc_t gl = {0, 0, 0, 0};
-  if (left) gl = mfma_tile_nt<T, NMAX, true>(Cl, Aj);
-  __syncthreads();
-  mfma_tile_store<T, NMAX, false>(Cj, gr, T(1));
-  if (left) mfma_tile_store<T, NMAX, false>(Cl, gl, T(1));
+  if constexpr (NMAX == 32) {
+    // G products: wave w forms row tile w % 2 of G_r (w < 2) or of G_l (w >= 2), both
+    // column tiles, skipping the zero upper quadrant of L^{-1}: 12 MFMA steps per wave
+    // instead of 16.  Without a left neighbour waves 2 and 3 have nothing to do here.
+    const int w = wave_id();
+    const int ti = w & 1;
+    acc_t g0, g1;
+    if (w < 2)
+      mfma_rowtile_lower<T, false>(Cj, Aj, ti, g0, g1);
+    else if (left)
+      mfma_rowtile_lower<T, true>(Cl, Aj, ti, g0, g1);
+    __syncthreads();
+    if (w < 2 || left) {
+      T* G = w < 2 ? Cj : Cl;
+      mfma_tile_store_at<T, false>(G, g0, T(1), ti, 0);
+      mfma_tile_store_at<T, false>(G, g1, T(1), ti, 1);
+    }
+  } else {
+    acc_t gr = mfma_tile_nt<T, NMAX, false>(Cj, Aj);
+    acc_t gl = {0, 0, 0, 0};
+    if (left) gl = mfma_tile_nt<T, NMAX, true>(Cl, Aj);
+    __syncthreads();
+    mfma_tile_store<T, NMAX, false>(Cj, gr, T(1));
+    if (left) mfma_tile_store<T, NMAX, false>(Cl, gl, T(1));
+  }
   if constexpr (FWD)  // y_j = L_jj^{-1} V_j (Aj and Vj are not written in this phase)
     block_matvec<T, NMAX>(Aj, Vj, nrhs, [&](int q, int o, T v) {
       Yt[q * NMAX + o] = v;
@@ -495,18 +525,22 @@ __device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T*
   if (!have_inverse) slot_store_packed<T, NMAX>(gLinv, Aj, n);
   slot_store<T, NMAX>(gGr, Cj, n);
   if (left) slot_store<T, NMAX>(gGl, Cl, n);
-  acc_t ur = mfma_tile_nt<T, NMAX, false>(Cj, Cj);
-  acc_t ul = {0, 0, 0, 0}, uf = {0, 0, 0, 0};
+  // The diagonal blocks' updates are symmetric and only their lower triangles are ever
+  // read (the factorization, and the lower-triangle loads of the next pass), so the
+  // wave of the upper-right tile skips them.
+  const bool upper = TileCfg<NMAX>::TILES == 2 && wave_id() == 1;
+  acc_t ur = {0, 0, 0, 0}, ul = {0, 0, 0, 0}, uf = {0, 0, 0, 0};
+  if (!upper) ur = mfma_tile_nt<T, NMAX, false>(Cj, Cj);
   if (left) {
-    ul = mfma_tile_nt<T, NMAX, false>(Cl, Cl);
+    if (!upper) ul = mfma_tile_nt<T, NMAX, false>(Cl, Cl);
     uf = mfma_tile_nt<T, NMAX, false>(Cj, Cl);
   }
   if constexpr (FWD)  // G_l is still in Cl
     push_products<T, NMAX>(Cj, left ? Cl : nullptr, Yt, Pr, Pl, nrhs);
   __syncthreads();
-  mfma_tile_store<T, NMAX, true>(Ar, ur, T(-1));
+  if (!upper) mfma_tile_store<T, NMAX, true>(Ar, ur, T(-1));
   if (left) {
-    mfma_tile_store<T, NMAX, true>(Al, ul, T(-1));
+    if (!upper) mfma_tile_store<T, NMAX, true>(Al, ul, T(-1));
     mfma_tile_store<T, NMAX, false>(Cl, uf, T(-1));
   }
   if constexpr (FWD) push_apply<T, NMAX>(Vr, left ? Vl : nullptr, Pr, Pl, nrhs);
@@ -520,9 +554,13 @@ constexpr int pass_min_blocks() {
   return FINAL ? 2 : 1;
 }
 
-template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
-__device__ __attribute__((always_inline)) inline void factor_pass_body(const FactorPassArgs& a,
-                                                                       unsigned bx) {
+// FULL: the block size is NMAX (n == NMAX), a compile-time constant here, so that the
+// per-element tests against n in the loads, stores and padding fold away.
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD, bool FULL>
+__device__ __attribute__((always_inline)) inline void factor_pass_body(
+    const FactorPassArgs& a_in, unsigned bx) {
+  FactorPassArgs a = a_in;
+  if constexpr (FULL) a.n = NMAX;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Slots<T, NMAX> sl{reinterpret_cast<T*>(smem_raw), a.Tw, FWD ? a.nrhs * NMAX : 0};
   const int n = a.n, N = a.N;
@@ -581,7 +619,7 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(const Fac
     constexpr int EL = Share<NMAX>::ELEMS;
     constexpr int kBatch = 4;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_id();
     const int nodd = (hi - lo + 1) / 2;
     const int cap = min(kBatch, 2 * a.Tw + 3);
     for (int i0 = 0; i0 < nodd; i0 += cap) {
@@ -845,10 +883,10 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(const Fac
   }
 }
 
-template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD, bool FULL>
 __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
     factor_pass_kernel(FactorPassArgs a) {
-  factor_pass_body<T, NMAX, FIRST, FINAL, FWD>(a, blockIdx.x);
+  factor_pass_body<T, NMAX, FIRST, FINAL, FWD, FULL>(a, blockIdx.x);
 }
 
 __global__ void factor_init_kernel(unsigned long long* info) {
@@ -946,7 +984,7 @@ __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restri
 
 // ---- one launch over the systems of a ragged batch (see multi.h) ----
 
-template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD, bool FULL>
 __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
     factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems, Reloc r) {
   const MultiItem<FactorPassArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
@@ -955,7 +993,7 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
   a.E = rel(r.E, a.E);
   a.C = rel(r.C, a.C);
   a.b = FWD ? rel(r.b, a.b) : nullptr;
-  factor_pass_body<T, NMAX, FIRST, FINAL, FWD>(a, multi_local(it).x);
+  factor_pass_body<T, NMAX, FIRST, FINAL, FWD, FULL>(a, multi_local(it).x);
 }
 
 __global__ void __launch_bounds__(1024) root_reduce_multi(const MultiItem<RootArgs>* items,
@@ -977,27 +1015,35 @@ __global__ void info_reset_kernel(unsigned long long* info, int count) {
     info[i] = ~0ull;
 }
 
-template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
-void launch_multi_kf(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
-                     size_t lds, const Reloc& r, hipStream_t st) {
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD, bool FULL>
+void launch_multi_kff(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
+                      size_t lds, const Reloc& r, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&factor_pass_multi<T, NMAX, FIRST, FINAL, FWD>),
+        reinterpret_cast<const void*>(&factor_pass_multi<T, NMAX, FIRST, FINAL, FWD, FULL>),
         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL((factor_pass_multi<T, NMAX, FIRST, FINAL, FWD>), dim3(blocks),
+  hipLaunchKernelGGL((factor_pass_multi<T, NMAX, FIRST, FINAL, FWD, FULL>), dim3(blocks),
                      dim3(TileCfg<NMAX>::NT), lds, st, items, nitems, r);
+}
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+void launch_multi_kf(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
+                     bool full, size_t lds, const Reloc& r, hipStream_t st) {
+  if (full)
+    launch_multi_kff<T, NMAX, FIRST, FINAL, FWD, true>(items, nitems, blocks, lds, r, st);
+  else
+    launch_multi_kff<T, NMAX, FIRST, FINAL, FWD, false>(items, nitems, blocks, lds, r, st);
 }
 
 template <typename T, int NMAX>
 void launch_multi_pass_t(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
-                         bool first, bool final, bool fwd, size_t lds, const Reloc& r,
-                         hipStream_t st) {
+                         bool first, bool final, bool fwd, bool full, size_t lds,
+                         const Reloc& r, hipStream_t st) {
 #define BMPC_MULTI_KF(F, L, W)                                                          \
   if (first == F && final == L && fwd == W)                                            \
-    return launch_multi_kf<T, NMAX, F, L, W>(items, nitems, blocks, lds, r, st);
+    return launch_multi_kf<T, NMAX, F, L, W>(items, nitems, blocks, full, lds, r, st);
   BMPC_MULTI_KF(true, true, true)
   BMPC_MULTI_KF(true, true, false)
   BMPC_MULTI_KF(true, false, true)
@@ -1016,19 +1062,26 @@ size_t pass_lds_bytes(int Tw, int nrhs_fused) {
          sizeof(T);
 }
 
-template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
-void launch_pass_kf(const FactorPassArgs& a, hipStream_t st) {
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD, bool FULL>
+void launch_pass_kff(const FactorPassArgs& a, hipStream_t st) {
   const size_t lds = pass_lds_bytes<T, NMAX>(a.Tw, FWD ? a.nrhs : 0);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&factor_pass_kernel<T, NMAX, FIRST, FINAL, FWD>),
+        reinterpret_cast<const void*>(&factor_pass_kernel<T, NMAX, FIRST, FINAL, FWD, FULL>),
         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   const unsigned grid = (unsigned)a.S * (unsigned)a.windows;
-  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX, FIRST, FINAL, FWD>), dim3(grid),
+  hipLaunchKernelGGL((factor_pass_kernel<T, NMAX, FIRST, FINAL, FWD, FULL>), dim3(grid),
                      dim3(TileCfg<NMAX>::NT), lds, st, a);
+}
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD>
+void launch_pass_kf(const FactorPassArgs& a, hipStream_t st) {
+  if (a.n == NMAX)
+    launch_pass_kff<T, NMAX, FIRST, FINAL, FWD, true>(a, st);
+  else
+    launch_pass_kff<T, NMAX, FIRST, FINAL, FWD, false>(a, st);
 }
 
 // The fused forward substitution is its own kernel symbol, so the plain factorization
@@ -1085,19 +1138,19 @@ template void launch_factor_pass<float>(const FactorPassArgs&, int, hipStream_t)
 template <typename T>
 void launch_factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems,
                               unsigned blocks, int nmax, bool first, bool final, bool fwd,
-                              size_t lds, const Reloc& r, hipStream_t st) {
+                              bool full, size_t lds, const Reloc& r, hipStream_t st) {
   if (nmax <= 8)
-    launch_multi_pass_t<T, 8>(items, nitems, blocks, first, final, fwd, lds, r, st);
+    launch_multi_pass_t<T, 8>(items, nitems, blocks, first, final, fwd, full, lds, r, st);
   else if (nmax <= 16)
-    launch_multi_pass_t<T, 16>(items, nitems, blocks, first, final, fwd, lds, r, st);
+    launch_multi_pass_t<T, 16>(items, nitems, blocks, first, final, fwd, full, lds, r, st);
   else
-    launch_multi_pass_t<T, 32>(items, nitems, blocks, first, final, fwd, lds, r, st);
+    launch_multi_pass_t<T, 32>(items, nitems, blocks, first, final, fwd, full, lds, r, st);
 }
 template void launch_factor_pass_multi<double>(const MultiItem<FactorPassArgs>*, int, unsigned,
-                                               int, bool, bool, bool, size_t, const Reloc&,
-                                               hipStream_t);
+                                               int, bool, bool, bool, bool, size_t,
+                                               const Reloc&, hipStream_t);
 template void launch_factor_pass_multi<float>(const MultiItem<FactorPassArgs>*, int, unsigned,
-                                              int, bool, bool, bool, size_t, const Reloc&,
+                                              int, bool, bool, bool, bool, size_t, const Reloc&,
                                               hipStream_t);
 
 void launch_root_reduce_multi(const MultiItem<RootArgs>* items, int nitems, unsigned blocks,

@@ -100,10 +100,11 @@ struct SegRec {
 
 // Launchers (next to the kernels they wrap).  items: device table of nitems items in
 // launch order; blocks: the sum of their grids.
+// full: every item has n == nmax.
 template <typename T>
 void launch_factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems,
                               unsigned blocks, int nmax, bool first, bool final, bool fwd,
-                              size_t lds, const Reloc& r, hipStream_t st);
+                              bool full, size_t lds, const Reloc& r, hipStream_t st);
 void launch_root_reduce_multi(const MultiItem<RootArgs>* items, int nitems, unsigned blocks,
                               hipStream_t st);
 void launch_root_potrf_multi(const MultiItem<RootArgs>* items, int nitems, unsigned blocks,

@@ -6,7 +6,7 @@
 
 #include <vector>
 
-#include "../../include/bmpc.h"
+#include "bmpc.h"
 #include "bmpc_internal.h"
 #include "multi.h"
 
@@ -15,7 +15,7 @@ namespace bmpc {
 constexpr int kLdsBudget = 160 * 1024;
 
 struct PassPlan {
-  int mk, shift, windows, is_final;
+  int mk, shift, windows, is_final, tw;  // tw: levels of this pass
   double flops, bytes;  // algorithmic flops / HBM bytes of the pass
 };
 
@@ -30,7 +30,7 @@ struct Costs {
          residual_bytes = 0, L_bytes = 0;
   double pass_flops[KC_COUNT] = {0}, pass_bytes[KC_COUNT] = {0};
   int launches[KC_COUNT] = {0};
-  int levels = 0, Tw = 0;
+  int levels = 0, Tw = 0, Tw2 = 0;
 };
 
 struct RaggedState;  // ragged.hip
@@ -43,7 +43,7 @@ struct bmpc_plan_s {
   bmpc_dims d{};
   bmpc_precision prec = BMPC_FP64;
   bool fp64 = true;
-  int m = 0, nmax = 8, Tw = 1, groups = 1;
+  int m = 0, nmax = 8, Tw = 1, Tw2 = 1, groups = 1;
   int B = 1;      // systems in the batch
   int opt_flags = 0;  // BMPC_FLAG_*
   int chunk = bmpc::kMaxRhs;  // right-hand sides per launch
@@ -104,8 +104,10 @@ struct bmpc_plan_s {
 namespace bmpc {
 
 size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw, int nrhs_fused);
+int pick_later_depth(bool fp64, int nmax, int nrhs, int Tw, const bmpc_dims& d,
+                     const bmpc_options* o);
 int nmax_for(int n);
-Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int B, bool no_top_merge);
+Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int Tw2, int B, bool no_top_merge);
 std::vector<int> make_permpos(int N);
 std::vector<int> make_perm(int N);
 bool dims_ok(const bmpc_dims* d, int B = 1);

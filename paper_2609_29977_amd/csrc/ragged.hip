@@ -251,8 +251,8 @@ void build_factor(bmpc_plan p, Seq& seq, bool fused) {
   int maxpass = 0;
   for (bmpc_plan s : R.subs) maxpass = std::max(maxpass, (int)s->costs.passes.size());
   for (int k = 0; k < maxpass; ++k) {
-    std::map<std::tuple<int, bool>, std::vector<Pending<FactorPassArgs>>> groups;
-    std::map<std::tuple<int, bool>, LaunchRec> recs;
+    std::map<std::tuple<int, bool, bool>, std::vector<Pending<FactorPassArgs>>> groups;
+    std::map<std::tuple<int, bool, bool>, LaunchRec> recs;
     for (int i = 0; i < B; ++i) {
       bmpc_plan s = R.subs[i];
       const int np = (int)s->costs.passes.size();
@@ -262,16 +262,19 @@ void build_factor(bmpc_plan p, Seq& seq, bool fused) {
                                                 fake(R.offC[i]), fused ? fake(R.offV[i]) : nullptr,
                                                 nq);
       const bool fin = k == np - 1;
-      const auto key = std::make_tuple(s->nmax, fin);
+      const bool full = s->d.n == s->nmax;
+      const auto key = std::make_tuple(s->nmax, fin, full);
       groups[key].push_back({i, a, 0, 0, (unsigned)(s->d.S * s->costs.passes[k].windows), 1u, 1u});
       LaunchRec& rec = recs[key];
       rec.op = RO_FACTOR;
+      rec.full = full;
       rec.cls = fin ? KC_FACTOR_FINAL : (k == 0 ? KC_FACTOR_FIRST : KC_FACTOR_MID);
       rec.nmax = s->nmax;
       rec.first = k == 0;
       rec.final = fin;
       rec.fwd = fused;
-      rec.lds = std::max(rec.lds, factor_pass_lds_bytes(s->fp64, s->nmax, s->Tw, nq));
+      rec.lds = std::max(rec.lds,
+                         factor_pass_lds_bytes(s->fp64, s->nmax, s->costs.passes[k].tw, nq));
     }
     for (auto& g : groups) emit(R, seq, recs[g.first], g.second);
   }
@@ -350,7 +353,7 @@ void run(bmpc_plan p, const Seq& seq, const Reloc& r) {
         case RO_FACTOR:
           launch_factor_pass_multi<T>(static_cast<const MultiItem<FactorPassArgs>*>(tab),
                                       rec.nitems, rec.blocks, rec.nmax, rec.first, rec.final,
-                                      rec.fwd, rec.lds, r, st);
+                                      rec.fwd, rec.full, rec.lds, r, st);
           break;
         case RO_ROOT_REDUCE:
           launch_root_reduce_multi(static_cast<const MultiItem<RootArgs>*>(tab), rec.nitems,

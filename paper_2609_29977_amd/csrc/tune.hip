@@ -1,11 +1,14 @@
 // Autotuner of a plan's launch configuration (gfx950).
 //
-// For one shape (S, N, n, nrhs) and precision it builds a plan for every candidate
+// For one shape (S, N, n, nrhs), a batch count and a precision it builds a plan for every candidate
 // configuration -- levels per factor pass (window depth), the backward sweep's top
 // levels in one launch with one workgroup per chain or one launch per level with one
 // wave per position, the forward sweep's positions on up to four waves or on one --
 // and times the plan's own step (FP64: factor + solve; FP32: factor + one refinement
-// correction) on synthetic data in HBM with HIP events, the median of a few runs.  The
+// correction) on synthetic data in HBM with HIP events, the median of a few runs.  One
+// system of a small shape leaves most of the GPU idle and is timed for its latency; a
+// batch of systems (num_systems > 1, the arrays stacked as in a batch plan) is timed for
+// its throughput, which is what a system sharing the GPU with many others sees.  The
 // data is a block-diagonally dominant SPD system; the kernels' timing does not depend
 // on the values.
 #include <hip/hip_runtime.h>
@@ -23,7 +26,8 @@ namespace {
 // D = 2 I, E and C entries 1 / (4 n) (spectral norms <= 1/4), R = (S / 4 + 1) I, b = 1:
 // every row block's diagonal exceeds its off-diagonal norms, so K is SPD.
 __global__ void tune_fill_kernel(double* D, double* E, double* C, double* R, double* b,
-                                 size_t nD, size_t nE, size_t nC, size_t nb, int n, int S) {
+                                 size_t nD, size_t nE, size_t nC, size_t nR, size_t nb, int n,
+                                 int S) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nn = (size_t)n * n;
@@ -34,7 +38,10 @@ __global__ void tune_fill_kernel(double* D, double* E, double* C, double* R, dou
   }
   for (size_t i = t0; i < nE; i += stride) E[i] = off;
   for (size_t i = t0; i < nC; i += stride) C[i] = off;
-  for (size_t i = t0; i < nn; i += stride) R[i] = (i / n == i % n) ? 0.25 * S + 1.0 : 0.0;
+  for (size_t i = t0; i < nR; i += stride) {
+    const size_t e = i % nn;
+    R[i] = (e / n == e % n) ? 0.25 * S + 1.0 : 0.0;
+  }
   for (size_t i = t0; i < nb; i += stride) b[i] = 1.0;
 }
 
@@ -44,17 +51,20 @@ __global__ void tune_fill_kernel(double* D, double* E, double* C, double* R, dou
 
 using namespace bmpc;
 
-extern "C" bmpc_status bmpc_autotune(const bmpc_dims* dims, bmpc_precision prec, void* stream,
-                                     int32_t reps, bmpc_options* best, double* best_ms,
-                                     double* times, int32_t cap, int32_t* count) {
-  if (!dims_ok(dims, 1) || !best || reps < 1 || reps > 100 || cap < 0 || (cap > 0 && !times) ||
+extern "C" bmpc_status bmpc_autotune(const bmpc_dims* dims, int32_t num_systems,
+                                     bmpc_precision prec, void* stream, int32_t reps,
+                                     bmpc_options* best, double* best_ms, double* times,
+                                     int32_t cap, int32_t* count) {
+  const int B = num_systems > 0 ? num_systems : 1;
+  if (!dims_ok(dims, B) || !best || reps < 1 || reps > 100 || cap < 0 || (cap > 0 && !times) ||
       (prec != BMPC_FP64 && prec != BMPC_FP32_REFINE))
     return BMPC_ERR_INVALID;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bmpc_dims& d = *dims;
   const size_t nn = (size_t)d.n * d.n;
-  const size_t nD = (size_t)d.S * d.N * nn, nE = (size_t)d.S * (d.N - 1) * nn;
-  const size_t nC = (size_t)d.S * nn, nb = (size_t)d.nrhs * ((size_t)d.S * d.N + 1) * d.n;
+  const size_t nD = (size_t)B * d.S * d.N * nn, nE = (size_t)B * d.S * (d.N - 1) * nn;
+  const size_t nC = (size_t)B * d.S * nn, nR = (size_t)B * nn;
+  const size_t nb = (size_t)B * d.nrhs * ((size_t)d.S * d.N + 1) * d.n;
   double *D = nullptr, *E = nullptr, *C = nullptr, *R = nullptr, *b = nullptr, *x = nullptr;
   auto release = [&] {
     for (double* p : {D, E, C, R, b, x})
@@ -62,14 +72,14 @@ extern "C" bmpc_status bmpc_autotune(const bmpc_dims* dims, bmpc_precision prec,
   };
   if (hipMalloc((void**)&D, nD * 8) != hipSuccess ||
       hipMalloc((void**)&E, std::max<size_t>(nE, 1) * 8) != hipSuccess ||
-      hipMalloc((void**)&C, nC * 8) != hipSuccess || hipMalloc((void**)&R, nn * 8) != hipSuccess ||
+      hipMalloc((void**)&C, nC * 8) != hipSuccess || hipMalloc((void**)&R, nR * 8) != hipSuccess ||
       hipMalloc((void**)&b, nb * 8) != hipSuccess || hipMalloc((void**)&x, nb * 8) != hipSuccess) {
     (void)hipGetLastError();
     release();
     return BMPC_ERR_ALLOC;
   }
   hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, st, D, E, C, R, b, nD, nE, nC,
-                     nb, d.n, d.S);
+                     nR, nb, d.n, d.S);
   // candidates: every window depth the shared memory allows, crossed with the two sweep
   // mappings
   const bool fp64 = prec == BMPC_FP64;
@@ -83,6 +93,7 @@ extern "C" bmpc_status bmpc_autotune(const bmpc_dims* dims, bmpc_precision prec,
       bmpc_options o{};
       o.window_depth = tw;
       o.flags = f;
+      o.num_systems = B;
       cands.push_back(o);
     }
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -130,6 +141,7 @@ extern "C" bmpc_status bmpc_autotune(const bmpc_dims* dims, bmpc_precision prec,
     if (best_t < 0.0 || med < best_t) {
       best_t = med;
       *best = o;
+      best->num_systems = 0;
     }
   }
   (void)hipEventDestroy(e0);

@@ -60,3 +60,13 @@ def test_tuned_options_in_a_ragged_batch():
         xi = rp.unpack(4, x, i).cpu().numpy().reshape(1, -1)
         assert np.max(np.abs(xi - ref)) <= 1e-10 * np.max(np.abs(ref))
     rp.close()
+
+
+def test_autotune_on_a_batch():
+    """Tuned on a batch of systems (throughput): the choice is still a candidate, and a
+    batch is timed slower than one of its systems."""
+    from paper_2609_29977_amd import bmpc
+    wd1, _, one, _ = bmpc.autotune(16, 40, 16, 1, "fp32", reps=3)
+    wd, flags, many, times = bmpc.autotune(16, 40, 16, 1, "fp32", reps=3, num_systems=64)
+    assert 1 <= wd <= 6 and flags in (0, 1, 2, 3)
+    assert many == pytest.approx(min(times)) and many > one

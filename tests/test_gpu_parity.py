@@ -84,6 +84,44 @@ def test_factor_blocks_match_dense_reordered_cholesky(S, N, n, precision):
         plan.close()
 
 
+@pytest.mark.parametrize("S,N,n", [(2, 129, 32), (1, 256, 32), (3, 64, 17), (2, 100, 31)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("wd,later", [(3, 1), (2, 1), (4, 2), (1, 3)])
+def test_later_pass_depth_gives_the_same_factor(S, N, n, precision, wd, later):
+    """Passes after the first with their own depth: the factor is still chol(Pi K Pi^T)
+    block by block, and the fused factor + solve still matches the oracle."""
+    bm = _bmpc()
+    s = make_system(S, N, n, 1, 1e-1, 8)
+    K = dense.assemble_K(s.D, s.E, s.C, s.R)
+    p = dense.perm_index(S, N, n, "d")
+    L = np.linalg.cholesky(K[np.ix_(p, p)])
+    D, E, C, R, b = dev(s)
+    tol = 1e-12 if precision == "fp64" else 5e-5
+    plan = bm.Plan(S, N, n, 1, precision, wd, later_depth=later)
+    c = plan.cost()
+    assert (c.window_depth, c.later_depth) == (wd, later)
+    plan.factor(D, E, C, R)
+    Nn = N * n
+    scale = np.max(np.abs(L))
+    for t in range(S):
+        Lt, F = plan.export_tail_factor(t)
+        got = Lt.copy()
+        for k in range(N):
+            blk = slice(k * n, (k + 1) * n)
+            got[blk, blk] = np.linalg.inv(Lt[blk, blk])
+        assert np.max(np.abs(got - L[t * Nn:(t + 1) * Nn, t * Nn:(t + 1) * Nn])) <= tol * scale
+    ref, _ = oracle.solve(s.D, s.E, s.C, s.R, s.b, nthreads=4)
+    if precision == "fp64":
+        x = plan.factor_solve(D, E, C, R, b)
+        bar = 1e-11
+    else:
+        x = plan.factor_refine(D, E, C, R, b, tol=1e-13, max_iters=10)
+        bar = 1e-10
+    assert rel_inf(x.cpu().numpy(), ref) <= bar
+    assert plan.info() == 0
+    plan.close()
+
+
 @pytest.mark.parametrize("S,N,n", SHAPES)
 def test_fp64_solve_matches_oracle(S, N, n):
     s = make_system(S, N, n, 2, 1e-2, 11)

@@ -87,3 +87,21 @@ def test_cost_model_counts_right_hand_side_chunks():
     twelve = bmpc.cost_model(16, 33, 8, 12, "fp64")
     assert twelve.solve_flops == pytest.approx(12 * one.solve_flops, rel=1e-12)
     assert twelve.factor_flops == one.factor_flops
+
+
+@pytest.mark.parametrize("N,wd,later", [(256, 4, 4), (256, 4, 2), (256, 3, 1), (129, 2, 3),
+                                        (64, 1, 5), (17, 4, 1), (2, 3, 1)])
+def test_cost_model_pass_depths(N, wd, later):
+    """The first pass eliminates wd levels of the chain, every later pass `later` levels
+    of what is left, until fewer than 2^depth positions remain for the final pass; the
+    flop count does not depend on the schedule."""
+    c = bmpc.cost_model(8, N, 16, 1, "fp32", window_depth=wd, later_depth=later)
+    assert (c.window_depth, c.later_depth) == (wd, later)
+    mk, depth, passes = N - 1, wd, 1
+    while mk >= (1 << depth):
+        mk >>= depth
+        depth = later
+        passes += 1
+    assert c.passes == passes
+    base = bmpc.cost_model(8, N, 16, 1, "fp32")
+    assert c.factor_flops == pytest.approx(base.factor_flops, rel=1e-12)
