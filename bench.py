@@ -59,7 +59,7 @@ def log(msg):
 
 # The translation unit of the factor pass kernels: the measured HBM traffic of a
 # factor pass stays valid while none of these files changes.
-FACTOR_SOURCES = ("factor.hip", "bmpc_internal.h", "blockops.h", "regblock.h")
+FACTOR_SOURCES = ("factor.hip", "bmpc_internal.h", "blockops.h", "multi.h", "regblock.h")
 
 
 def source_digest(names=None):

@@ -71,10 +71,12 @@ typedef enum {
 typedef struct {
   int32_t S;    /* scenarios, >= 1 */
   int32_t N;    /* stages per tail, >= 1 */
-  int32_t n;    /* block size n_b (Assumption 1, uniform), 1..32 */
-  int32_t nrhs; /* right-hand sides per solve, >= 1 (Section III-B partitions each
+  int32_t n;    /* block size n_b (Assumption 1, uniform), 1..64.  Blocks of 33..64
+                   are factored one level per pass (two 32 x 32 quadrants per block
+                   dimension) and without the fused forward substitution */
+  int32_t nrhs; /* right-hand sides per solve, 1..4096 (Section III-B partitions each
                    right-hand side like the unknowns; their number is free).  The
-                   kernels take them in chunks of 8. */
+                   kernels take them in chunks of 8 (n <= 32) or 4 (n > 32). */
 } bmpc_dims;
 
 /* bmpc_options.flags */
@@ -124,7 +126,9 @@ typedef struct bmpc_plan_s* bmpc_plan;
  * persistent workspaces).  Validates dims, builds the ordering Pi_i
  * (Section IV-A: reverse the tail, apply Gamma_{N-1} to (x_N..x_2), keep x_1 last),
  * the level table and the factor structure, and allocates every workspace.  Reads
- * no caller array.  BMPC_ERR_INVALID for bad dims (n > 32 is unsupported),
+ * no caller array.  BMPC_ERR_INVALID for bad dims (S, N < 1; n outside 1..64; nrhs
+ * outside 1..4096; or sizes whose element counts would overflow the 32-bit grid and
+ * index arithmetic: S*N*n < 2e9, nrhs*(S*N+1)*n < 4e9 per plan),
  * BMPC_ERR_ALLOC when device memory runs out, BMPC_ERR_DEVICE if no GPU.
  * On success *out owns its workspaces until bmpc_destroy. */
 bmpc_status bmpc_analyze(const bmpc_dims* dims, bmpc_precision prec, void* stream,

@@ -744,7 +744,11 @@ static bmpc_status refine_impl(bmpc_plan p, const double* D, const double* E, co
                                p->kper, p->kroot, p->knorm, p->bnorm, tol, 1, p->flags,
                                p->relcorr, rnorm, st);
       });
-      if ((stopped = stop_reached(p))) break;
+      // The first solve of an FP32 plan cannot meet a tolerance far below FP32's
+      // rounding, so the host does not wait for that check (the device still applies it:
+      // the later launches of a converged loop return at once).
+      const bool hopeless = it == 0 && !p->fp64 && tol < 0x1p-30;
+      if (!hopeless && (stopped = stop_reached(p))) break;
     } else {
       timed(p, KC_REFINE_MISC, [&] {
         launch_maxabs(p->rbuf, segs, len, p->npart, rnorm, p->flags, st);

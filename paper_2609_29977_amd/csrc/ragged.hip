@@ -519,7 +519,9 @@ bmpc_status ragged_refine(bmpc_plan p, const double* D, const double* E, const d
     residual(be && it == 0);
     if (be) {
       check(1, nullptr, it == 0, 1);
-      if ((stopped = stop_reached(p))) break;
+      // as in the one-system loop: no host wait on an FP32 first solve's check
+      const bool hopeless = it == 0 && !p->fp64 && tol < 0x1p-30;
+      if (!hopeless && (stopped = stop_reached(p))) break;
     } else {
       timed(p, KC_REFINE_MISC, [&] {
         launch_seg_maxabs(R.rbuf, nullptr, R.segs, R.nseg, R.rnorm, nullptr, p->flags, st);

@@ -311,14 +311,31 @@ __device__ __attribute__((always_inline)) inline void residual_root_body(const R
     __syncthreads();
   }
   if (a.knorm_root) {
-    // root rows of |K|: |C_s| rows summed over the scenarios in order, plus |R|
+    // root rows of |K|: the |C_s| row sums of the scenarios (G interleaved groups, each
+    // in scenario order, then the groups in order, as the sum of w above), plus |R|
+    const double* cr = a.crow + (size_t)sys * S * n;
+    double acc = 0.0;
+    if (i < n) {
+      constexpr int B = 8;
+      for (int s0 = g; s0 < S; s0 += G * B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int sc = s0 + G * u;
+          v[u] = sc < S ? cr[(size_t)sc * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) acc += v[u];
+      }
+    }
+    part[g][i] = acc;
+    __syncthreads();
     double m = 0.0;
     if (t < n) {
-      const double* cr = a.crow + (size_t)sys * S * n;
-      double acc = 0.0;
-      for (int sc = 0; sc < S; ++sc) acc += cr[(size_t)sc * n + t];
-      for (int c = 0; c < n; ++c) acc += fabs(t >= c ? R[t * n + c] : R[c * n + t]);
-      m = acc;
+      double sum = 0.0;
+      for (int gg = 0; gg < G; ++gg) sum += part[gg][t];
+      for (int c = 0; c < n; ++c) sum += fabs(t >= c ? R[t * n + c] : R[c * n + t]);
+      m = sum;
     }
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
     if (t == 0) a.knorm_root[sys] = m;  // n <= 64: the rows sit in wave 0
