@@ -70,6 +70,9 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw1, int Tw2, int B, bool no
   const double len = ((double)S * N + 1) * n;
   int mk = m, shift = 0;
   double nG = 0;  // off-diagonal factor blocks per tail
+  // the odd positions' inverses of the first pass come from their own kernel (n <= 32)
+  const bool level1 = n <= 32 && m >= 1;
+  double l1_fl = 0, l1_by = 0;
   for (;;) {
     PassPlan p{};
     const int Tw = shift == 0 ? Tw1 : Tw2;
@@ -83,9 +86,18 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw1, int Tw2, int B, bool no
       const int v = ctz_host((unsigned)q);
       if (!p.is_final && v >= Tw) continue;  // a window boundary, eliminated later
       const int hl = (q != (1 << v)) ? 1 : 0;
+      nG += 1 + hl;
+      if (shift == 0 && level1 && v == 0) {
+        // inverted beforehand (level1_inverse_kernel: read D, write L_jj^{-1}); the pass
+        // reads the inverse back and writes the G's
+        l1_fl += potrf_flops(n);
+        l1_by += 8.0 * tri + tb * tri;
+        fl += (1 + hl) * (trsm_flops(n) + syrk_flops(n)) + hl * gemm_flops(n);
+        by += tb * (tri + (1 + hl) * nn);
+        continue;
+      }
       fl += potrf_flops(n) + (1 + hl) * (trsm_flops(n) + syrk_flops(n)) + hl * gemm_flops(n);
       by += 8.0 * tri + tb * (tri + (1 + hl) * nn);  // read D, write L_jj^{-1}, G's
-      nG += 1 + hl;
     }
     if (shift == 0) by += 8.0 * nn * m;  // every E block is read by the first pass
     if (p.is_final) {
@@ -107,6 +119,9 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw1, int Tw2, int B, bool no
     c.pass_bytes[cls] += p.bytes;
     c.factor_flops += p.flops;
   }
+  c.pass_flops[KC_FACTOR_L1INV] = l1_fl * S;
+  c.pass_bytes[KC_FACTOR_L1INV] = l1_by * S;
+  c.factor_flops += l1_fl * S;
   c.factor_flops += (double)S * nn + potrf_flops(n);  // root reduction + root Cholesky
   c.pass_flops[KC_ROOT_POTRF] = potrf_flops(n) + (double)S * nn;
   const double K_bytes = 8.0 * ((double)S * N * tri + (double)S * m * nn + (double)S * nn + tri);
@@ -141,6 +156,7 @@ Costs make_costs(const bmpc_dims& d, bool fp64, int Tw1, int Tw2, int B, bool no
   c.pass_flops[KC_RESIDUAL_ROOT] = q * 2.0 * ((double)S * nn + nn);
   const int L = chain_levels(m);
   for (int k = 0; k < KC_COUNT; ++k) c.launches[k] = 1;
+  if (!level1) c.launches[KC_FACTOR_L1INV] = 0;
   // the solve and residual classes run once per chunk of right-hand sides
   const int ck = rhs_chunk(nmax_for(n));
   const int chunks = (d.nrhs + ck - 1) / ck, last = d.nrhs - (chunks - 1) * ck;
@@ -341,6 +357,10 @@ void enqueue_factor(bmpc_plan p, const double* D, const double* E, const double*
   hipStream_t st = p->stream;
   timed(p, KC_FACTOR_INIT, [&] { launch_factor_init(p->d_info, st); });
   const int npass = (int)p->costs.passes.size();
+  if (p->nmax <= 32 && d.N > 1) {
+    const FactorPassArgs a0 = factor_pass_args(p, 0, D, E, C, nullptr, 0);
+    timed(p, KC_FACTOR_L1INV, [&] { launch_level1_inverse<T>(a0, p->nmax, st); });
+  }
   for (int k = 0; k < npass; ++k) {
     const PassPlan& pp = p->costs.passes[k];
     const FactorPassArgs a = factor_pass_args(p, k, D, E, C, b, nq);
@@ -1041,7 +1061,7 @@ const char* bmpc_kernel_class_name(int32_t cls) {
       "factor_init",  "factor_first_pass", "factor_mid_pass", "factor_final_pass",
       "root_reduce",  "root_potrf",        "solve_fwd",       "solve_x_fwd",
       "solve_root",   "solve_x_bwd",       "solve_bwd",       "residual",
-      "residual_root", "refine_misc",     "grad_blocks"};
+      "residual_root", "refine_misc",     "grad_blocks",     "factor_level1_inverse"};
   if (cls < 0 || cls >= KC_COUNT) return "";
   return names[cls];
 }

@@ -58,6 +58,7 @@ enum KernelClass : int {
   KC_RESIDUAL_ROOT,  // FP64 root residual
   KC_REFINE_MISC,    // refinement bookkeeping (norm reset, stop test)
   KC_GRAD_BLOCKS,    // block gradients through the solve
+  KC_FACTOR_L1INV,   // level-1 diagonal inverses before the first factor pass
   KC_COUNT
 };
 
@@ -172,6 +173,10 @@ struct GradArgs {
 // launchers (defined next to their kernels)
 template <typename T>
 void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st);
+// L^{-1} of the odd chain positions' diagonal blocks (D only), before the first pass
+// (whose arguments a are).
+template <typename T>
+void launch_level1_inverse(const FactorPassArgs& a, int nmax, hipStream_t st);
 // block sizes 33..64: window depth 1, no fused forward substitution (factor64.hip)
 template <typename T>
 void launch_factor_pass64(const FactorPassArgs& a, hipStream_t st);

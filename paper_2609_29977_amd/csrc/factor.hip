@@ -606,9 +606,10 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(
   FetchEven<T, NMAX, FIRST, FWD> fe;
   if constexpr (kEarlyEvenFetch)
     if (lo + 2 <= hi) fe.issue(a, vc, s, lo + 2);
-  // Prologue: the pass-local level-1 positions (odd q) see no update from inside the
-  // window, so their diagonal blocks (D plus updates carried from earlier passes) are
-  // factored and inverted up front.  Up to kBatch blocks at a time are loaded by the
+  // Prologue (passes after the first): the pass-local level-1 positions (odd q) see no
+  // update from inside the window, so their diagonal blocks (D plus updates carried from
+  // earlier passes) are factored and inverted up front.  In the first pass these blocks
+  // are D alone, and level1_inverse_kernel has inverted them before the pass.  Up to kBatch blocks at a time are loaded by the
   // whole workgroup into the window's still unused LDS slots (all loads in flight at
   // once), then each wave inverts its share of them, and the inverses go to the
   // factor storage; the streaming phase below reloads them.
@@ -620,7 +621,8 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(
     constexpr int kBatch = 4;
     const int lane = threadIdx.x & 63;
     const int wv = wave_id();
-    const int nodd = (hi - lo + 1) / 2;
+    // the first pass's level-1 inverses come from level1_inverse_kernel
+    const int nodd = FIRST ? 0 : (hi - lo + 1) / 2;
     const int cap = min(kBatch, 2 * a.Tw + 3);
     for (int i0 = 0; i0 < nodd; i0 += cap) {
       const int cnt = min(cap, nodd - i0);
@@ -889,6 +891,70 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
   factor_pass_body<T, NMAX, FIRST, FINAL, FWD, FULL>(a, blockIdx.x);
 }
 
+// Level-1 inverses of the first pass.  The odd chain positions (level 1 of Gamma's
+// order) take no Schur update from the rest of the chain, so L_jj^{-1} of their
+// diagonal blocks depends on D alone (Algorithm 1's diagonal factorizations at the
+// lowest level, all independent).  One wave per block, four blocks per workgroup, at
+// full occupancy: the blocks are factored here instead of in each window's prologue,
+// where three of a workgroup's four waves would wait on the serial factorization.
+// Block bi of the launch is the (bi % nodd)-th odd position of chain bi / nodd.
+template <typename T, int NMAX, bool FULL>
+__device__ __attribute__((always_inline)) inline void level1_inverse_body(
+    const FactorPassArgs& a_in, unsigned bi, int nodd, unsigned total) {
+  FactorPassArgs a = a_in;
+  if constexpr (FULL) a.n = NMAX;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int LD = Lay<NMAX>::LD;
+  constexpr int SZ = Lay<NMAX>::SZ;
+  if (bi >= total) return;  // the whole wave leaves; no workgroup barrier follows
+  T* slot = reinterpret_cast<T*>(smem_raw) + wave_id() * SZ;
+  const int n = a.n, N = a.N;
+  const size_t nn = (size_t)n * n;
+  const int s = (int)(bi / (unsigned)nodd);
+  const int j = 2 * (int)(bi - (unsigned)s * nodd) + 1;
+  const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
+  const int lane = threadIdx.x & 63;
+  // the symmetric block from D's lower triangle, identity padded
+  double dv[NMAX * NMAX / 64];
+#pragma unroll
+  for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+    const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
+    dv[u] = (r < n && c < n) ? D[r >= c ? r * n + c : c * n + r] : (r == c ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+    const int e = lane + 64 * u;
+    slot[(e / NMAX) * LD + e % NMAX] = static_cast<T>(dv[u]);
+  }
+  wave_lds_fence();
+  const int fail = wave_potrf_inv<T, NMAX>(slot);
+  if (fail >= 0 && fail < n && lane == 0) {
+    const int sys = s / a.Ssys;
+    const unsigned long long row0 =
+        (unsigned long long)sys * ((unsigned long long)a.Ssys * N + 1) * n +
+        (unsigned long long)(s - sys * a.Ssys) * N * n;
+    atomicMin(a.info, row0 + (unsigned long long)a.permpos[j - 1] * n + fail + 1);
+  }
+  wave_lds_fence();
+  // packed lower triangle, as slot_store_packed but by one wave
+  T* Li = reinterpret_cast<T*>(a.Linv) + ((size_t)s * N + (j - 1)) * nn;
+  const int np = n * (n + 1) / 2;
+#pragma unroll
+  for (int p0 = 0; p0 < NMAX * (NMAX + 1) / 2; p0 += 64) {
+    const int p = p0 + lane;
+    int r = (int)((__fsqrt_rn(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+    r = (r * (r + 1) / 2 > p) ? r - 1 : r;
+    r = ((r + 1) * (r + 2) / 2 <= p) ? r + 1 : r;
+    if (p < np) Li[p] = slot[r * LD + (p - r * (r + 1) / 2)];
+  }
+}
+
+template <typename T, int NMAX, bool FULL>
+__global__ void __launch_bounds__(256) level1_inverse_kernel(FactorPassArgs a, int nodd,
+                                                             unsigned total) {
+  level1_inverse_body<T, NMAX, FULL>(a, blockIdx.x * 4u + (unsigned)wave_id(), nodd, total);
+}
+
 __global__ void factor_init_kernel(unsigned long long* info) {
   if (threadIdx.x == 0) *info = ~0ull;
 }
@@ -994,6 +1060,17 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
   a.C = rel(r.C, a.C);
   a.b = FWD ? rel(r.b, a.b) : nullptr;
   factor_pass_body<T, NMAX, FIRST, FINAL, FWD, FULL>(a, multi_local(it).x);
+}
+
+// Ragged batches: item p0 = odd positions per chain, p1 = blocks of the system.
+template <typename T, int NMAX, bool FULL>
+__global__ void __launch_bounds__(256) level1_inverse_multi(const MultiItem<FactorPassArgs>* items,
+                                                            int nitems, Reloc r) {
+  const MultiItem<FactorPassArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
+  FactorPassArgs a = it.a;
+  a.D = rel(r.D, a.D);
+  level1_inverse_body<T, NMAX, FULL>(a, multi_local(it).x * 4u + (unsigned)wave_id(), it.p0,
+                                     (unsigned)it.p1);
 }
 
 __global__ void __launch_bounds__(1024) root_reduce_multi(const MultiItem<RootArgs>* items,
@@ -1134,6 +1211,63 @@ void launch_factor_pass(const FactorPassArgs& a, int nmax, hipStream_t st) {
 }
 template void launch_factor_pass<double>(const FactorPassArgs&, int, hipStream_t);
 template void launch_factor_pass<float>(const FactorPassArgs&, int, hipStream_t);
+
+namespace {
+template <typename T, int NMAX>
+void launch_l1inv_t(const FactorPassArgs& a, hipStream_t st) {
+  const int nodd = (a.m + 1) / 2;
+  const unsigned total = (unsigned)a.S * (unsigned)nodd;
+  if (total == 0) return;
+  const size_t lds = 4 * (size_t)Lay<NMAX>::SZ * sizeof(T);
+  const dim3 grid((total + 3) / 4);
+  if (a.n == NMAX)
+    hipLaunchKernelGGL((level1_inverse_kernel<T, NMAX, true>), grid, dim3(256), lds, st, a, nodd,
+                       total);
+  else
+    hipLaunchKernelGGL((level1_inverse_kernel<T, NMAX, false>), grid, dim3(256), lds, st, a,
+                       nodd, total);
+}
+template <typename T, int NMAX>
+void launch_l1inv_multi_t(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
+                          bool full, const Reloc& r, hipStream_t st) {
+  const size_t lds = 4 * (size_t)Lay<NMAX>::SZ * sizeof(T);
+  if (full)
+    hipLaunchKernelGGL((level1_inverse_multi<T, NMAX, true>), dim3(blocks), dim3(256), lds, st,
+                       items, nitems, r);
+  else
+    hipLaunchKernelGGL((level1_inverse_multi<T, NMAX, false>), dim3(blocks), dim3(256), lds, st,
+                       items, nitems, r);
+}
+}  // namespace
+
+template <typename T>
+void launch_level1_inverse(const FactorPassArgs& a, int nmax, hipStream_t st) {
+  if (nmax <= 8)
+    launch_l1inv_t<T, 8>(a, st);
+  else if (nmax <= 16)
+    launch_l1inv_t<T, 16>(a, st);
+  else
+    launch_l1inv_t<T, 32>(a, st);
+}
+template void launch_level1_inverse<double>(const FactorPassArgs&, int, hipStream_t);
+template void launch_level1_inverse<float>(const FactorPassArgs&, int, hipStream_t);
+
+template <typename T>
+void launch_level1_inverse_multi(const MultiItem<FactorPassArgs>* items, int nitems,
+                                 unsigned blocks, int nmax, bool full, const Reloc& r,
+                                 hipStream_t st) {
+  if (nmax <= 8)
+    launch_l1inv_multi_t<T, 8>(items, nitems, blocks, full, r, st);
+  else if (nmax <= 16)
+    launch_l1inv_multi_t<T, 16>(items, nitems, blocks, full, r, st);
+  else
+    launch_l1inv_multi_t<T, 32>(items, nitems, blocks, full, r, st);
+}
+template void launch_level1_inverse_multi<double>(const MultiItem<FactorPassArgs>*, int,
+                                                  unsigned, int, bool, const Reloc&,
+                                                  hipStream_t);
+template void launch_level1_inverse_multi<float>(const MultiItem<FactorPassArgs>*, int, unsigned,
+                                                 int, bool, const Reloc&, hipStream_t);
 
 template <typename T>
 void launch_factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems,

@@ -105,6 +105,12 @@ template <typename T>
 void launch_factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems,
                               unsigned blocks, int nmax, bool first, bool final, bool fwd,
                               bool full, size_t lds, const Reloc& r, hipStream_t st);
+// Level-1 inverses of a ragged batch: item p0 = odd positions per chain, p1 = blocks
+// (one per wave, four per workgroup) of the system.
+template <typename T>
+void launch_level1_inverse_multi(const MultiItem<FactorPassArgs>* items, int nitems,
+                                 unsigned blocks, int nmax, bool full, const Reloc& r,
+                                 hipStream_t st);
 void launch_root_reduce_multi(const MultiItem<RootArgs>* items, int nitems, unsigned blocks,
                               hipStream_t st);
 void launch_root_potrf_multi(const MultiItem<RootArgs>* items, int nitems, unsigned blocks,

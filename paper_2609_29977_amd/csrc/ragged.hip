@@ -28,7 +28,8 @@ enum RaggedOp {
   RO_ROOT_POTRF,
   RO_SOLVE,
   RO_RESIDUAL,
-  RO_RESIDUAL_ROOT
+  RO_RESIDUAL_ROOT,
+  RO_L1INV
 };
 
 struct LaunchRec {
@@ -248,6 +249,29 @@ void build_factor(bmpc_plan p, Seq& seq, bool fused) {
     rec.cls = KC_FACTOR_INIT;
     seq.push_back(rec);
   }
+  {
+    // level-1 inverses of every system's first pass, one launch per tile size and
+    // n == NMAX (one wave per block, four per workgroup)
+    std::map<std::tuple<int, bool>, std::vector<Pending<FactorPassArgs>>> groups;
+    for (int i = 0; i < B; ++i) {
+      bmpc_plan s = R.subs[i];
+      const int nodd = s->d.N / 2;  // odd positions 1, 3, .. of the N - 1 chain positions
+      if (nodd == 0) continue;
+      const FactorPassArgs a = factor_pass_args(s, 0, fake(R.offD[i]), fake(R.offE[i]),
+                                                fake(R.offC[i]), nullptr, 0);
+      const unsigned total = (unsigned)(s->B * s->d.S) * (unsigned)nodd;
+      groups[std::make_tuple(s->nmax, s->d.n == s->nmax)].push_back(
+          {i, a, nodd, (int)total, (total + 3) / 4, 1u, 1u});
+    }
+    for (auto& g : groups) {
+      LaunchRec rec;
+      rec.op = RO_L1INV;
+      rec.cls = KC_FACTOR_L1INV;
+      rec.nmax = std::get<0>(g.first);
+      rec.full = std::get<1>(g.first);
+      emit(R, seq, rec, g.second);
+    }
+  }
   int maxpass = 0;
   for (bmpc_plan s : R.subs) maxpass = std::max(maxpass, (int)s->costs.passes.size());
   for (int k = 0; k < maxpass; ++k) {
@@ -349,6 +373,10 @@ void run(bmpc_plan p, const Seq& seq, const Reloc& r) {
       switch (rec.op) {
         case RO_INFO_RESET:
           launch_info_reset(R.info, (int)R.subs.size(), st);
+          break;
+        case RO_L1INV:
+          launch_level1_inverse_multi<T>(static_cast<const MultiItem<FactorPassArgs>*>(tab),
+                                         rec.nitems, rec.blocks, rec.nmax, rec.full, r, st);
           break;
         case RO_FACTOR:
           launch_factor_pass_multi<T>(static_cast<const MultiItem<FactorPassArgs>*>(tab),
