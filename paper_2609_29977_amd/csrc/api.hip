@@ -29,9 +29,12 @@ double gemm_flops(double n) { return 2.0 * n * n * n; }
 // to 256): deeper windows save pass launches and boundary traffic but lengthen the
 // serial walk of each window, which sets the pass time once the chains are short or
 // few; 3 (FP64) and 4 (FP32) were fastest or within a few percent of it throughout.
+// Levels per pass, measured on the paper-grid and c2/c3 shapes: four for FP32 blocks
+// up to 16, three otherwise (FP64, whose slots are twice as large; FP32 32 x 32 blocks,
+// where three levels let four workgroups share a CU).
 int default_window_depth(bool fp64, int nmax) {
   if (nmax > 32) return 1;  // blocks of 33..64: one level per pass (factor64.hip)
-  return fp64 ? 3 : 4;
+  return (fp64 || nmax == 32) ? 3 : 4;
 }
 
 int ctz_host(unsigned v) { return __builtin_ctz(v); }

@@ -547,11 +547,15 @@ __device__ __attribute__((always_inline)) inline void eliminate(T* Aj, T* Cj, T*
   __syncthreads();
 }
 
-// The last pass has one workgroup per chain; two per CU keep all of them resident, so
-// its register budget is held to that.
-template <bool FINAL>
+// Waves per SIMD the register allocation must allow.  The last pass has one workgroup
+// per chain; two per CU keep all of them resident.  The FP32 first pass of 32 x 32
+// blocks fits in 128 registers without spilling, which with three levels per pass
+// (39 KB of LDS) lets four workgroups share a CU instead of three: measured against
+// four levels at three workgroups, the first pass is 16% and the whole factorization 5%
+// faster.
+template <typename T, int NMAX, bool FIRST, bool FINAL, bool FULL>
 constexpr int pass_min_blocks() {
-  return FINAL ? 2 : 1;
+  return FINAL ? 2 : ((FIRST && FULL && NMAX == 32 && sizeof(T) == 4) ? 4 : 1);
 }
 
 // FULL: the block size is NMAX (n == NMAX), a compile-time constant here, so that the
@@ -886,7 +890,8 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(
 }
 
 template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD, bool FULL>
-__global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
+__global__ void __launch_bounds__(TileCfg<NMAX>::NT,
+                                  (pass_min_blocks<T, NMAX, FIRST, FINAL, FULL>()))
     factor_pass_kernel(FactorPassArgs a) {
   factor_pass_body<T, NMAX, FIRST, FINAL, FWD, FULL>(a, blockIdx.x);
 }
@@ -1051,7 +1056,8 @@ __global__ void __launch_bounds__(1024) root_potrf_kernel(const double* __restri
 // ---- one launch over the systems of a ragged batch (see multi.h) ----
 
 template <typename T, int NMAX, bool FIRST, bool FINAL, bool FWD, bool FULL>
-__global__ void __launch_bounds__(TileCfg<NMAX>::NT, (pass_min_blocks<FINAL>()))
+__global__ void __launch_bounds__(TileCfg<NMAX>::NT,
+                                  (pass_min_blocks<T, NMAX, FIRST, FINAL, FULL>()))
     factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems, Reloc r) {
   const MultiItem<FactorPassArgs>& it = items[multi_find(items, nitems, blockIdx.x)];
   FactorPassArgs a = it.a;
