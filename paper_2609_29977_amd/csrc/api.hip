@@ -39,11 +39,6 @@ int default_window_depth(bool fp64, int nmax) {
 
 int ctz_host(unsigned v) { return __builtin_ctz(v); }
 
-int later_depth_default(bool fp64, int Tw, const bmpc_dims& d) {
-  (void)fp64;
-  (void)d;
-  return Tw;
-}
 
 // Permuted position of every chain position (Gamma_{N-1} on the reversed tail,
 // Section IV-A): level-major, positions in increasing order inside a level; X last.
@@ -251,17 +246,15 @@ int pick_window_depth(bool fp64, int nmax, int nrhs, const bmpc_options* o) {
   return Tw;
 }
 
-// Levels of the passes after the first.  Automatic: the first pass's depth, except
-// where the chain left after the first pass would fill the final pass's one workgroup
-// per chain with a long serial walk; then a smaller depth gives the next pass more
-// workgroups per chain and leaves the final pass a short chain.
-int pick_later_depth(bool fp64, int nmax, int nrhs, int Tw, const bmpc_dims& d,
-                     const bmpc_options* o) {
+// Levels of the passes after the first: the option, else the first pass's depth.  A
+// smaller depth gives the later passes more workgroups per chain and the final pass a
+// shorter walk, but adds passes; on the c2 and c3 shapes the extra passes cost more
+// than the shorter walks save.
+int pick_later_depth(bool fp64, int nmax, int nrhs, int Tw, const bmpc_options* o) {
   if (nmax > 32) return 1;
   bmpc_options lo{};
   if (o) lo = *o;
-  int T2 = (o && o->later_depth > 0) ? o->later_depth : later_depth_default(fp64, Tw, d);
-  lo.window_depth = std::min(T2, kMaxWindowDepth);
+  lo.window_depth = std::min((o && o->later_depth > 0) ? o->later_depth : Tw, kMaxWindowDepth);
   return pick_window_depth(fp64, nmax, nrhs, &lo);
 }
 
@@ -502,7 +495,7 @@ bmpc_status init_plan(bmpc_plan p, const bmpc_dims* dims, bmpc_precision prec, v
   p->m = dims->N - 1;
   p->nmax = nmax_for(dims->n);
   p->Tw = pick_window_depth(p->fp64, p->nmax, dims->nrhs, opts);
-  p->Tw2 = pick_later_depth(p->fp64, p->nmax, dims->nrhs, p->Tw, *dims, opts);
+  p->Tw2 = pick_later_depth(p->fp64, p->nmax, dims->nrhs, p->Tw, opts);
   p->B = systems_of(opts);
   p->opt_flags = flags_of(opts);
   p->chunk = rhs_chunk(p->nmax);
@@ -626,7 +619,7 @@ bmpc_status bmpc_cost_model(const bmpc_dims* dims, bmpc_precision prec,
     return BMPC_ERR_INVALID;
   const bool fp64 = prec == BMPC_FP64;
   const int Tw = pick_window_depth(fp64, nmax_for(dims->n), dims->nrhs, opts);
-  const int Tw2 = pick_later_depth(fp64, nmax_for(dims->n), dims->nrhs, Tw, *dims, opts);
+  const int Tw2 = pick_later_depth(fp64, nmax_for(dims->n), dims->nrhs, Tw, opts);
   Costs c = make_costs(*dims, fp64, Tw, Tw2, systems_of(opts), no_top_merge_of(opts));
   std::memset(cost, 0, sizeof(*cost));
   cost->factor_flops = c.factor_flops;

@@ -104,8 +104,7 @@ struct bmpc_plan_s {
 namespace bmpc {
 
 size_t factor_pass_lds_bytes(bool fp64, int nmax, int Tw, int nrhs_fused);
-int pick_later_depth(bool fp64, int nmax, int nrhs, int Tw, const bmpc_dims& d,
-                     const bmpc_options* o);
+int pick_later_depth(bool fp64, int nmax, int nrhs, int Tw, const bmpc_options* o);
 int nmax_for(int n);
 Costs make_costs(const bmpc_dims& d, bool fp64, int Tw, int Tw2, int B, bool no_top_merge);
 std::vector<int> make_permpos(int N);
