@@ -180,7 +180,10 @@ def test_deterministic_bits():
     assert np.array_equal(c, d)
 
 
-@pytest.mark.parametrize("stage,shift", [(7, -60.0), (0, -60.0), (3, -3.0)])
+# stages 8 and 4 are odd chain positions (1 and 5), factored by the level-1 inverse
+# kernel before the first pass; 7 and 3 are even positions, 0 is x_1
+@pytest.mark.parametrize("stage,shift", [(7, -60.0), (0, -60.0), (3, -3.0), (8, -60.0),
+                                         (4, -3.0)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_info_names_first_failing_pivot_in_elimination_order(stage, shift, precision):
     """A non-SPD input: info is the natural row of the first non-positive pivot in the

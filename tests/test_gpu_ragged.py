@@ -166,11 +166,15 @@ def test_backward_error_stop():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_info_names_the_failing_system(precision):
+@pytest.mark.parametrize("which", ["x1", "odd"])
+def test_info_names_the_failing_system(precision, which):
     bm = _bm()
     systems = _systems(1, seed=900)[:6]
     bad = 3
-    systems[bad].D[1, 0] -= 80.0 * np.eye(systems[bad].n)  # stage 0 = x_1, eliminated last
+    # stage 0 = x_1, eliminated last; stage N-1 = chain position 1, a level-1 block
+    # factored by the level-1 inverse launch before the first pass
+    stage = 0 if which == "x1" else systems[bad].N - 1
+    systems[bad].D[1, stage] -= 80.0 * np.eye(systems[bad].n)
     rp = bm.RaggedPlan([(s.S, s.N, s.n, 1) for s in systems], precision)
     D, E, C, R, b = _pack(rp, systems)
     rp.factor(D, E, C, R)
