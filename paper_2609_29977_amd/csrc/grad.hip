@@ -80,9 +80,10 @@ __global__ void __launch_bounds__(GT) grad_blocks_kernel(GradArgs a, int spw, in
           const double* lq = ls + (q * V + w) * n;
           d0 += lq[r] * xq[c] + lq[c] * xq[r];
         }
-        const double v = -0.5 * d0;
-        double* o = a.dR + (size_t)sys * nn + rem;
-        if (a.dR) *o = q0 == 0 ? v : *o + v;
+        if (a.dR) {
+          double* o = a.dR + (size_t)sys * nn + rem;
+          *o = q0 == 0 ? -0.5 * d0 : *o - 0.5 * d0;
+        }
         continue;
       }
       for (int q = 0; q < nq; ++q) {
