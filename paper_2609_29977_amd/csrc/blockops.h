@@ -101,6 +101,46 @@ __device__ inline double wave_set_lane(double v, double x) {
   return __hiloint2double(hi, lo);
 }
 
+// v += yb[SRC of v's 16-lane row] * m: the row broadcast (DPP row_newbcast) is an
+// operand of the multiply-add, so a broadcast costs no instruction of its own.  WAIT
+// puts in front the two wait states that a DPP read needs after a vector write of its
+// source (the read is inside the asm, where the compiler cannot see it); the
+// statements are volatile so that they keep their order and the first one of a group
+// is the one that waits.
+template <int SRC, bool WAIT>
+__device__ __attribute__((always_inline)) inline void row_bcast_fma(float& v, float yb,
+                                                                    float m) {
+  if constexpr (WAIT)
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
+  else
+    asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
+}
+template <int SRC, bool WAIT>
+__device__ __attribute__((always_inline)) inline void row_bcast_fma(double& v, double yb,
+                                                                    double m) {
+  if constexpr (WAIT)
+    asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
+  else
+    asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
+}
+
+// Lanes 0-15 of y copied into lanes 16-31 (and 32-47 into 48-63): the odd 16-lane rows
+// of one copy swapped with the even rows of another (v_permlane16_swap).
+__device__ inline float rows_even_to_odd(float y) {
+  const unsigned u = __float_as_uint(y);
+  return __uint_as_float(__builtin_amdgcn_permlane16_swap(u, u, false, false)[0]);
+}
+__device__ inline double rows_even_to_odd(double y) {
+  const unsigned lo = __double2loint(y), hi = __double2hiint(y);
+  const unsigned l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false)[0];
+  const unsigned h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false)[0];
+  return __hiloint2double((int)h2, (int)l2);
+}
+
 // f(std::integral_constant<int, K>{}) for K = 0 .. N-1 in order (a loop whose index is
 // a constant expression in the body).
 template <typename F, int... Ks>
@@ -170,15 +210,15 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
 // applied to the identity with unscaled rows: row c of Z loses (L[c][k] / L[k][k])
 // times row k, and row k is divided by L[k][k] once step k has used it.  Both updates
 // of step k are "entry c -= L[c][k] * y" with y = entry k / L[k][k] on every lane
-// (L[i][k] on a row lane, Z[k][j] / L[k][k] on a column lane), so one readlane
-// broadcast of L[c][k] and one FMA per column c > k serve the factor and the inverse
-// together, and entry k keeps y (the finished entry of L^{-1} on a column lane).  No
+// (L[i][k] on a row lane, Z[k][j] / L[k][k] on a column lane), so one FMA per column
+// c > k, with L[c][k] broadcast inside it, serves the factor and the inverse together,
+// and entry k keeps y (the finished entry of L^{-1} on a column lane).  No
 // per-lane branches: row lanes also update entries above the diagonal, which are
 // never read.  Blocks smaller than NMAX must be padded with an identity block.
 // Returns (on every lane) the 0-based row of the first non-positive pivot, or -1.
 template <typename T, int NMAX, int LD = Lay<NMAX>::LD>
 __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
-  static_assert(2 * NMAX <= 64, "two lane groups per wave");
+  static_assert(NMAX == 8 || NMAX == 16, "row and column lanes in the first 32 lanes");
   const int lane = threadIdx.x & 63;
   const bool rowl = lane < NMAX;
   const int j = lane - NMAX;
@@ -203,18 +243,17 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
     const T inv = pivot_rsqrt(piv);
     const T y = v[k] * inv;  // L[i][k] on row lane i (>= k); Z[k][j] / L[k][k] on column lane j
     v[k] = y;
-    // broadcasts in groups of BG: the scalar reads of a group are issued together
-    // (hiding the read-after-write wait) with bounded temporaries
-    constexpr int BG = 8;
-#pragma unroll
-    for (int c0 = k + 1; c0 < NMAX; c0 += BG) {
-      T lc[BG];
-#pragma unroll
-      for (int u = 0; u < BG; ++u)
-        if (c0 + u < NMAX) lc[u] = wave_bcast(y, c0 + u);
-#pragma unroll
-      for (int u = 0; u < BG; ++u)
-        if (c0 + u < NMAX) v[c0 + u] -= lc[u] * y;
+    if constexpr (k + 1 < NMAX) {
+      // L[c][k] is y on row lane c.  The row lanes and the column lanes share one 16-lane
+      // row at NMAX = 8; at NMAX = 16 the column lanes are the next row, which gets a copy
+      // of the row lanes' y.  Then entry c of every lane is updated by one multiply-add
+      // whose first factor is lane c of its row.
+      const T yb = NMAX == 16 ? rows_even_to_odd(y) : y;
+      const T ny = -y;
+      static_for<NMAX - 1 - k>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        row_bcast_fma<k + 1 + u, u == 0>(v[k + 1 + u], yb, ny);
+      });
     }
   });
   // Column lane j's entries above the diagonal (i < j) are exact zeros: they start at
