@@ -919,17 +919,36 @@ __device__ __attribute__((always_inline)) inline void level1_inverse_body(
   const int j = 2 * (int)(bi - (unsigned)s * nodd) + 1;
   const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
   const int lane = threadIdx.x & 63;
-  // the symmetric block from D's lower triangle, identity padded
   double dv[NMAX * NMAX / 64];
+  if constexpr (FULL && NMAX * NMAX % 128 == 0) {
+    // D's lower triangle, two consecutive row entries per 16-byte load; pairs above the
+    // diagonal are not fetched (they read as zero) and a pair that starts on it brings
+    // one entry above it: the factorization reads only the lower triangle
+    const auto rd = block_rsrc(D, (unsigned)(NMAX * NMAX) * 8u);
 #pragma unroll
-  for (int u = 0; u < NMAX * NMAX / 64; ++u) {
-    const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
-    dv[u] = (r < n && c < n) ? D[r >= c ? r * n + c : c * n + r] : (r == c ? 1.0 : 0.0);
-  }
+    for (int h = 0; h < NMAX * NMAX / 128; ++h) {
+      const int e = 2 * (lane + 64 * h), r = e / NMAX, c = e % NMAX;
+      const auto w = __builtin_amdgcn_raw_buffer_load_b128(
+          rd, c <= r ? (unsigned)e * 8u : kOutOfRange, 0, 0);
+      __builtin_memcpy(&dv[2 * h], &w, 16);
+    }
 #pragma unroll
-  for (int u = 0; u < NMAX * NMAX / 64; ++u) {
-    const int e = lane + 64 * u;
-    slot[(e / NMAX) * LD + e % NMAX] = static_cast<T>(dv[u]);
+    for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+      const int e = 2 * (lane + 64 * (u >> 1)) + (u & 1);
+      slot[(e / NMAX) * LD + e % NMAX] = static_cast<T>(dv[u]);
+    }
+  } else {
+    // the symmetric block from D's lower triangle, identity padded
+#pragma unroll
+    for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+      const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
+      dv[u] = (r < n && c < n) ? D[r >= c ? r * n + c : c * n + r] : (r == c ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+      const int e = lane + 64 * u;
+      slot[(e / NMAX) * LD + e % NMAX] = static_cast<T>(dv[u]);
+    }
   }
   wave_lds_fence();
   const int fail = wave_potrf_inv<T, NMAX>(slot);

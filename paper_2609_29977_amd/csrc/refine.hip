@@ -51,10 +51,33 @@ struct StageFetch {
 
   // A block that does not exist (exists = false) is read as zero without a memory
   // access, so every fetch issues the same loads.
+  // Element of the block held in v[u]: with PAIRS, v[2h] and v[2h+1] are two
+  // consecutive elements of a row, read by one 16-byte load.
+  static constexpr bool PAIRS = FULL && NMAX * NMAX % (2 * RES_T) == 0;
+  __device__ static int elem(int u) {
+    if constexpr (PAIRS)
+      return 2 * ((int)threadIdx.x + (u >> 1) * RES_T) + (u & 1);
+    else
+      return (int)threadIdx.x + u * RES_T;
+  }
+
   template <bool LOWER>
   __device__ static void block(double (&v)[PER], const double* __restrict__ g, int n,
                                bool exists) {
-    if constexpr (FULL) {
+    if constexpr (PAIRS) {
+      // pairs past the diagonal of a lower triangle are not fetched; a pair that starts
+      // on the diagonal brings one entry above it, which is never read
+      const auto rs = block_rsrc(g, exists ? (unsigned)(NMAX * NMAX) * 8u : 0u);
+#pragma unroll
+      for (int h = 0; h < PER / 2; ++h) {
+        const int el = elem(2 * h);
+        const int r = el / NMAX, c = el % NMAX;
+        const bool ok = !LOWER || c <= r;
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? (unsigned)el * 8u
+                                                                    : kOutOfRange, 0, 0);
+        __builtin_memcpy(&v[2 * h], &w, 16);
+      }
+    } else if constexpr (FULL) {
       const auto rs = block_rsrc(g, exists ? (unsigned)(NMAX * NMAX) * 8u : 0u);
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
@@ -77,7 +100,7 @@ struct StageFetch {
     constexpr int LD = NMAX + 1;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int el = threadIdx.x + u * RES_T;
+      const int el = elem(u);
       if (el < NMAX * NMAX) dst[(el / NMAX) * LD + el % NMAX] = v[u];
     }
   }
