@@ -203,6 +203,23 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
   return fail;
 }
 
+// Where entry (r, c) of a block lives in LDS.  RowMajor: rows of LD entries (the padded
+// slots).  PackedLower: only the lower triangle of a 32 x 32 block, packed by rows
+// ((r, c), c <= r, at r (r + 1) / 2 + c); R0 selects the diagonal sub-block starting at
+// (R0, R0).  Entries above the diagonal do not exist there: reads of them are replaced by
+// zero and writes dropped.
+template <int LD>
+struct RowMajor {
+  static constexpr bool kLowerOnly = false;
+  __device__ static int at(int r, int c) { return r * LD + c; }
+};
+template <int R0>
+struct PackedLower {
+  static constexpr bool kLowerOnly = true;
+  __device__ static int at(int r, int c) { return (R0 + r) * (R0 + r + 1) / 2 + R0 + c; }
+};
+constexpr int kPacked32 = 32 * 33 / 2;  // entries of a packed 32 x 32 lower triangle
+
 // In place: A (symmetric NMAX x NMAX, lower triangle read) := L^{-1} with L L^T = A.
 // One wave, two lane groups.  Lane i < NMAX keeps row i of A and runs the
 // right-looking Cholesky sweep: step k forms column k of L (L[i][k] on lane i).
@@ -216,7 +233,7 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
 // per-lane branches: row lanes also update entries above the diagonal, which are
 // never read.  Blocks smaller than NMAX must be padded with an identity block.
 // Returns (on every lane) the 0-based row of the first non-positive pivot, or -1.
-template <typename T, int NMAX, int LD = Lay<NMAX>::LD>
+template <typename T, int NMAX, typename Ix = RowMajor<Lay<NMAX>::LD>>
 __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   static_assert(NMAX == 8 || NMAX == 16, "row and column lanes in the first 32 lanes");
   const int lane = threadIdx.x & 63;
@@ -224,12 +241,13 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   const int j = lane - NMAX;
   const int idx = rowl ? lane : (j < NMAX ? j : NMAX - 1);
   // Every lane reads a row (column lanes a row they then discard): loads under a lane
-  // condition become a branch per element, each waiting for its own read.
+  // condition become a branch per element, each waiting for its own read.  (In packed
+  // storage the places above the diagonal hold later rows' entries, in range.)
   T v[NMAX];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) v[c] = A[idx * LD + c];
+  for (int c = 0; c < NMAX; ++c) v[c] = A[Ix::at(idx, c)];
 #pragma unroll
-  for (int c = 0; c < NMAX; ++c) v[c] = rowl ? v[c] : T(0);
+  for (int c = 0; c < NMAX; ++c) v[c] = (rowl && (!Ix::kLowerOnly || c <= idx)) ? v[c] : T(0);
   int fail = -1;
   static_for<NMAX>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -261,7 +279,8 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   // itself zero.  So the whole column is stored without a mask.
   if (!rowl && j < NMAX) {
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i) A[i * LD + j] = v[i];
+    for (int i = 0; i < NMAX; ++i)
+      if (!Ix::kLowerOnly || i >= j) A[Ix::at(i, j)] = v[i];
   }
   return fail;
 }
@@ -422,13 +441,13 @@ template <typename T, int NMAX, int LD = Lay<NMAX>::LD>
 __device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
   static_assert(NMAX <= 32, "one wave per block up to 32 x 32");
   if constexpr (NMAX < 32) {
-    return wave_potrf_inv_leaf<T, NMAX, LD>(A);
+    return wave_potrf_inv_leaf<T, NMAX, RowMajor<LD>>(A);
   } else {
     typedef typename Mfma<T>::acc_t acc_t;
     const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
     T* A21 = A + 16 * LD;
     T* A22 = A + 16 * LD + 16;
-    int fail = wave_potrf_inv_leaf<T, 16, LD>(A);  // A11 := L11^{-1}
+    int fail = wave_potrf_inv_leaf<T, 16, RowMajor<LD>>(A);  // A11 := L11^{-1}
     wave_lds_fence();
     // L21 = A21 L11^{-T}: out[r][c] = sum_k A21[r][k] Linv11[c][k]
     acc_t t = {0, 0, 0, 0};
@@ -454,7 +473,7 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) A22[Mfma<T>::row(l, v) * LD + i] = sacc[v];
     wave_lds_fence();
-    const int fail2 = wave_potrf_inv_leaf<T, 16, LD>(A22);  // A22 := L22^{-1}
+    const int fail2 = wave_potrf_inv_leaf<T, 16, RowMajor<LD>>(A22);  // A22 := L22^{-1}
     wave_lds_fence();
     // W = L21 L11^{-1}: out[r][c] = sum_k L21[r][k] Linv11[k][c]
     acc_t w = {0, 0, 0, 0};
@@ -484,6 +503,80 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv(T* A) {
     if (fail >= 0) return fail;
     return fail2 >= 0 ? 16 + fail2 : -1;
   }
+}
+
+// wave_potrf_inv for a 32 x 32 block held as its packed lower triangle (kPacked32
+// entries): the same 2 x 2 blocked steps, reading only entries on or below the diagonal
+// (the operands' upper entries are zeros of the triangular factors) and leaving L^{-1}'s
+// lower triangle in place.  Half the LDS of a padded slot.  One wave.
+template <typename T>
+__device__ __attribute__((always_inline)) inline int wave_potrf_inv_packed(T* A) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  typedef PackedLower<0> P;
+  const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+  int fail = wave_potrf_inv_leaf<T, 16, PackedLower<0>>(A);  // A11 := L11^{-1}
+  wave_lds_fence();
+  // L21 = A21 L11^{-T}: out[r][c] = sum_k A21[r][k] Linv11[c][k]
+  acc_t t = {0, 0, 0, 0};
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 4 * g + st;
+    const T li = A[P::at(i, k)];  // in range for k > i too; replaced by zero there
+    t = Mfma<T>::mma(A[P::at(16 + i, k)], k <= i ? li : T(0), t);
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) A[P::at(16 + Mfma<T>::row(l, v), i)] = t[v];
+  wave_lds_fence();
+  // S = A22 - L21 L21^T, lower triangle
+  acc_t sacc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = Mfma<T>::row(l, v);
+    const T a22 = A[P::at(16 + r, 16 + i)];
+    sacc[v] = i <= r ? a22 : T(0);
+  }
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 4 * g + st;
+    const T l21 = A[P::at(16 + i, k)];
+    sacc = Mfma<T>::mma(-l21, l21, sacc);
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = Mfma<T>::row(l, v);
+    if (i <= r) A[P::at(16 + r, 16 + i)] = sacc[v];
+  }
+  wave_lds_fence();
+  const int fail2 = wave_potrf_inv_leaf<T, 16, PackedLower<16>>(A);  // A22 := L22^{-1}
+  wave_lds_fence();
+  // W = L21 L11^{-1}: out[r][c] = sum_k L21[r][k] Linv11[k][c]
+  acc_t w = {0, 0, 0, 0};
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 4 * g + st;
+    const T li = A[P::at(k, i)];  // in range for i > k too; replaced by zero there
+    w = Mfma<T>::mma(A[P::at(16 + i, k)], i <= k ? li : T(0), w);
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) A[P::at(16 + Mfma<T>::row(l, v), i)] = w[v];
+  wave_lds_fence();
+  // (L^{-1})21 = -L22^{-1} W: out[r][c] = sum_k Linv22[r][k] W[k][c]
+  acc_t x = {0, 0, 0, 0};
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 4 * g + st;
+    const T l22 = A[P::at(16 + i, 16 + k)];
+    x = Mfma<T>::mma(k <= i ? -l22 : T(0), A[P::at(16 + k, i)], x);
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) A[P::at(16 + Mfma<T>::row(l, v), i)] = x[v];
+  wave_lds_fence();
+  if (fail >= 0) return fail;
+  return fail2 >= 0 ? 16 + fail2 : -1;
 }
 
 }  // namespace bmpc

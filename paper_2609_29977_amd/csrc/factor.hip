@@ -896,6 +896,12 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT,
   factor_pass_body<T, NMAX, FIRST, FINAL, FWD, FULL>(a, blockIdx.x);
 }
 
+// LDS entries per wave of the level-1 inverse kernels.
+template <int NMAX>
+constexpr int level1_slot_entries() {
+  return NMAX == 32 ? kPacked32 : Lay<NMAX>::SZ;
+}
+
 // Level-1 inverses of the first pass.  The odd chain positions (level 1 of Gamma's
 // order) take no Schur update from the rest of the chain, so L_jj^{-1} of their
 // diagonal blocks depends on D alone (Algorithm 1's diagonal factorizations at the
@@ -909,10 +915,13 @@ __device__ __attribute__((always_inline)) inline void level1_inverse_body(
   FactorPassArgs a = a_in;
   if constexpr (FULL) a.n = NMAX;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // 32 x 32 blocks are held as their packed lower triangles (half the LDS of a padded
+  // slot, so that more waves fit on a CU); smaller ones in padded slots
+  constexpr bool PK = NMAX == 32;
   constexpr int LD = Lay<NMAX>::LD;
-  constexpr int SZ = Lay<NMAX>::SZ;
+  typedef typename std::conditional<PK, PackedLower<0>, RowMajor<LD>>::type Ix;
   if (bi >= total) return;  // the whole wave leaves; no workgroup barrier follows
-  T* slot = reinterpret_cast<T*>(smem_raw) + wave_id() * SZ;
+  T* slot = reinterpret_cast<T*>(smem_raw) + wave_id() * level1_slot_entries<NMAX>();
   const int n = a.n, N = a.N;
   const size_t nn = (size_t)n * n;
   const int s = (int)(bi / (unsigned)nodd);
@@ -934,8 +943,8 @@ __device__ __attribute__((always_inline)) inline void level1_inverse_body(
     }
 #pragma unroll
     for (int u = 0; u < NMAX * NMAX / 64; ++u) {
-      const int e = 2 * (lane + 64 * (u >> 1)) + (u & 1);
-      slot[(e / NMAX) * LD + e % NMAX] = static_cast<T>(dv[u]);
+      const int e = 2 * (lane + 64 * (u >> 1)) + (u & 1), r = e / NMAX, c = e % NMAX;
+      if (!Ix::kLowerOnly || c <= r) slot[Ix::at(r, c)] = static_cast<T>(dv[u]);
     }
   } else {
     // the symmetric block from D's lower triangle, identity padded
@@ -946,12 +955,16 @@ __device__ __attribute__((always_inline)) inline void level1_inverse_body(
     }
 #pragma unroll
     for (int u = 0; u < NMAX * NMAX / 64; ++u) {
-      const int e = lane + 64 * u;
-      slot[(e / NMAX) * LD + e % NMAX] = static_cast<T>(dv[u]);
+      const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
+      if (!Ix::kLowerOnly || c <= r) slot[Ix::at(r, c)] = static_cast<T>(dv[u]);
     }
   }
   wave_lds_fence();
-  const int fail = wave_potrf_inv<T, NMAX>(slot);
+  int fail;
+  if constexpr (PK)
+    fail = wave_potrf_inv_packed<T>(slot);
+  else
+    fail = wave_potrf_inv<T, NMAX>(slot);
   if (fail >= 0 && fail < n && lane == 0) {
     const int sys = s / a.Ssys;
     const unsigned long long row0 =
@@ -960,16 +973,21 @@ __device__ __attribute__((always_inline)) inline void level1_inverse_body(
     atomicMin(a.info, row0 + (unsigned long long)a.permpos[j - 1] * n + fail + 1);
   }
   wave_lds_fence();
-  // packed lower triangle, as slot_store_packed but by one wave
+  // packed lower triangle (rows of length r + 1 whatever n is, so the n x n block's
+  // packing is a prefix of the 32 x 32 one)
   T* Li = reinterpret_cast<T*>(a.Linv) + ((size_t)s * N + (j - 1)) * nn;
   const int np = n * (n + 1) / 2;
 #pragma unroll
   for (int p0 = 0; p0 < NMAX * (NMAX + 1) / 2; p0 += 64) {
     const int p = p0 + lane;
-    int r = (int)((__fsqrt_rn(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
-    r = (r * (r + 1) / 2 > p) ? r - 1 : r;
-    r = ((r + 1) * (r + 2) / 2 <= p) ? r + 1 : r;
-    if (p < np) Li[p] = slot[r * LD + (p - r * (r + 1) / 2)];
+    if constexpr (PK) {
+      if (p < np) Li[p] = slot[p];
+    } else {
+      int r = (int)((__fsqrt_rn(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+      r = (r * (r + 1) / 2 > p) ? r - 1 : r;
+      r = ((r + 1) * (r + 2) / 2 <= p) ? r + 1 : r;
+      if (p < np) Li[p] = slot[r * LD + (p - r * (r + 1) / 2)];
+    }
   }
 }
 
@@ -1243,7 +1261,7 @@ void launch_l1inv_t(const FactorPassArgs& a, hipStream_t st) {
   const int nodd = (a.m + 1) / 2;
   const unsigned total = (unsigned)a.S * (unsigned)nodd;
   if (total == 0) return;
-  const size_t lds = 4 * (size_t)Lay<NMAX>::SZ * sizeof(T);
+  const size_t lds = 4 * (size_t)level1_slot_entries<NMAX>() * sizeof(T);
   const dim3 grid((total + 3) / 4);
   if (a.n == NMAX)
     hipLaunchKernelGGL((level1_inverse_kernel<T, NMAX, true>), grid, dim3(256), lds, st, a, nodd,
@@ -1255,7 +1273,7 @@ void launch_l1inv_t(const FactorPassArgs& a, hipStream_t st) {
 template <typename T, int NMAX>
 void launch_l1inv_multi_t(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
                           bool full, const Reloc& r, hipStream_t st) {
-  const size_t lds = 4 * (size_t)Lay<NMAX>::SZ * sizeof(T);
+  const size_t lds = 4 * (size_t)level1_slot_entries<NMAX>() * sizeof(T);
   if (full)
     hipLaunchKernelGGL((level1_inverse_multi<T, NMAX, true>), dim3(blocks), dim3(256), lds, st,
                        items, nitems, r);
