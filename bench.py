@@ -63,13 +63,16 @@ FACTOR_SOURCES = ("factor.hip", "bmpc_internal.h", "blockops.h", "multi.h", "reg
 
 
 def source_digest(names=None):
-    """Digest of the named files under csrc/ (all of them by default)."""
+    """Digest of the code of the named files under csrc/ (all of them by default):
+    line comments, trailing blanks and empty lines do not count, so that a comment edit
+    does not retire counters taken on the same code."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2609_29977_amd", "csrc")
     for name in sorted(names if names is not None else os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            code = [ln.split("//", 1)[0].rstrip() for ln in f]
+        h.update(name.encode())
+        h.update("\n".join(ln for ln in code if ln).encode())
     return h.hexdigest()[:16]
 
 

@@ -276,7 +276,8 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   });
   // Column lane j's entries above the diagonal (i < j) are exact zeros: they start at
   // zero, and each update subtracts a multiple of y = Z[k][j] / L[k][k] with k < i < j,
-  // itself zero.  So the whole column is stored without a mask.
+  // itself zero.  So in row-major storage the whole column is stored without a mask
+  // (packed storage has no places above the diagonal).
   if (!rowl && j < NMAX) {
 #pragma unroll
     for (int i = 0; i < NMAX; ++i)

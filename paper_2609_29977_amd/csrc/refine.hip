@@ -49,8 +49,6 @@ struct StageFetch {
   static constexpr int VPER = (rhs_chunk(NMAX) * NMAX + RES_T - 1) / RES_T;
   double d[PER], e[PER], xv[VPER], bv[VPER];
 
-  // A block that does not exist (exists = false) is read as zero without a memory
-  // access, so every fetch issues the same loads.
   // Element of the block held in v[u]: with PAIRS, v[2h] and v[2h+1] are two
   // consecutive elements of a row, read by one 16-byte load.
   static constexpr bool PAIRS = FULL && NMAX * NMAX % (2 * RES_T) == 0;
@@ -61,6 +59,8 @@ struct StageFetch {
       return (int)threadIdx.x + u * RES_T;
   }
 
+  // A block that does not exist (exists = false) is read as zero without a memory
+  // access, so every fetch issues the same loads.
   template <bool LOWER>
   __device__ static void block(double (&v)[PER], const double* __restrict__ g, int n,
                                bool exists) {
