@@ -431,6 +431,23 @@ struct BoundaryFetch {
 template <typename T, int NMAX>
 __device__ inline void slot_store(T* __restrict__ dst, const T* src, int n) {
   constexpr int LD = Lay<NMAX>::LD;
+  constexpr int NT = TileCfg<NMAX>::NT;
+  constexpr int V = 16 / (int)sizeof(T);  // entries per 16-byte store
+  if constexpr (NMAX * NMAX % (V * NT) == 0 && NMAX % V == 0) {
+    if (n == NMAX) {  // full block: V consecutive row entries per store
+      typedef T vt __attribute__((ext_vector_type(V)));
+#pragma unroll
+      for (int k = 0; k < NMAX * NMAX / (V * NT); ++k) {
+        const int e = V * ((int)(threadIdx.x & (NT - 1)) + k * NT);
+        const int r = e / NMAX, c = e % NMAX;
+        vt w;
+#pragma unroll
+        for (int u = 0; u < V; ++u) w[u] = src[r * LD + c + u];
+        *reinterpret_cast<vt*>(dst + e) = w;
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
     const int e = Share<NMAX>::elem(j);
