@@ -75,6 +75,17 @@ __device__ inline void slot_zero(T* dst) {
   }
 }
 
+// Zero the entries of an NMAX x NMAX slot above its diagonal.
+template <typename T, int NMAX>
+__device__ inline void slot_zero_upper(T* dst) {
+  constexpr int LD = Lay<NMAX>::LD;
+#pragma unroll
+  for (int j = 0; j < Share<NMAX>::ELEMS; ++j) {
+    const int e = Share<NMAX>::elem(j);
+    if (e < NMAX * NMAX && e % NMAX > e / NMAX) dst[(e / NMAX) * LD + e % NMAX] = T(0);
+  }
+}
+
 // dst = src (n x n global, type S, optionally added to dst), zero padding.
 template <typename T, int NMAX, typename S>
 __device__ inline void slot_load(T* dst, const S* __restrict__ src, int n, bool add) {
@@ -260,10 +271,20 @@ __device__ inline void push_apply(T* Vr, T* Vl, const T* Pr, const T* Pl, int nr
 // factored by the window prologue: their fetch reloads L^{-1} and the coupling to the
 // successor.  Even positions fetch D plus the updates carried from earlier passes and
 // the coupling.
-template <typename T, int NMAX, bool FIRST, bool FWD>
+template <typename T, int NMAX, bool FIRST, bool FWD, bool FULL>
 struct FetchOdd {
   static constexpr int EL = Share<NMAX>::ELEMS;
+  static constexpr int NT = Share<NMAX>::NT;
   typedef typename std::conditional<FIRST, double, T>::type CT;
+  // Full 32 x 32 FP64 blocks: L^{-1} read as V consecutive packed entries per 16-byte
+  // load, in R rounds of the workgroup, and placed on and below the diagonal only (the
+  // level-0 slot's upper triangle is zeroed once per window and nothing else writes
+  // there).  (In FP32 the commit's registers make the first pass spill.)
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int NP = NMAX * (NMAX + 1) / 2;
+  static constexpr bool PACKED = FULL && NMAX == 32 && sizeof(T) == 8;
+  static constexpr int R = (NP / V + NT - 1) / NT;
+  static_assert(!PACKED || (NP % V == 0 && R * V <= EL), "chunks fit the registers");
   T li[EL];
   CT cp[EL];
   VecFetch<T, NMAX, FIRST, FWD> vf;
@@ -279,6 +300,24 @@ struct FetchOdd {
       cpl = a.E + ((size_t)s * (N - 1) + (N - 1 - q)) * nn;  // K[q+1,q] = E[s][N-1-q]^T
     else
       cpl = reinterpret_cast<const T*>(a.fill_in) + ((size_t)s * a.stride + q) * nn;
+    if constexpr (PACKED) {
+      typedef T vt __attribute__((ext_vector_type(V)));
+#pragma unroll
+      for (int h = 0; h < R; ++h) {
+        const int k = (int)(threadIdx.x & (NT - 1)) + h * NT;
+        if (k < NP / V) {
+          const vt w = *reinterpret_cast<const vt*>(Li + V * k);
+#pragma unroll
+          for (int u = 0; u < V; ++u) li[h * V + u] = w[u];
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < EL; ++jj) {
+        const int e = Share<NMAX>::elem(jj);
+        cp[jj] = cpl[e];
+      }
+      return;
+    }
 #pragma unroll
     for (int jj = 0; jj < EL; ++jj) {
       const int e = Share<NMAX>::elem(jj);
@@ -293,6 +332,38 @@ struct FetchOdd {
 
   __device__ void commit(T* A, T* C, int n) const {
     constexpr int LD = Lay<NMAX>::LD;
+    if constexpr (PACKED) {
+#pragma unroll
+      for (int h = 0; h < R; ++h) {
+        const int k = (int)(threadIdx.x & (NT - 1)) + h * NT;
+        if (k < NP / V) {
+          // row of packed entry p: the r with r (r + 1) / 2 <= p < (r + 1) (r + 2) / 2
+          const int p = V * k;
+          int r = (int)((__fsqrt_rn(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+          r = (r * (r + 1) / 2 > p) ? r - 1 : r;
+          r = ((r + 1) * (r + 2) / 2 <= p) ? r + 1 : r;
+          int c = p - r * (r + 1) / 2;
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            A[r * LD + c] = li[h * V + u];
+            const bool wrap = c == r;  // the next packed entry starts row r + 1
+            r = wrap ? r + 1 : r;
+            c = wrap ? 0 : c + 1;
+          }
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < EL; ++jj) {
+        const int e = Share<NMAX>::elem(jj);
+        const int r = e / NMAX, c = e % NMAX;
+        const T cv = static_cast<T>(cp[jj]);
+        if constexpr (FIRST)
+          C[c * LD + r] = cv;
+        else
+          C[r * LD + c] = cv;
+      }
+      return;
+    }
 #pragma unroll
     for (int jj = 0; jj < EL; ++jj) {
       const int e = Share<NMAX>::elem(jj);
@@ -720,7 +791,7 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(
     }
     __threadfence_block();
   }
-  FetchOdd<T, NMAX, FIRST, FWD> fo;
+  FetchOdd<T, NMAX, FIRST, FWD, FULL> fo;
   if (lo + 1 <= hi) fo.issue(a, vc, s, lo + 1);
   if constexpr (!kEarlyEvenFetch)
     if (lo + 2 <= hi) fe.issue(a, vc, s, lo + 2);
@@ -729,6 +800,7 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(
   // boundary in earlier passes; they travel with it in its left accumulator.
   if (has_left) bf.commit(sl.AL(), sl.CL());
   slot_zero<T, NMAX>(sl.AR());
+  if constexpr (decltype(fo)::PACKED) slot_zero_upper<T, NMAX>(sl.A(0));
   bvf.commit(a, sl.VL(), sl.VR());
   __syncthreads();
 
