@@ -141,6 +141,22 @@ __device__ inline double rows_even_to_odd(double y) {
   return __hiloint2double((int)h2, (int)l2);
 }
 
+// The first two 16-lane rows of y each copied into both rows: lo = rows (0, 0, 2, 2),
+// hi = rows (1, 1, 3, 3) of y (both outputs of one v_permlane16_swap per 32 bits).
+__device__ inline void rows_both(float y, float& lo, float& hi) {
+  const unsigned u = __float_as_uint(y);
+  const auto pr = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  lo = __uint_as_float(pr[0]);
+  hi = __uint_as_float(pr[1]);
+}
+__device__ inline void rows_both(double y, double& lo, double& hi) {
+  const unsigned l = __double2loint(y), h = __double2hiint(y);
+  const auto pl = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+  const auto ph = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+  lo = __hiloint2double((int)ph[0], (int)pl[0]);
+  hi = __hiloint2double((int)ph[1], (int)pl[1]);
+}
+
 // f(std::integral_constant<int, K>{}) for K = 0 .. N-1 in order (a loop whose index is
 // a constant expression in the body).
 template <typename F, int... Ks>
@@ -173,8 +189,10 @@ __device__ inline double pivot_rsqrt(double x) {
 
 // In place: A (symmetric NMAX x NMAX, lower triangle read; pad smaller blocks with an
 // identity block) := L with L L^T = A, zeros above the diagonal.  One wave, lane i
-// keeps row i; column k of L is broadcast with readlane.  Returns (on every lane)
-// the 0-based row of the first non-positive pivot, or -1.
+// keeps row i; column k of L is broadcast to the other rows: up to 32 rows as a DPP
+// row-broadcast operand of each multiply-add (as in the inverse leaves), 64 rows with
+// readlane.  Returns (on every lane) the 0-based row of the first non-positive pivot,
+// or -1.
 template <typename T, int NMAX>
 __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
   constexpr int LD = Lay<NMAX>::LD;
@@ -184,6 +202,37 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
 #pragma unroll
   for (int c = 0; c < NMAX; ++c) a[c] = A[row * LD + c];
   int fail = -1;
+  if constexpr (NMAX <= 32) {
+    static_for<NMAX>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const T piv = wave_bcast(a[k], k);
+      if (fail < 0 && !(piv > T(0))) fail = k;
+      const T inv = pivot_rsqrt(piv);
+      const T lik = (lane == k) ? piv * inv : a[k] * inv;
+      a[k] = lik;
+      if constexpr (k + 1 < NMAX) {
+        // L[c][k] is lik on lane c.  With 32 rows both 16-lane rows get a copy of rows
+        // 0-15 (lo) and of rows 16-31 (hi); entry c of every lane then takes one
+        // multiply-add whose first factor is lane c % 16 of the copy holding row c.
+        T lo = lik, hi = lik;
+        if constexpr (NMAX == 32) rows_both(lik, lo, hi);
+        const T nl = -lik;
+        static_for<NMAX - 1 - k>([&](auto uc) {
+          constexpr int u = decltype(uc)::value, c = k + 1 + u;
+          // the first use of each copy waits for its write
+          if constexpr (c < 16)
+            row_bcast_fma<c, u == 0>(a[c], lo, nl);
+          else
+            row_bcast_fma<c - 16, u == 0 || c == 16>(a[c], hi, nl);
+        });
+      }
+    });
+    if (lane < NMAX) {
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) A[lane * LD + c] = (c <= lane) ? a[c] : T(0);
+    }
+    return fail;
+  }
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
     const T piv = wave_bcast(a[k], k);
