@@ -205,6 +205,33 @@ def test_info_names_first_failing_pivot_in_elimination_order(stage, shift, preci
     plan.close()
 
 
+@pytest.mark.parametrize("S,N,n,k", [(2, 9, 3, 1), (3, 5, 16, 11), (2, 5, 32, 20),
+                                     (2, 4, 32, 0)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_info_names_failing_root_pivot(S, N, n, k, precision):
+    """A root block that loses definiteness after the tails' Schur updates: the tails
+    factor (their leading minors of Pi K Pi^T are positive definite, checked by a dense
+    Cholesky), and info is the natural row of the root's first non-positive pivot, the
+    first leading minor of Pi K Pi^T past the tails that is not positive definite
+    (brute-force eigenvalues).  The root Cholesky is FP64 in both precisions."""
+    bm = _bmpc()
+    s = make_system(S, N, n, 1, 1e-1, 40 + n)
+    s.R[k, k] -= 1e3 * (1.0 + abs(s.R[k, k]))
+    K = dense.assemble_K(s.D, s.E, s.C, s.R)
+    p = dense.perm_index(S, N, n, "d")
+    Kp = K[np.ix_(p, p)]
+    m = S * N * n
+    np.linalg.cholesky(Kp[:m, :m])  # the tails are positive definite
+    first = next(i for i in range(m + 1, m + n + 1) if np.linalg.eigvalsh(Kp[:i, :i])[0] <= 0)
+    natural = int(p[first - 1]) + 1
+    assert natural == m + k + 1  # the root is ordered last, its rows in order
+    D, E, C, R, b = dev(s)
+    plan = bm.Plan(S, N, n, 1, precision)
+    plan.factor(D, E, C, R)
+    assert plan.info() == natural
+    plan.close()
+
+
 def test_state_and_argument_errors():
     bm = _bmpc()
     s = make_system(2, 4, 3, 1, 1.0, 15)
