@@ -406,16 +406,22 @@ struct FetchEven {
       accL = reinterpret_cast<const T*>(a.accL_in) + o;
       cpl = reinterpret_cast<const T*>(a.fill_in) + o;
     }
-    // Every element reads its lower-triangle counterpart (D's upper triangle is not
-    // read), so the loads carry no lane mask; the upper half of the slot is never used
-    // before the block is factored.
+    // The upper half of the slot is never used before the block is factored, so it is
+    // not read from the blocks: in the first pass the entries above D's diagonal are
+    // buffer loads out of range (zero, no memory access); the carried updates of later
+    // passes read each element's lower-triangle counterpart.  No lane mask either way.
 #pragma unroll
     for (int jj = 0; jj < EL; ++jj) {
       const int e = Share<NMAX>::elem(jj);
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
       const int lo = (r >= c ? r * n + c : c * n + r);
-      d[jj] = in ? D[lo] : 0.0;
+      if constexpr (FIRST) {
+        const auto rd = block_rsrc(D, (unsigned)nn * 8u);
+        d[jj] = buf_load_f64(rd, in && c <= r ? (unsigned)(r * n + c) * 8u : kOutOfRange);
+      } else {
+        d[jj] = in ? D[lo] : 0.0;
+      }
       if constexpr (!FIRST) {
         ar[jj] = in ? accR[lo] : T(0);
         al[jj] = in ? accL[lo] : T(0);
