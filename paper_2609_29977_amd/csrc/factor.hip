@@ -407,24 +407,27 @@ struct FetchEven {
       cpl = reinterpret_cast<const T*>(a.fill_in) + o;
     }
     // The upper half of the slot is never used before the block is factored, so it is
-    // not read from the blocks: in the first pass the entries above D's diagonal are
-    // buffer loads out of range (zero, no memory access); the carried updates of later
-    // passes read each element's lower-triangle counterpart.  No lane mask either way.
+    // not read from the blocks: the entries above the diagonal of D and of the carried
+    // updates are buffer loads out of range (zero, no memory access).  No lane mask.
 #pragma unroll
     for (int jj = 0; jj < EL; ++jj) {
       const int e = Share<NMAX>::elem(jj);
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
-      const int lo = (r >= c ? r * n + c : c * n + r);
-      if constexpr (FIRST) {
-        const auto rd = block_rsrc(D, (unsigned)nn * 8u);
-        d[jj] = buf_load_f64(rd, in && c <= r ? (unsigned)(r * n + c) * 8u : kOutOfRange);
-      } else {
-        d[jj] = in ? D[lo] : 0.0;
-      }
+      const bool low = in && c <= r;
+      const auto rd = block_rsrc(D, (unsigned)nn * 8u);
+      d[jj] = buf_load_f64(rd, low ? (unsigned)(r * n + c) * 8u : kOutOfRange);
       if constexpr (!FIRST) {
-        ar[jj] = in ? accR[lo] : T(0);
-        al[jj] = in ? accL[lo] : T(0);
+        const auto rr = block_rsrc(accR, (unsigned)nn * (unsigned)sizeof(T));
+        const auto rl = block_rsrc(accL, (unsigned)nn * (unsigned)sizeof(T));
+        const unsigned o = low ? (unsigned)(r * n + c) * (unsigned)sizeof(T) : kOutOfRange;
+        if constexpr (sizeof(T) == 8) {
+          ar[jj] = buf_load_f64(rr, o);
+          al[jj] = buf_load_f64(rl, o);
+        } else {
+          ar[jj] = buf_load_f32(rr, o);
+          al[jj] = buf_load_f32(rl, o);
+        }
       }
       cp[jj] = in ? cpl[r * n + c] : CT(0);
     }
