@@ -736,8 +736,8 @@ __device__ __attribute__((always_inline)) inline void factor_pass_body(
       for (int jj = 0; jj < EL; ++jj) {
         const int e = Share<NMAX>::elem(jj);
         const int r = e / NMAX, c = e % NMAX;
-        const bool in = e < NMAX * NMAX && r < n && c < n;
-        off[jj] = in ? (unsigned)(c <= r ? r * n + c : c * n + r) : kOutOfRange / 8;
+        const bool in = e < NMAX * NMAX && r < n && c <= r;  // lower triangle only
+        off[jj] = in ? (unsigned)(r * n + c) : kOutOfRange / 8;
       }
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
@@ -1045,11 +1045,11 @@ __device__ __attribute__((always_inline)) inline void level1_inverse_body(
       if (!Ix::kLowerOnly || c <= r) slot[Ix::at(r, c)] = static_cast<T>(dv[u]);
     }
   } else {
-    // the symmetric block from D's lower triangle, identity padded
+    // D's lower triangle, identity padded (zeros above the diagonal)
 #pragma unroll
     for (int u = 0; u < NMAX * NMAX / 64; ++u) {
       const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
-      dv[u] = (r < n && c < n) ? D[r >= c ? r * n + c : c * n + r] : (r == c ? 1.0 : 0.0);
+      dv[u] = (r < n && c <= r) ? D[r * n + c] : (r == c ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int u = 0; u < NMAX * NMAX / 64; ++u) {
