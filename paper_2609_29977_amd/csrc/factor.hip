@@ -323,9 +323,15 @@ struct FetchOdd {
       const int e = Share<NMAX>::elem(jj);
       const int r = e / NMAX, c = e % NMAX;
       const bool in = e < NMAX * NMAX && r < n && c < n;
-      // the upper triangle reads the row's diagonal entry (in range) and drops it
-      const T lv = in ? Li[r * (r + 1) / 2 + (c <= r ? c : r)] : T(0);
-      li[jj] = c <= r ? lv : T(0);
+      // the places above the diagonal are buffer loads out of range (zero, no memory
+      // access)
+      const auto rl = block_rsrc(Li, (unsigned)(n * (n + 1) / 2) * (unsigned)sizeof(T));
+      const unsigned o =
+          in && c <= r ? (unsigned)(r * (r + 1) / 2 + c) * (unsigned)sizeof(T) : kOutOfRange;
+      if constexpr (sizeof(T) == 8)
+        li[jj] = buf_load_f64(rl, o);
+      else
+        li[jj] = buf_load_f32(rl, o);
       cp[jj] = in ? cpl[r * n + c] : CT(0);
     }
   }
