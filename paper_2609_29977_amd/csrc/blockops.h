@@ -173,16 +173,17 @@ __device__ __attribute__((always_inline)) inline void static_for(F&& f) {
 // the last place, which is the rounding level of the FP32 factor anyway (and the
 // refinement around the FP32 path removes it); a Newton step would only lengthen the
 // dependency chain of every column of a factorization.  FP64: the hardware estimate
-// refined by two Newton steps y <- y (3 - x y^2) / 2 (the estimate's error squares
-// each step).
+// (relative error below 2^-24 on gfx950) refined by one Halley step: with
+// e = 1 - x y^2, the series 1/sqrt(1 - e) = 1 + e/2 + 3e^2/8 + O(e^3) gives
+// y <- y + y e (1/2 + 3e/8), whose error is cubic in the estimate's (below 2^-70).
+// Four dependent operations, where two Newton steps (quadratic each) take six.
 __device__ inline float pivot_rsqrt(float x) {
   return __builtin_amdgcn_rsqf(x);
 }
 __device__ inline double pivot_rsqrt(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-(x * y), y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
 
 // ---- Cholesky of one block (one wave, lane = row) ------------------------------
