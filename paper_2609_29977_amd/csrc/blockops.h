@@ -101,30 +101,31 @@ __device__ inline double wave_set_lane(double v, double x) {
   return __hiloint2double(hi, lo);
 }
 
-// v += yb[SRC of v's 16-lane row] * m: the row broadcast (DPP row_newbcast) is an
-// operand of the multiply-add, so a broadcast costs no instruction of its own.  WAIT
+// v -= yb[SRC of v's 16-lane row] * m: the row broadcast (DPP row_newbcast) is an
+// operand of the multiply-add, and so is the negation (a source modifier), so neither
+// costs an instruction of its own.  WAIT
 // puts in front the two wait states that a DPP read needs after a vector write of its
 // source (the read is inside the asm, where the compiler cannot see it); the
 // statements are volatile so that they keep their order and the first one of a group
 // is the one that waits.
 template <int SRC, bool WAIT>
-__device__ __attribute__((always_inline)) inline void row_bcast_fma(float& v, float yb,
+__device__ __attribute__((always_inline)) inline void row_bcast_fms(float& v, float yb,
                                                                     float m) {
   if constexpr (WAIT)
-    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
                  : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
   else
-    asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+    asm volatile("v_fmac_f32_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
                  : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
 }
 template <int SRC, bool WAIT>
-__device__ __attribute__((always_inline)) inline void row_bcast_fma(double& v, double yb,
+__device__ __attribute__((always_inline)) inline void row_bcast_fms(double& v, double yb,
                                                                     double m) {
   if constexpr (WAIT)
-    asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+    asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
                  : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
   else
-    asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+    asm volatile("v_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
                  : "+v"(v) : "v"(yb), "v"(m), "n"(SRC));
 }
 
@@ -217,14 +218,13 @@ __device__ __attribute__((always_inline)) inline int wave_potrf(T* A) {
         // multiply-add whose first factor is lane c % 16 of the copy holding row c.
         T lo = lik, hi = lik;
         if constexpr (NMAX == 32) rows_both(lik, lo, hi);
-        const T nl = -lik;
         static_for<NMAX - 1 - k>([&](auto uc) {
           constexpr int u = decltype(uc)::value, c = k + 1 + u;
           // the first use of each copy waits for its write
           if constexpr (c < 16)
-            row_bcast_fma<c, u == 0>(a[c], lo, nl);
+            row_bcast_fms<c, u == 0>(a[c], lo, lik);
           else
-            row_bcast_fma<c - 16, u == 0 || c == 16>(a[c], hi, nl);
+            row_bcast_fms<c - 16, u == 0 || c == 16>(a[c], hi, lik);
         });
       }
     });
@@ -317,10 +317,9 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
       // of the row lanes' y.  Then entry c of every lane is updated by one multiply-add
       // whose first factor is lane c of its row.
       const T yb = NMAX == 16 ? rows_even_to_odd(y) : y;
-      const T ny = -y;
       static_for<NMAX - 1 - k>([&](auto uc) {
         constexpr int u = decltype(uc)::value;
-        row_bcast_fma<k + 1 + u, u == 0>(v[k + 1 + u], yb, ny);
+        row_bcast_fms<k + 1 + u, u == 0>(v[k + 1 + u], yb, y);
       });
     }
   });
