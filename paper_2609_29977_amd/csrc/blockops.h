@@ -158,6 +158,21 @@ __device__ inline void rows_both(double y, double& lo, double& hi) {
   hi = __hiloint2double((int)ph[1], (int)pl[1]);
 }
 
+// Lane K of rows 0 and 2 to every lane of rows 0-1 and 2-3: a row broadcast (DPP
+// row_newbcast) and the even-to-odd row copy.  The pivot broadcast of a leaf that
+// factors one block in each 32-lane half of the wave.
+template <int K>
+__device__ inline float half_bcast(float x) {
+  const int b = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + K, 0xf, 0xf, false);
+  return rows_even_to_odd(__int_as_float(b));
+}
+template <int K>
+__device__ inline double half_bcast(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + K, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + K, 0xf, 0xf, false);
+  return rows_even_to_odd(__hiloint2double(hi, lo));
+}
+
 // f(std::integral_constant<int, K>{}) for K = 0 .. N-1 in order (a loop whose index is
 // a constant expression in the body).
 template <typename F, int... Ks>
@@ -283,10 +298,14 @@ constexpr int kPacked32 = 32 * 33 / 2;  // entries of a packed 32 x 32 lower tri
 // per-lane branches: row lanes also update entries above the diagonal, which are
 // never read.  Blocks smaller than NMAX must be padded with an identity block.
 // Returns (on every lane) the 0-based row of the first non-positive pivot, or -1.
-template <typename T, int NMAX, typename Ix = RowMajor<Lay<NMAX>::LD>>
+// PAIR: two independent blocks, one per 32-lane half of the wave (A is the lane's own
+// block; lanes 32-63 repeat the layout of lanes 0-31), each half's pivot broadcast to
+// its half only; the return value is per half.  The instructions are the same as for
+// one block, so the pair costs one block's issue slots.
+template <typename T, int NMAX, typename Ix = RowMajor<Lay<NMAX>::LD>, bool PAIR = false>
 __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
   static_assert(NMAX == 8 || NMAX == 16, "row and column lanes in the first 32 lanes");
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & (PAIR ? 31 : 63);
   const bool rowl = lane < NMAX;
   const int j = lane - NMAX;
   const int idx = rowl ? lane : (j < NMAX ? j : NMAX - 1);
@@ -306,7 +325,12 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_leaf(T* A) {
     // earlier step subtracts zero from it), and a per-lane constant per column would
     // otherwise be kept in a register across the caller's loop.
     v[k] = wave_set_lane<NMAX + k>(v[k], T(1));
-    const T piv = wave_bcast(v[k], k);
+    if constexpr (PAIR) v[k] = wave_set_lane<32 + NMAX + k>(v[k], T(1));
+    T piv;
+    if constexpr (PAIR)
+      piv = half_bcast<k>(v[k]);
+    else
+      piv = wave_bcast(v[k], k);
     if (fail < 0 && !(piv > T(0))) fail = k;
     const T inv = pivot_rsqrt(piv);
     const T y = v[k] * inv;  // L[i][k] on row lane i (>= k); Z[k][j] / L[k][k] on column lane j
@@ -624,6 +648,106 @@ __device__ __attribute__((always_inline)) inline int wave_potrf_inv_packed(T* A)
   wave_lds_fence();
 #pragma unroll
   for (int v = 0; v < 4; ++v) A[P::at(16 + Mfma<T>::row(l, v), i)] = x[v];
+  wave_lds_fence();
+  if (fail >= 0) return fail;
+  return fail2 >= 0 ? 16 + fail2 : -1;
+}
+
+// wave_potrf_inv_packed for two blocks (A0 and A1) in one wave: the leaves factor both
+// at once, one per 32-lane half, and each MFMA step is taken for A0 and then A1 between
+// the same LDS fences.  Returns, on lanes 0-31, the row of A0's first non-positive pivot
+// (or -1), on lanes 32-63 that of A1.
+template <typename T>
+__device__ __attribute__((always_inline)) inline int wave_potrf_inv_packed_pair(T* A0, T* A1) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  typedef PackedLower<0> P;
+  const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+  T* const Ab[2] = {A0, A1};
+  T* const Ah = (l & 32) ? A1 : A0;
+  int fail = wave_potrf_inv_leaf<T, 16, PackedLower<0>, true>(Ah);  // A11 := L11^{-1}
+  wave_lds_fence();
+  // L21 = A21 L11^{-T}: out[r][c] = sum_k A21[r][k] Linv11[c][k]
+  acc_t t[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    T* A = Ab[b];
+    t[b] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      const T li = A[P::at(i, k)];  // in range for k > i too; replaced by zero there
+      t[b] = Mfma<T>::mma(A[P::at(16 + i, k)], k <= i ? li : T(0), t[b]);
+    }
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ab[b][P::at(16 + Mfma<T>::row(l, v), i)] = t[b][v];
+  wave_lds_fence();
+  // S = A22 - L21 L21^T, lower triangle
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    T* A = Ab[b];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = Mfma<T>::row(l, v);
+      const T a22 = A[P::at(16 + r, 16 + i)];
+      t[b][v] = i <= r ? a22 : T(0);
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      const T l21 = A[P::at(16 + i, k)];
+      t[b] = Mfma<T>::mma(-l21, l21, t[b]);
+    }
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = Mfma<T>::row(l, v);
+      if (i <= r) Ab[b][P::at(16 + r, 16 + i)] = t[b][v];
+    }
+  wave_lds_fence();
+  const int fail2 = wave_potrf_inv_leaf<T, 16, PackedLower<16>, true>(Ah);  // A22 := L22^{-1}
+  wave_lds_fence();
+  // W = L21 L11^{-1}: out[r][c] = sum_k L21[r][k] Linv11[k][c]
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    T* A = Ab[b];
+    t[b] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      const T li = A[P::at(k, i)];  // in range for i > k too; replaced by zero there
+      t[b] = Mfma<T>::mma(A[P::at(16 + i, k)], i <= k ? li : T(0), t[b]);
+    }
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ab[b][P::at(16 + Mfma<T>::row(l, v), i)] = t[b][v];
+  wave_lds_fence();
+  // (L^{-1})21 = -L22^{-1} W: out[r][c] = sum_k Linv22[r][k] W[k][c]
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    T* A = Ab[b];
+    t[b] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * g + st;
+      const T l22 = A[P::at(16 + i, 16 + k)];
+      t[b] = Mfma<T>::mma(k <= i ? -l22 : T(0), A[P::at(16 + k, i)], t[b]);
+    }
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ab[b][P::at(16 + Mfma<T>::row(l, v), i)] = t[b][v];
   wave_lds_fence();
   if (fail >= 0) return fail;
   return fail2 >= 0 ? 16 + fail2 : -1;

@@ -1000,7 +1000,7 @@ __global__ void __launch_bounds__(TileCfg<NMAX>::NT,
   factor_pass_body<T, NMAX, FIRST, FINAL, FWD, FULL>(a, blockIdx.x);
 }
 
-// LDS entries per wave of the level-1 inverse kernels.
+// LDS entries per block of the level-1 inverse kernels.
 template <int NMAX>
 constexpr int level1_slot_entries() {
   return NMAX == 32 ? kPacked32 : Lay<NMAX>::SZ;
@@ -1009,88 +1009,116 @@ constexpr int level1_slot_entries() {
 // Level-1 inverses of the first pass.  The odd chain positions (level 1 of Gamma's
 // order) take no Schur update from the rest of the chain, so L_jj^{-1} of their
 // diagonal blocks depends on D alone (Algorithm 1's diagonal factorizations at the
-// lowest level, all independent).  One wave per block, four blocks per workgroup, at
-// full occupancy: the blocks are factored here instead of in each window's prologue,
-// where three of a workgroup's four waves would wait on the serial factorization.
-// Block bi of the launch is the (bi % nodd)-th odd position of chain bi / nodd.
+// lowest level, all independent).  One wave per block (per pair of FP64 32 x 32
+// blocks), four waves per workgroup, at full occupancy: the blocks are factored here instead of
+// in each window's prologue, where three of a workgroup's four waves would wait on the
+// serial factorization.  Block bi of the launch is the (bi % nodd)-th odd position of
+// chain bi / nodd; wave wi takes blocks wi * BPW .. wi * BPW + BPW - 1.
 template <typename T, int NMAX, bool FULL>
 __device__ __attribute__((always_inline)) inline void level1_inverse_body(
-    const FactorPassArgs& a_in, unsigned bi, int nodd, unsigned total) {
+    const FactorPassArgs& a_in, unsigned wi, int nodd, unsigned total) {
   FactorPassArgs a = a_in;
   if constexpr (FULL) a.n = NMAX;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // 32 x 32 blocks are held as their packed lower triangles (half the LDS of a padded
-  // slot, so that more waves fit on a CU); smaller ones in padded slots
+  // slot, so that more waves fit on a CU), in FP64 two per wave (the diagonal leaves
+  // use 32 lanes, so one wave factors both for the issue slots of one); smaller ones in
+  // padded slots; one block per wave but for the FP64 pairs
   constexpr bool PK = NMAX == 32;
+  constexpr int BPW = level1_blocks_per_wave(NMAX, sizeof(T) == 8);
+  constexpr int E = level1_slot_entries<NMAX>();
   constexpr int LD = Lay<NMAX>::LD;
   typedef typename std::conditional<PK, PackedLower<0>, RowMajor<LD>>::type Ix;
-  if (bi >= total) return;  // the whole wave leaves; no workgroup barrier follows
-  T* slot = reinterpret_cast<T*>(smem_raw) + wave_id() * level1_slot_entries<NMAX>();
+  const unsigned b0 = wi * BPW;
+  if (b0 >= total) return;  // the whole wave leaves; no workgroup barrier follows
+  T* const slot0 = reinterpret_cast<T*>(smem_raw) + wave_id() * BPW * E;
   const int n = a.n, N = a.N;
   const size_t nn = (size_t)n * n;
-  const int s = (int)(bi / (unsigned)nodd);
-  const int j = 2 * (int)(bi - (unsigned)s * nodd) + 1;
-  const double* D = a.D + ((size_t)s * N + (N - j)) * nn;
   const int lane = threadIdx.x & 63;
-  double dv[NMAX * NMAX / 64];
-  if constexpr (FULL && NMAX * NMAX % 128 == 0) {
-    // D's lower triangle, two consecutive row entries per 16-byte load; pairs above the
-    // diagonal are not fetched (they read as zero) and a pair that starts on it brings
-    // one entry above it: the factorization reads only the lower triangle
-    const auto rd = block_rsrc(D, (unsigned)(NMAX * NMAX) * 8u);
+  // block h of the wave: chain s[h], odd position j[h]; past the end of the launch the
+  // last block again (factored, not reported, not stored)
+  int s[BPW], j[BPW];
 #pragma unroll
-    for (int h = 0; h < NMAX * NMAX / 128; ++h) {
-      const int e = 2 * (lane + 64 * h), r = e / NMAX, c = e % NMAX;
-      const auto w = __builtin_amdgcn_raw_buffer_load_b128(
-          rd, c <= r ? (unsigned)e * 8u : kOutOfRange, 0, 0);
-      __builtin_memcpy(&dv[2 * h], &w, 16);
-    }
+  for (int h = 0; h < BPW; ++h) {
+    const unsigned bi = min(b0 + h, total - 1);
+    s[h] = (int)(bi / (unsigned)nodd);
+    j[h] = 2 * (int)(bi - (unsigned)s[h] * nodd) + 1;
+  }
 #pragma unroll
-    for (int u = 0; u < NMAX * NMAX / 64; ++u) {
-      const int e = 2 * (lane + 64 * (u >> 1)) + (u & 1), r = e / NMAX, c = e % NMAX;
-      if (!Ix::kLowerOnly || c <= r) slot[Ix::at(r, c)] = static_cast<T>(dv[u]);
-    }
-  } else {
-    // D's lower triangle, identity padded (zeros above the diagonal)
+  for (int h = 0; h < BPW; ++h) {
+    const double* D = a.D + ((size_t)s[h] * N + (N - j[h])) * nn;
+    T* slot = slot0 + h * E;
+    double dv[NMAX * NMAX / 64];
+    if constexpr (FULL && NMAX * NMAX % 128 == 0) {
+      // D's lower triangle, two consecutive row entries per 16-byte load; pairs above the
+      // diagonal are not fetched (they read as zero) and a pair that starts on it brings
+      // one entry above it: the factorization reads only the lower triangle
+      const auto rd = block_rsrc(D, (unsigned)(NMAX * NMAX) * 8u);
 #pragma unroll
-    for (int u = 0; u < NMAX * NMAX / 64; ++u) {
-      const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
-      dv[u] = (r < n && c <= r) ? D[r * n + c] : (r == c ? 1.0 : 0.0);
-    }
+      for (int q = 0; q < NMAX * NMAX / 128; ++q) {
+        const int e = 2 * (lane + 64 * q), r = e / NMAX, c = e % NMAX;
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(
+            rd, c <= r ? (unsigned)e * 8u : kOutOfRange, 0, 0);
+        __builtin_memcpy(&dv[2 * q], &w, 16);
+      }
 #pragma unroll
-    for (int u = 0; u < NMAX * NMAX / 64; ++u) {
-      const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
-      if (!Ix::kLowerOnly || c <= r) slot[Ix::at(r, c)] = static_cast<T>(dv[u]);
+      for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+        const int e = 2 * (lane + 64 * (u >> 1)) + (u & 1), r = e / NMAX, c = e % NMAX;
+        if (!Ix::kLowerOnly || c <= r) slot[Ix::at(r, c)] = static_cast<T>(dv[u]);
+      }
+    } else {
+      // D's lower triangle, identity padded (zeros above the diagonal)
+#pragma unroll
+      for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+        const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
+        dv[u] = (r < n && c <= r) ? D[r * n + c] : (r == c ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < NMAX * NMAX / 64; ++u) {
+        const int e = lane + 64 * u, r = e / NMAX, c = e % NMAX;
+        if (!Ix::kLowerOnly || c <= r) slot[Ix::at(r, c)] = static_cast<T>(dv[u]);
+      }
     }
   }
   wave_lds_fence();
-  int fail;
-  if constexpr (PK)
-    fail = wave_potrf_inv_packed<T>(slot);
+  int fail;  // pairs: per 32-lane half, that half's block
+  if constexpr (PK && BPW == 2)
+    fail = wave_potrf_inv_packed_pair<T>(slot0, slot0 + E);
+  else if constexpr (PK)
+    fail = wave_potrf_inv_packed<T>(slot0);
   else
-    fail = wave_potrf_inv<T, NMAX>(slot);
-  if (fail >= 0 && fail < n && lane == 0) {
-    const int sys = s / a.Ssys;
-    const unsigned long long row0 =
-        (unsigned long long)sys * ((unsigned long long)a.Ssys * N + 1) * n +
-        (unsigned long long)(s - sys * a.Ssys) * N * n;
-    atomicMin(a.info, row0 + (unsigned long long)a.permpos[j - 1] * n + fail + 1);
+    fail = wave_potrf_inv<T, NMAX>(slot0);
+  {
+    const int h = lane >> 5;
+    if (h < BPW && (lane & 31) == 0 && b0 + h < total && fail >= 0 && fail < n) {
+      const int sh = h ? s[BPW - 1] : s[0], jh = h ? j[BPW - 1] : j[0];
+      const int sys = sh / a.Ssys;
+      const unsigned long long row0 =
+          (unsigned long long)sys * ((unsigned long long)a.Ssys * N + 1) * n +
+          (unsigned long long)(sh - sys * a.Ssys) * N * n;
+      atomicMin(a.info, row0 + (unsigned long long)a.permpos[jh - 1] * n + fail + 1);
+    }
   }
   wave_lds_fence();
   // packed lower triangle (rows of length r + 1 whatever n is, so the n x n block's
   // packing is a prefix of the 32 x 32 one)
-  T* Li = reinterpret_cast<T*>(a.Linv) + ((size_t)s * N + (j - 1)) * nn;
   const int np = n * (n + 1) / 2;
 #pragma unroll
-  for (int p0 = 0; p0 < NMAX * (NMAX + 1) / 2; p0 += 64) {
-    const int p = p0 + lane;
-    if constexpr (PK) {
-      if (p < np) Li[p] = slot[p];
-    } else {
-      int r = (int)((__fsqrt_rn(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
-      r = (r * (r + 1) / 2 > p) ? r - 1 : r;
-      r = ((r + 1) * (r + 2) / 2 <= p) ? r + 1 : r;
-      if (p < np) Li[p] = slot[r * LD + (p - r * (r + 1) / 2)];
+  for (int h = 0; h < BPW; ++h) {
+    if (b0 + h >= total) break;  // wave-uniform
+    T* Li = reinterpret_cast<T*>(a.Linv) + ((size_t)s[h] * N + (j[h] - 1)) * nn;
+    const T* slot = slot0 + h * E;
+#pragma unroll
+    for (int p0 = 0; p0 < NMAX * (NMAX + 1) / 2; p0 += 64) {
+      const int p = p0 + lane;
+      if constexpr (PK) {
+        if (p < np) Li[p] = slot[p];
+      } else {
+        int r = (int)((__fsqrt_rn(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+        r = (r * (r + 1) / 2 > p) ? r - 1 : r;
+        r = ((r + 1) * (r + 2) / 2 <= p) ? r + 1 : r;
+        if (p < np) Li[p] = slot[r * LD + (p - r * (r + 1) / 2)];
+      }
     }
   }
 }
@@ -1365,8 +1393,9 @@ void launch_l1inv_t(const FactorPassArgs& a, hipStream_t st) {
   const int nodd = (a.m + 1) / 2;
   const unsigned total = (unsigned)a.S * (unsigned)nodd;
   if (total == 0) return;
-  const size_t lds = 4 * (size_t)level1_slot_entries<NMAX>() * sizeof(T);
-  const dim3 grid((total + 3) / 4);
+  constexpr unsigned PER_WG = 4 * level1_blocks_per_wave(NMAX, sizeof(T) == 8);
+  const size_t lds = PER_WG * (size_t)level1_slot_entries<NMAX>() * sizeof(T);
+  const dim3 grid((total + PER_WG - 1) / PER_WG);
   if (a.n == NMAX)
     hipLaunchKernelGGL((level1_inverse_kernel<T, NMAX, true>), grid, dim3(256), lds, st, a, nodd,
                        total);
@@ -1377,7 +1406,9 @@ void launch_l1inv_t(const FactorPassArgs& a, hipStream_t st) {
 template <typename T, int NMAX>
 void launch_l1inv_multi_t(const MultiItem<FactorPassArgs>* items, int nitems, unsigned blocks,
                           bool full, const Reloc& r, hipStream_t st) {
-  const size_t lds = 4 * (size_t)level1_slot_entries<NMAX>() * sizeof(T);
+  const size_t lds =
+      4 * (size_t)level1_blocks_per_wave(NMAX, sizeof(T) == 8) * level1_slot_entries<NMAX>() *
+      sizeof(T);
   if (full)
     hipLaunchKernelGGL((level1_inverse_multi<T, NMAX, true>), dim3(blocks), dim3(256), lds, st,
                        items, nitems, r);

@@ -105,8 +105,12 @@ template <typename T>
 void launch_factor_pass_multi(const MultiItem<FactorPassArgs>* items, int nitems,
                               unsigned blocks, int nmax, bool first, bool final, bool fwd,
                               bool full, size_t lds, const Reloc& r, hipStream_t st);
+// Blocks per wave of the level-1 inverse kernels for tile size nmax: FP64 32 x 32 blocks
+// in pairs (one per 32-lane half of the wave in the diagonal leaves), the others alone
+// (in FP32 a pair measured no faster).  A workgroup holds four waves.
+constexpr int level1_blocks_per_wave(int nmax, bool fp64) { return fp64 && nmax > 16 ? 2 : 1; }
 // Level-1 inverses of a ragged batch: item p0 = odd positions per chain, p1 = blocks
-// (one per wave, four per workgroup) of the system.
+// (level1_blocks_per_wave per wave, four waves per workgroup) of the system.
 template <typename T>
 void launch_level1_inverse_multi(const MultiItem<FactorPassArgs>* items, int nitems,
                                  unsigned blocks, int nmax, bool full, const Reloc& r,

@@ -251,7 +251,7 @@ void build_factor(bmpc_plan p, Seq& seq, bool fused) {
   }
   {
     // level-1 inverses of every system's first pass, one launch per tile size and
-    // n == NMAX (one wave per block, four per workgroup)
+    // n == NMAX (level1_blocks_per_wave blocks per wave, four waves per workgroup)
     std::map<std::tuple<int, bool>, std::vector<Pending<FactorPassArgs>>> groups;
     for (int i = 0; i < B; ++i) {
       bmpc_plan s = R.subs[i];
@@ -260,8 +260,10 @@ void build_factor(bmpc_plan p, Seq& seq, bool fused) {
       const FactorPassArgs a = factor_pass_args(s, 0, fake(R.offD[i]), fake(R.offE[i]),
                                                 fake(R.offC[i]), nullptr, 0);
       const unsigned total = (unsigned)(s->B * s->d.S) * (unsigned)nodd;
+      const unsigned per_wg =
+          4u * (unsigned)level1_blocks_per_wave(s->nmax, p->prec == BMPC_FP64);
       groups[std::make_tuple(s->nmax, s->d.n == s->nmax)].push_back(
-          {i, a, nodd, (int)total, (total + 3) / 4, 1u, 1u});
+          {i, a, nodd, (int)total, (total + per_wg - 1) / per_wg, 1u, 1u});
     }
     for (auto& g : groups) {
       LaunchRec rec;

@@ -46,7 +46,9 @@ def gpu_solve(system, precision="fp64", window_depth=0, refine=None):
 
 
 SHAPES = [(1, 1, 1), (3, 1, 5), (2, 2, 3), (1, 3, 8), (2, 5, 4), (3, 9, 3), (2, 16, 8),
-          (4, 17, 16), (2, 33, 5), (3, 64, 17), (2, 100, 31), (2, 129, 32), (1, 256, 32)]
+          (4, 17, 16), (2, 33, 5), (3, 64, 17), (2, 100, 31), (2, 129, 32), (1, 256, 32),
+          # an odd number of level-1 blocks (9 and 1) at the 32 x 32 tile size
+          (3, 7, 32), (1, 3, 20)]
 
 
 @pytest.mark.parametrize("S,N,n", SHAPES)
@@ -225,6 +227,51 @@ def test_info_names_failing_root_pivot(S, N, n, k, precision):
     first = next(i for i in range(m + 1, m + n + 1) if np.linalg.eigvalsh(Kp[:i, :i])[0] <= 0)
     natural = int(p[first - 1]) + 1
     assert natural == m + k + 1  # the root is ordered last, its rows in order
+    D, E, C, R, b = dev(s)
+    plan = bm.Plan(S, N, n, 1, precision)
+    plan.factor(D, E, C, R)
+    assert plan.info() == natural
+    plan.close()
+
+
+def _first_nonpositive_pivot(A):
+    """1-based index of the first leading minor of A that is not positive definite: the
+    first non-positive pivot of an unpivoted Cholesky (pivot i is det(A_i) / det(A_i-1)),
+    or 0."""
+    A = np.array(A, dtype=np.float64)
+    for i in range(A.shape[0]):
+        if not A[i, i] > 0:
+            return i + 1
+        l = A[i + 1:, i] / np.sqrt(A[i, i])
+        A[i + 1:, i + 1:] -= np.outer(l, l)
+    return 0
+
+
+# Level-1 blocks of 32 x 32 tiles (n = 32, and n = 20 identity padded): stage N - j is
+# chain position j, and the odd positions 1, 3, .. of chain s are level-1 blocks
+# s * nodd, s * nodd + 1, ..; FP64 factors them two per wave, so these cases put the
+# failure in the first and the second block of a pair and in the unpaired last block of
+# an odd count (S = 1, N = 7: three blocks).
+@pytest.mark.parametrize("S,N,n,sc,stage,k", [(1, 9, 32, 0, 8, 5), (1, 9, 32, 0, 6, 20),
+                                              (1, 7, 32, 0, 2, 9), (2, 9, 20, 1, 6, 17),
+                                              (3, 7, 32, 2, 2, 30)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_info_names_failing_pivot_in_level1_pairs(S, N, n, sc, stage, k, precision):
+    """A non-positive pivot at row k of a level-1 block: info is the natural row of the
+    first leading minor of Pi K Pi^T that is not positive definite (an unpivoted dense
+    Cholesky's first non-positive pivot, confirmed by eigenvalues on either side)."""
+    bm = _bmpc()
+    s = make_system(S, N, n, 1, 1e-1, 60 + n + stage)
+    s.D[sc, stage, k, k] -= 1e3 * (1.0 + abs(s.D[sc, stage, k, k]))
+    K = dense.assemble_K(s.D, s.E, s.C, s.R)
+    p = dense.perm_index(S, N, n, "d")
+    Kp = K[np.ix_(p, p)]
+    first = _first_nonpositive_pivot(Kp)
+    assert first > 1
+    assert np.linalg.eigvalsh(Kp[:first, :first])[0] <= 0
+    assert np.linalg.eigvalsh(Kp[:first - 1, :first - 1])[0] > 0
+    natural = int(p[first - 1]) + 1
+    assert natural == (sc * N + stage) * n + k + 1  # the perturbed row itself
     D, E, C, R, b = dev(s)
     plan = bm.Plan(S, N, n, 1, precision)
     plan.factor(D, E, C, R)
