@@ -414,10 +414,25 @@ __global__ void __launch_bounds__(256) maxabs_partial_kernel(const double* v, co
   }
 }
 
+// max of the non-negative (or NaN) p[i] over i = t0, t0 + step, .. < cnt, 0 if none.
+// U loads are issued together per round (indices clamped into range, the extra ones
+// not counted), so that a thread waits once per round rather than once per load.
+template <int U>
+__device__ inline double strided_max(const double* p, int cnt, int t0, int step) {
+  double m = 0.0;
+  for (int i0 = t0; i0 < cnt; i0 += U * step) {
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = p[min(i0 + u * step, cnt - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) m = i0 + u * step < cnt ? nan_max(t[u], m) : m;
+  }
+  return m;
+}
+
 // max over the block partials of one vector and right-hand side, on one wave
 __device__ inline double wave_reduce_partials(const double* part, int blocks) {
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < blocks; i += 64) mx = nan_max(part[i], mx);
+  double mx = strided_max<16>(part, blocks, (int)threadIdx.x, 64);
   for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
   return mx;
 }
@@ -487,8 +502,7 @@ __global__ void __launch_bounds__(256) refine_be_check_kernel(
   double worst = 0.0;
   for (int sys = 0; sys < B; ++sys) {
     if (kpart) {
-      double m = 0.0;
-      for (int i = threadIdx.x; i < kper; i += blockDim.x) m = nan_max(kpart[(size_t)sys * kper + i], m);
+      double m = strided_max<8>(kpart + (size_t)sys * kper, kper, (int)threadIdx.x, (int)blockDim.x);
       m = block_max(m, sh);
       if (threadIdx.x == 0) knorm[sys] = nan_max(m, kroot[sys]);
       __syncthreads();
@@ -496,11 +510,10 @@ __global__ void __launch_bounds__(256) refine_be_check_kernel(
     const double kn = knorm[sys];
     for (int q = 0; q < nrhs; ++q) {
       const int seg = sys * nrhs + q;
-      double mr = 0.0, mx = 0.0;
-      for (int i = threadIdx.x; i < blocks; i += blockDim.x) {
-        mr = nan_max(partial[(size_t)seg * blocks + i], mr);
-        mx = nan_max(partial[((size_t)segs + seg) * blocks + i], mx);
-      }
+      double mr = strided_max<4>(partial + (size_t)seg * blocks, blocks, (int)threadIdx.x,
+                                 (int)blockDim.x);
+      double mx = strided_max<4>(partial + ((size_t)segs + seg) * blocks, blocks,
+                                 (int)threadIdx.x, (int)blockDim.x);
       mr = block_max(mr, sh);
       mx = block_max(mx, sh);
       if (threadIdx.x == 0) {
@@ -579,9 +592,8 @@ __global__ void __launch_bounds__(256) ragged_sys_check_kernel(
   __shared__ double sh[4];
   const int sys = blockIdx.x;
   if (mode == 1 && kpart) {
-    double m = 0.0;
-    for (int i = kp_off[sys] + threadIdx.x; i < kp_off[sys + 1]; i += blockDim.x)
-      m = nan_max(kpart[i], m);
+    double m = strided_max<8>(kpart + kp_off[sys], kp_off[sys + 1] - kp_off[sys],
+                              (int)threadIdx.x, (int)blockDim.x);
     m = block_max(m, sh);
     if (threadIdx.x == 0) knorm[sys] = nan_max(m, kroot[sys]);
     __syncthreads();
